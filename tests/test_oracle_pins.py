@@ -1,0 +1,333 @@
+"""Pins of the oracle against facts that do not come from the oracle itself:
+published generator outputs, an independent inverse of the mix, brute-force
+topological-order enumeration, numpy re-derivation of every task from its
+predecessors, closed forms and element-set conflict checks."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_16522_amd import workloads as wl
+from tests import _checks as C
+
+pytestmark = pytest.mark.usefixtures("oracle_lib")
+
+
+# ---------------------------------------------------------------- generators
+
+def test_splitmix64_published_outputs():
+    # SplitMix64 seeded with 0: the first two outputs are widely published.
+    assert oracle.sm64(0) == 0xE220A8397B1DCDAF
+    assert oracle.sm64(0x9E3779B97F4A7C15) == 0x6E789E6AA1B965F4
+
+
+def test_xorshift32_marsaglia_example():
+    # Marsaglia, "Xorshift RNGs" (2003): y = 2463534242 with the (13,17,5)
+    # triple gives 723471715 as its first output.
+    assert oracle.xorshift32(2463534242) == 723471715
+
+
+def test_multiplier_inverse_constant():
+    assert (C.MUL * C.MUL_INV) & C.M32 == 1
+
+
+@pytest.mark.parametrize("rounds", [0, 1, 2, 7, 64])
+def test_mix_inverts(rounds):
+    rng = np.random.default_rng(rounds)
+    for x in list(rng.integers(0, 2**32, size=200)) + [0, 1, C.M32]:
+        y = oracle.mix(int(x), rounds)
+        assert C.unmix(y, rounds) == int(x)
+
+
+def test_mix_zero_rounds_is_identity_and_rounds_compose():
+    for x in (0, 1, 0xDEADBEEF, C.M32):
+        assert oracle.mix(x, 0) == x
+        assert oracle.mix(oracle.mix(x, 3), 5) == oracle.mix(x, 8)
+
+
+def test_mix_np_agrees_with_unmix():
+    rng = np.random.default_rng(5)
+    x = rng.integers(0, 2**32, size=64, dtype=np.uint64).astype(np.uint32)
+    y = C.mix_np(x, 9)
+    assert all(C.unmix(int(b), 9) == int(a) for a, b in zip(x, y))
+
+
+def test_h32_key_structure():
+    # h32 keys the second SplitMix64 call with the first, then keeps 32 bits
+    for seed, stream, idx in [(0, 1, 0), (0, 2, 3), (7, 4, 1 << 40), (2**63 + 5, 3, 99)]:
+        key = oracle.sm64((seed ^ (stream << 32)) & (2**64 - 1))
+        assert oracle.h32(seed, stream, idx) == oracle.sm64(key ^ idx) & C.M32
+    # the input generator's independent implementation agrees
+    idx = np.arange(50, dtype=np.uint64)
+    assert np.array_equal(wl.h32(3, 1, idx), np.array([oracle.h32(3, 1, int(i)) for i in idx], np.uint32))
+
+
+# ------------------------------------------------------------ explicit mode
+
+def _rederive(eg, res):
+    """Every stored payload must equal the body applied to the stored payloads
+    of its distinct predecessors (sources: the seeded initial payload)."""
+    sets = C.pred_sets(eg.pred_ptr, eg.preds)
+    P = res["payload"]
+    n = P.shape[1]
+    k = np.arange(n, dtype=np.uint64)
+    for v in range(eg.N):
+        if sets[v]:
+            inp = np.zeros(n, np.uint64)
+            for p in sets[v]:
+                inp += P[p].astype(np.uint64)
+            inp &= np.uint64(C.M32)
+        else:
+            inp = wl.h32(eg.seed, 1, (np.uint64(v) << np.uint64(16)) | k).astype(np.uint64)
+        want = C.mix_np((inp ^ np.uint64(v)).astype(np.uint32), eg.rounds)
+        assert np.array_equal(P[v], want), f"task {v}"
+        assert int(res["digest"][v]) == C.digest_np(P[v]), f"digest {v}"
+    assert res["checksum"] == C.checksum_py(res["digest"])
+
+
+def _run(eg, **kw):
+    return oracle.exec_explicit(eg.N, eg.n, eg.pred_ptr, eg.preds, eg.rounds, seed=eg.seed, **kw)
+
+
+def test_fig6_dag_has_two_orders_with_one_result():
+    eg = wl.fig6_graph(n=64, rounds=16)
+    sets = C.pred_sets(eg.pred_ptr, eg.preds)
+    orders = C.topo_orders(4, sets)
+    assert sorted(orders) == [(0, 1, 2, 3), (0, 2, 1, 3)]
+    base = _run(eg, want_order=True)
+    assert tuple(base["order"]) in orders
+    for o in orders:
+        rc, r = oracle.exec_in_order(4, 64, eg.pred_ptr, eg.preds, 16, o, seed=0)
+        assert rc == 0
+        assert np.array_equal(r["payload"], base["payload"])
+        assert r["checksum"] == base["checksum"]
+    _rederive(eg, base)
+
+
+def test_invalid_orders_are_rejected():
+    eg = wl.fig6_graph()
+    for bad in [(1, 0, 2, 3), (0, 1, 3, 2), (0, 1, 1, 3), (3, 2, 1, 0)]:
+        rc, _ = oracle.exec_in_order(4, 64, eg.pred_ptr, eg.preds, 16, bad)
+        assert rc == oracle.OR_EORDER
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_every_topological_order_same_result_small_random(seed):
+    rng = np.random.default_rng(seed)
+    eg = wl.random_dag(6, 3, rng, n=64, rounds=2, seed=seed)
+    sets = C.pred_sets(eg.pred_ptr, eg.preds)
+    base = _run(eg)
+    orders = C.topo_orders(eg.N, sets)
+    assert len(orders) >= 1
+    for o in orders:
+        rc, r = oracle.exec_in_order(eg.N, 64, eg.pred_ptr, eg.preds, 2, o, seed=seed)
+        assert rc == 0 and r["checksum"] == base["checksum"]
+        assert np.array_equal(r["digest"], base["digest"])
+    _rederive(eg, base)
+
+
+def test_stencil_2x3_all_orders():
+    eg = wl.pattern_graph("stencil", 2, 3, seed=1, n=64, rounds=3)
+    base = _run(eg)
+    orders = C.topo_orders(eg.N, C.pred_sets(eg.pred_ptr, eg.preds))
+    assert len(orders) == 8  # lanes of one timestep commute: 2!^3
+    for o in orders:
+        rc, r = oracle.exec_in_order(eg.N, 64, eg.pred_ptr, eg.preds, 3, o, seed=1)
+        assert rc == 0 and np.array_equal(r["payload"], base["payload"])
+
+
+@pytest.mark.parametrize("pattern", wl.PATTERNS)
+def test_execution_order_is_exactly_once_and_respects_edges(pattern):
+    eg = wl.pattern_graph(pattern, 13, 9, seed=4, n=64, rounds=1)
+    res = _run(eg, want_order=True)
+    order = [int(x) for x in res["order"]]
+    assert sorted(order) == list(range(eg.N))
+    pos = {v: i for i, v in enumerate(order)}
+    for v, s in enumerate(C.pred_sets(eg.pred_ptr, eg.preds)):
+        assert all(pos[p] < pos[v] for p in s)
+    _rederive(eg, res)
+
+
+def test_random_topological_order_matches_kahn_medium():
+    eg = wl.pattern_graph("random", 64, 40, seed=9, n=128, rounds=5)
+    base = _run(eg)
+    sets = C.pred_sets(eg.pred_ptr, eg.preds)
+    # a random topological order: repeatedly pick a random ready task
+    rng = np.random.default_rng(0)
+    indeg = [len(s) for s in sets]
+    succ = [[] for _ in range(eg.N)]
+    for v, s in enumerate(sets):
+        for p in s:
+            succ[p].append(v)
+    ready = [v for v in range(eg.N) if indeg[v] == 0]
+    order = []
+    while ready:
+        v = ready.pop(int(rng.integers(len(ready))))
+        order.append(v)
+        for w in succ[v]:
+            indeg[w] -= 1
+            if indeg[w] == 0:
+                ready.append(w)
+    rc, r = oracle.exec_in_order(eg.N, eg.n, eg.pred_ptr, eg.preds, eg.rounds, order, seed=9)
+    assert rc == 0 and np.array_equal(r["payload"], base["payload"])
+
+
+def test_duplicate_predecessors_are_a_set():
+    rng = np.random.default_rng(3)
+    eg = wl.random_dag(40, 4, rng, n=64, rounds=3, dup=True)
+    sets = C.pred_sets(eg.pred_ptr, eg.preds)
+    ptr = np.zeros(eg.N + 1, np.uint64)
+    ptr[1:] = np.cumsum([len(s) for s in sets])
+    flat = np.array([p for s in sets for p in s], np.uint32)
+    a = _run(eg)
+    b = oracle.exec_explicit(eg.N, 64, ptr, flat, 3)
+    assert np.array_equal(a["payload"], b["payload"])
+    _rederive(eg, a)
+
+
+def test_no_deps_closed_form():
+    eg = wl.pattern_graph("none", 16, 4, seed=2, n=64, rounds=7)
+    res = _run(eg)
+    k = np.arange(64, dtype=np.uint64)
+    for v in range(eg.N):
+        init = wl.h32(2, 1, (np.uint64(v) << np.uint64(16)) | k)
+        assert np.array_equal(res["payload"][v], C.mix_np(init ^ np.uint32(v), 7))
+
+
+def test_chain_closed_form():
+    # W = 1: (t) <- (t-1); out_t = mix(out_{t-1} ^ t), t >= 1
+    eg = wl.pattern_graph("stencil", 1, 12, seed=0, n=64, rounds=4)
+    res = _run(eg)
+    for t in range(1, 12):
+        want = np.array([C.unmix(int(y), 4) for y in res["payload"][t]], np.uint32) ^ np.uint32(t)
+        assert np.array_equal(want, res["payload"][t - 1])
+
+
+def test_c1_config_checksum_is_stable():
+    # The smallest benchmark configuration: stencil 8 x 16, n = 64, R = 16.
+    eg = wl.pattern_graph("stencil", 8, 16, seed=0, n=64, rounds=16)
+    assert eg.E == 330
+    res = _run(eg)
+    _rederive(eg, res)
+
+
+def test_cycle_and_bad_input_detection():
+    # a predecessor that names a later task is refused
+    ptr = np.array([0, 1, 1], np.uint64)
+    rc_raised = False
+    try:
+        oracle.exec_explicit(2, 64, ptr, np.array([1], np.uint32), 0)
+    except RuntimeError:
+        rc_raised = True
+    assert rc_raised
+
+
+# ------------------------------------------------------------- implicit mode
+
+def _dag_edges(N, row_ptr, col):
+    return {(j, int(k)) for j in range(N) for k in col[int(row_ptr[j]):int(row_ptr[j + 1])]}
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_conflict_dag_equals_element_set_rule(seed):
+    rng = np.random.default_rng(100 + seed)
+    ig = wl.random_regions(12, 40, 3, 9, rng)
+    row_ptr, col = oracle.conflict_dag(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv)
+    assert _dag_edges(ig.N, row_ptr, col) == C.element_conflict_dag(ig)
+    for j in range(ig.N):
+        row = col[int(row_ptr[j]):int(row_ptr[j + 1])]
+        assert list(row) == sorted(set(int(x) for x in row))
+        assert np.array_equal(row, oracle.conflict_row(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, j))
+    for k in range(ig.N):
+        preds = oracle.conflict_preds(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, k)
+        assert set(int(p) for p in preds) == {j for (j, kk) in C.element_conflict_dag(ig) if kk == k}
+
+
+@pytest.mark.parametrize("P,iters,want", [(8, 4, 160), (16, 5, 535), (5, 7, 301)])
+def test_halo_dag_closed_form(P, iters, want):
+    ig = wl.halo_graph(P, 128, iters, seed=0, rounds=1)
+    row_ptr, col = oracle.conflict_dag(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv)
+    assert len(col) == C.halo_edge_count(P, iters) == want
+    assert _dag_edges(ig.N, row_ptr, col) == C.element_conflict_dag(ig)
+
+
+def test_c3_closed_form_edge_count():
+    assert C.halo_edge_count(1024, 64) == 6254592
+
+
+def test_halo_dag_independent_of_halo_seed():
+    a = wl.halo_graph(9, 128, 5, seed=0)
+    b = wl.halo_graph(9, 128, 5, seed=17)
+    ra = oracle.conflict_dag(a.N, a.req_ptr, a.lo, a.hi, a.priv)
+    rb = oracle.conflict_dag(b.N, b.req_ptr, b.lo, b.hi, b.priv)
+    assert np.array_equal(ra[0], rb[0]) and np.array_equal(ra[1], rb[1])
+
+
+def _random_topo(N, row_ptr, col, rng):
+    indeg = np.zeros(N, np.int64)
+    for k in col:
+        indeg[int(k)] += 1
+    ready = [v for v in range(N) if indeg[v] == 0]
+    order = []
+    while ready:
+        v = ready.pop(int(rng.integers(len(ready))))
+        order.append(v)
+        for k in col[int(row_ptr[v]):int(row_ptr[v + 1])]:
+            indeg[int(k)] -= 1
+            if indeg[int(k)] == 0:
+                ready.append(int(k))
+    assert len(order) == N
+    return order
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_dag_order_equals_program_order_random(seed):
+    rng = np.random.default_rng(200 + seed)
+    ig = wl.random_regions(16, 60, 3, 12, rng, rounds=3, seed=seed)
+    base = oracle.implicit_program_order(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, 3, ig.space, seed=seed)
+    row_ptr, col = oracle.conflict_dag(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv)
+    for _ in range(10):
+        order = _random_topo(ig.N, row_ptr, col, rng)
+        r = oracle.implicit_in_order(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, 3, ig.space, order, seed=seed)
+        assert np.array_equal(r["A"], base["A"]) and np.array_equal(r["digest"], base["digest"])
+
+
+def test_dag_order_equals_program_order_halo():
+    ig = wl.halo_graph(6, 64, 5, seed=3, rounds=2)
+    base = oracle.implicit_program_order(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, 2, ig.space, seed=3)
+    row_ptr, col = oracle.conflict_dag(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv)
+    rng = np.random.default_rng(1)
+    for _ in range(10):
+        order = _random_topo(ig.N, row_ptr, col, rng)
+        r = oracle.implicit_in_order(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, 2, ig.space, order, seed=3)
+        assert np.array_equal(r["A"], base["A"])
+
+
+def test_dropping_an_edge_changes_the_result():
+    # the DAG is also necessary: a conflicting pair run in the wrong order
+    # changes the array (checks that the tests above have power)
+    ig = wl.halo_graph(4, 64, 2, seed=0, rounds=2)
+    base = oracle.implicit_program_order(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, 2, ig.space)
+    order = list(range(ig.N))
+    order[0], order[1] = order[1], order[0]  # (0,0) and (0,1) conflict
+    r = oracle.implicit_in_order(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, 2, ig.space, order)
+    assert not np.array_equal(r["A"], base["A"])
+
+
+def test_implicit_single_task_body():
+    # one task: RW [0,8), RO [8,12); c = sum of the initial RO elements
+    ig = wl.ImplicitGraph(N=1, req_ptr=np.array([0, 2], np.uint64), lo=np.array([0, 8], np.uint64),
+                          hi=np.array([8, 12], np.uint64), priv=np.array([2, 1], np.uint32), space=12,
+                          rounds=5, seed=4)
+    r = oracle.implicit_program_order(1, ig.req_ptr, ig.lo, ig.hi, ig.priv, 5, 12, seed=4)
+    A0 = wl.h32(4, 2, np.arange(12, dtype=np.uint64))
+    c = int(A0[8:12].astype(np.uint64).sum() & np.uint64(C.M32))
+    want = C.mix_np(A0[:8] ^ np.uint32(c) ^ np.uint32(0), 5)
+    assert np.array_equal(r["A"][:8], want) and np.array_equal(r["A"][8:], A0[8:])
+    assert int(r["digest"][0]) == C.digest_np(want)
+
+
+def test_invalid_requirements_refused():
+    ig = wl.ImplicitGraph(N=1, req_ptr=np.array([0, 2], np.uint64), lo=np.array([0, 4], np.uint64),
+                          hi=np.array([8, 12], np.uint64), priv=np.array([2, 1], np.uint32), space=12)
+    with pytest.raises(RuntimeError):
+        oracle.implicit_program_order(1, ig.req_ptr, ig.lo, ig.hi, ig.priv, 1, 12)
