@@ -1,0 +1,260 @@
+/*
+ * taskgraph.h -- C ABI of the MI355X (gfx950) task-DAG executor.
+ *
+ * The calls follow the paper's statement of the problem (Yadav et al., "On the
+ * Duality of Task and Actor Programming Models"):
+ *   - Figure 3 and Section 2: every operation returns an event for its
+ *     completion and is predicated on a set of earlier events.  Here an event
+ *     is the creation index of the task that produces it.
+ *   - Section 4.1: a graph of operations is built dynamically, registered
+ *     (finalised, i.e. compiled) once and then launched as one operation, as
+ *     often as needed.
+ *   - Algorithm 1: compilation gives every vertex an atomic counter of pending
+ *     in-edges and an O(1) out-edge index; execution resets the counters,
+ *     starts the vertices without in-edges, decrements one counter per edge
+ *     and runs a vertex when its counter reaches zero.
+ *   - Section 2 (implicitly parallel systems) and Section 5: instead of
+ *     events, tasks may declare the data they read and write; the runtime
+ *     infers the dependences, and the result equals sequential program order.
+ *
+ * Task body (the paper's Task Bench tasks run a floating-point busy loop,
+ * Section 6.1; this library runs an exact integer body so every result is
+ * reproducible bit for bit):
+ *   mix_round(x) = xorshift32_{13,17,5}(x) * 0x9E3779B1 + 0x7F4A7C15 (mod 2^32)
+ *   h32(s,t,i)   = low32(sm64(sm64(s ^ (t << 32)) ^ i)), sm64 = SplitMix64
+ *   explicit task v with payload of n words:
+ *     in[k]  = h32(seed, 1, (v << 16) | k)            if v has no predecessor
+ *            = sum over distinct predecessors p of out_p[k]   (mod 2^32)
+ *     out[k] = mix_round^R(in[k] ^ v)
+ *     digest = sum_k out[k] * (2k + 1)                (mod 2^32)
+ *   implicit task k on the shared array A (initially A[e] = h32(seed, 2, e)):
+ *     c = sum of A[e] over its read-only elements;
+ *     each read-write element e (declaration order): A[e] = mix^R(A[e]^c^k);
+ *     digest = sum_j A_new[e_j] * (2j + 1), j enumerating written elements.
+ *   checksum = sum_v digest(v) * (2v + 1)             (mod 2^64)
+ *
+ * Conventions.
+ *   - Every call returns tg_status; 0 is success, negative values are errors.
+ *     tg_status_str() names a status; tg_last_error() gives the message of the
+ *     most recent failure on the calling thread.
+ *   - Pointers named host_* / const arrays of the build calls are host memory
+ *     owned by the caller and copied before the call returns.  Device memory
+ *     is owned by the library (allocated through the allocator set with
+ *     tg_set_allocator, else hipMalloc) and freed by the matching destroy.
+ *   - Streams are hipStream_t passed as void*; NULL is the default stream.
+ *   - A handle may be used by one thread at a time.
+ *   - All kernels bound every wait: a wait that sees no progress for the
+ *     configured watchdog interval aborts the launch, and the following
+ *     wait/read call returns TG_ETIMEOUT.
+ */
+#ifndef TASKGRAPH_H
+#define TASKGRAPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tg_status;
+enum {
+  TG_OK = 0,
+  TG_EINVAL = -1,    /* bad argument: unknown event, bad interval, wrong mode */
+  TG_ENOMEM = -2,    /* device or host allocation failed, or budget exceeded */
+  TG_EBUSY = -3,     /* graph already finalised / execution in flight */
+  TG_EDEVICE = -4,   /* a HIP runtime call failed (message in tg_last_error) */
+  TG_ETIMEOUT = -5,  /* the device watchdog aborted a launch */
+  TG_ESTATE = -6     /* call not valid in the current state (e.g. not finalised) */
+};
+
+typedef struct tg_graph_s* tg_graph;
+typedef struct tg_batch_s* tg_batch;
+typedef struct tg_server_s* tg_server;
+typedef uint32_t tg_event; /* creation index of the producing task in its graph */
+
+enum { TG_EXPLICIT = 1, TG_IMPLICIT = 2 };
+enum { TG_RO = 1, TG_RW = 2 };
+
+/* Region requirement: half-open interval [lo, hi) of the graph's index space
+ * with privilege TG_RO or TG_RW (Section 2, implicitly parallel systems). */
+typedef struct {
+  uint64_t lo, hi;
+  uint32_t priv;
+  uint32_t _pad;
+} tg_region_req;
+
+/* Launch configuration of the persistent executor.  Zero fields mean "let the
+ * library choose" (built-in defaults).
+ *   mapping      : 1 = one wavefront per task, 2 = one workgroup per task.
+ *   workers      : number of workers (wavefronts or workgroups); 0 = as many
+ *                  as are co-resident (calibrated, see tg_exec_occupancy);
+ *                  larger values are clamped to that.
+ *   window       : ready-window length scanned per poll (1..64).
+ *   wg_waves     : wavefronts per workgroup for mapping 2 (1..16).
+ *   watchdog_ms  : abort a launch after this long without progress.
+ *   spin_limit   : if non-zero, abort after this many consecutive empty polls
+ *                  (lets a host test force the timeout path).
+ *   diag         : 1 = diagnostic launch (per-task execution counts and
+ *                  timestamps, readable with tg_graph_debug_*).
+ *   notify       : 1 = the decrement that empties a counter also rings the
+ *                  owning worker's doorbell, and idle workers poll only their
+ *                  doorbell (fewer polls, one more hop per task).
+ *   idle_sleep   : back-off of an idle worker, in units of 128 cycles
+ *                  (1..64, default 2). */
+typedef struct {
+  uint32_t mapping;
+  uint32_t workers;
+  uint32_t window;
+  uint32_t wg_waves;
+  uint32_t watchdog_ms;
+  uint32_t spin_limit;
+  uint32_t diag;
+  uint32_t notify;
+  uint32_t idle_sleep;
+} tg_exec_config;
+
+enum { TG_MAP_WAVE = 1, TG_MAP_WORKGROUP = 2 };
+
+/* ------------------------------------------------------------- status */
+const char* tg_status_str(tg_status s);
+const char* tg_last_error(void);
+/* Library version string; never NULL. */
+const char* tg_version(void);
+
+/* Device memory hooks (PyTorch's caching allocator in the Python binding).
+ * alloc(bytes, ctx) returns a device pointer or NULL; free_(ptr, ctx).
+ * Pass NULL, NULL to return to hipMalloc/hipFree.  Must be called while no
+ * graph, batch or server exists. */
+tg_status tg_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_)(void* ptr, void* ctx),
+                           void* ctx);
+
+/* ------------------------------------------------------------ graphs */
+
+/* Create an empty graph.
+ *   mode          : TG_EXPLICIT (events) or TG_IMPLICIT (region requirements).
+ *   payload_words : explicit mode: u32 words per task payload, a power of two
+ *                   in [64, 65536]; ignored (pass 0) in implicit mode.
+ *   index_space   : implicit mode: number of u32 elements of the shared array
+ *                   (1 .. 2^36); ignored in explicit mode.
+ *   seed          : seed of the initial payloads / initial array.
+ * Errors: TG_EINVAL for a bad mode or size, TG_ENOMEM. */
+tg_status tg_graph_create(tg_graph* out, uint32_t mode, uint32_t payload_words, uint64_t index_space,
+                          uint64_t seed);
+
+/* Explicit mode: add one task predicated on the events preds[0..npreds)
+ * (Figure 3 `launch(..., pre)`).  Duplicate events are merged.  Every event
+ * must already exist (an index below the current task count), so the graph is
+ * acyclic by construction.  *out_event receives the new task's event.
+ * Errors: TG_EINVAL (unknown event, wrong mode, NULL out_event), TG_EBUSY
+ * after finalise. */
+tg_status tg_task_add(tg_graph g, const tg_event* preds, uint32_t npreds, uint32_t mix_rounds,
+                      tg_event* out_event);
+
+/* Explicit mode, bulk form: add ntasks tasks whose predecessor lists are
+ * preds[pred_ptr[i] .. pred_ptr[i+1]) (pred_ptr has ntasks+1 entries, starting
+ * at 0).  Events may refer to tasks of the same call that come earlier.
+ * mix_rounds is an array of ntasks values, or NULL to use uniform_rounds for
+ * all.  *first_event receives the event of the first added task. */
+tg_status tg_task_add_many(tg_graph g, uint32_t ntasks, const uint64_t* pred_ptr, const tg_event* preds,
+                           const uint32_t* mix_rounds, uint32_t uniform_rounds, tg_event* first_event);
+
+/* Implicit mode: add one task (next in program order) declaring reqs[0..nreqs).
+ * Errors: TG_EINVAL for lo > hi, hi > index_space, an unknown privilege, or a
+ * read-write interval overlapping another interval of the same task. */
+tg_status tg_task_add_regions(tg_graph g, const tg_region_req* reqs, uint32_t nreqs, uint32_t mix_rounds,
+                              tg_event* out_event);
+
+/* Implicit mode, bulk form: task i declares reqs[req_ptr[i] .. req_ptr[i+1]). */
+tg_status tg_task_add_regions_many(tg_graph g, uint32_t ntasks, const uint64_t* req_ptr,
+                                   const tg_region_req* reqs, const uint32_t* mix_rounds,
+                                   uint32_t uniform_rounds, tg_event* first_event);
+
+/* Compile the graph (Algorithm 1, Compile): merge duplicate predecessors,
+ * build the out-edge CSR and in-degree counters, compute the level-ordered
+ * schedule, allocate device state.  Implicit mode first infers the dependence
+ * DAG on the device (interval-overlap tests in program order).  Idempotent.
+ * Blocks until done.  Errors: TG_ENOMEM, TG_EDEVICE. */
+tg_status tg_graph_finalize(tg_graph g);
+
+/* Launch one execution of the whole graph on `stream` (Algorithm 1, Execute):
+ * counters are reset, so executions repeat with identical results.  Returns
+ * without waiting.  cfg may be NULL.  Errors: TG_ESTATE if not finalised,
+ * TG_EBUSY if a previous execution has not been waited for. */
+tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfg, void* stream);
+
+/* Block until the last execution finished; surfaces watchdog aborts
+ * (TG_ETIMEOUT) and deferred HIP errors (TG_EDEVICE). */
+tg_status tg_graph_wait(tg_graph g);
+
+/* Read results (each waits for an in-flight execution first). */
+tg_status tg_graph_num_tasks(tg_graph g, uint64_t* n);
+tg_status tg_graph_num_edges(tg_graph g, uint64_t* e);          /* distinct edges */
+tg_status tg_graph_read_digests(tg_graph g, uint32_t* host_out, uint64_t n);  /* n = #tasks */
+tg_status tg_graph_read_payload(tg_graph g, tg_event v, uint32_t* host_out, uint32_t n); /* n = payload words */
+tg_status tg_graph_read_data(tg_graph g, uint32_t* host_out, uint64_t lo, uint64_t hi);  /* implicit A[lo,hi) */
+tg_status tg_graph_checksum(tg_graph g, uint64_t* out);
+/* Out-edge CSR of the (inferred or explicit) DAG: row j lists the successors
+ * of task j in ascending order.  row_ptr has #tasks+1 entries; col holds up to
+ * cap_e entries; *e receives the edge count (TG_ENOMEM if it exceeds cap_e). */
+tg_status tg_graph_read_dag(tg_graph g, uint64_t* row_ptr, uint32_t* col, uint64_t cap_e, uint64_t* e);
+/* Times of the last finalize (host compile, device inference) and of the last
+ * execution measured with HIP events, in milliseconds (0 when not measured). */
+tg_status tg_graph_timings(tg_graph g, double* compile_ms, double* infer_ms, double* exec_ms);
+tg_status tg_graph_destroy(tg_graph g);
+
+/* ------------------------------------------------------------ batches */
+
+/* Compile n finalised graphs of either mode into one persistent launch
+ * (graphs stay independent; each keeps its own results).  cfg may be NULL. */
+tg_status tg_batch_create(tg_batch* out, const tg_graph* graphs, uint32_t n, const tg_exec_config* cfg);
+tg_status tg_batch_execute(tg_batch b, void* stream);
+tg_status tg_batch_wait(tg_batch b);
+/* Device time of the last batch execution (HIP events), in milliseconds. */
+tg_status tg_batch_time_ms(tg_batch b, double* ms);
+tg_status tg_batch_destroy(tg_batch b);
+
+/* Residency of the persistent executor.  Every worker of a launch must be
+ * resident at the same time, so the library never launches more workers than
+ * a probe launch of the executor kernel has shown to be co-resident.
+ *   blocks_per_cu : the runtime's occupancy estimate (an upper bound);
+ *   cus           : compute units of the current device;
+ *   resident      : if not NULL, the calibrated number of co-resident
+ *                   workers (measured once per device and kernel variant). */
+tg_status tg_exec_occupancy(uint32_t mapping, uint32_t wg_waves, uint32_t* blocks_per_cu, uint32_t* cus,
+                            uint32_t* resident);
+/* Workers of the graph's last launch and, for a diagnostic launch (diag=1),
+ * how many of them started. */
+tg_status tg_graph_exec_info(tg_graph g, uint32_t* workers, uint32_t* started);
+/* Host-only model of a launch (no GPU needed): compiles the worker layout
+ * for nworkers workers and steps the same ready-window loop as the kernels
+ * in a seeded order.  order (#tasks entries) receives the execution order by
+ * event, *executed the number of tasks run; TG_ETIMEOUT if the schedule
+ * would deadlock. */
+tg_status tg_graph_emulate_schedule(tg_graph g, uint32_t nworkers, uint32_t window, uint64_t seed, uint32_t* order,
+                                    uint64_t* executed);
+/* After a diagnostic launch (diag=1) of the graph on its own: per task (by
+ * event) the pending in-edge counter, the number of times it ran, its worker
+ * and its entry in that worker's list; optionally (wprog != NULL, nworkers =
+ * the launch's worker count) how many list entries each worker finished. */
+tg_status tg_graph_debug_state(tg_graph g, uint32_t* pending, uint32_t* execs, uint32_t* owner, uint32_t* entry,
+                               uint32_t* wprog, uint32_t nworkers);
+/* After a diagnostic launch: per task (by event) the device clock at its
+ * start and at the end of its edge signals (2 u64 per task, 100 MHz ticks,
+ * 0 if it never ran); optionally per worker [first scan, last scan, scans,
+ * reserved]. */
+tg_status tg_graph_debug_times(tg_graph g, uint64_t* task_times, uint64_t* worker_stamps, uint32_t nworkers);
+
+/* ------------------------------------------------------- comparators */
+
+/* Plain comparators of the same graph: one kernel launch per task in creation
+ * order on `stream` (mode 1), or replay of a captured hipGraph with one kernel
+ * node per task and one dependency per edge (mode 2; the hipGraph is built on
+ * the first call and cached).  Results are identical to tg_graph_execute. */
+enum { TG_CMP_PER_TASK = 1, TG_CMP_HIPGRAPH = 2 };
+tg_status tg_graph_execute_comparator(tg_graph g, uint32_t mode, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TASKGRAPH_H */

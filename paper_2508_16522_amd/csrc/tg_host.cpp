@@ -1,0 +1,1147 @@
+// Host side of the C ABI: graph building, compilation into a worker layout,
+// launches, reads, batches and the plain comparators.
+//
+// Compilation follows Algorithm 1 (Compile): the graph's vertices are
+// partitioned over workers, every vertex gets a counter of pending in-edges
+// and an O(1) list of out-edges.  The partition used here is a
+// dependence-level schedule: vertices are sorted by (level, graph, id) and
+// dealt round-robin to the workers, so every worker's list is topologically
+// ordered and consecutive list entries tend to be independent.
+#include "taskgraph.h"
+#include "tg_internal.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <map>
+#include <tuple>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using tg::ExecParams;
+using tg::GraphEnt;
+using tg::ReqDev;
+using tg::TaskRec;
+
+namespace {
+
+thread_local std::string g_err;
+
+tg_status fail(tg_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) return fail(TG_EDEVICE, "%s: %s", #x, hipGetErrorString(e_));    \
+  } while (0)
+
+// ------------------------------------------------------------ allocation
+
+void* (*g_alloc)(size_t, void*) = nullptr;
+void (*g_free)(void*, void*) = nullptr;
+void* g_ctx = nullptr;
+std::atomic<long> g_live{0};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void* (*fa)(size_t, void*) = nullptr;
+  void (*ff)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) {
+      if (ff) ff(p, ctx);
+      else (void)hipFree(p);
+      g_live--;
+    }
+    p = nullptr;
+    bytes = 0;
+  }
+  tg_status alloc(size_t nbytes) {
+    release();
+    size_t b = nbytes ? ((nbytes + 255) & ~size_t(255)) : 256;
+    fa = g_alloc;
+    ff = g_free;
+    ctx = g_ctx;
+    if (fa) {
+      p = fa(b, ctx);
+      if (!p) return fail(TG_ENOMEM, "device allocation of %zu bytes failed (allocator hook)", b);
+    } else {
+      hipError_t e = hipMalloc(&p, b);
+      if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return fail(TG_ENOMEM, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
+      }
+    }
+    bytes = b;
+    g_live++;
+    return TG_OK;
+  }
+  template <class T>
+  T* as() const { return (T*)p; }
+};
+
+template <class T>
+tg_status upload(DevBuf& d, const std::vector<T>& h) {
+  tg_status s = d.alloc(h.size() * sizeof(T));
+  if (s != TG_OK) return s;
+  if (!h.empty()) HIPCHK(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return TG_OK;
+}
+
+uint64_t sm64_host(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------- device info
+
+struct DevInfo {
+  int cus = 0;
+  int dev = -1;
+};
+
+tg_status device_info(DevInfo& di) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t pr;
+  HIPCHK(hipGetDeviceProperties(&pr, dev));
+  di.cus = pr.multiProcessorCount;
+  di.dev = dev;
+  return TG_OK;
+}
+
+struct Config {
+  uint32_t mapping = 1, workers = 0, window = 64, wg_waves = 4, watchdog_ms = 5000, spin_limit = 0, diag = 0;
+  uint32_t idle_sleep = 2, notify = 0;
+};
+
+Config resolve(const tg_exec_config* c) {
+  Config r;
+  if (c) {
+    if (c->mapping) r.mapping = c->mapping;
+    if (c->workers) r.workers = c->workers;
+    if (c->window) r.window = c->window;
+    if (c->wg_waves) r.wg_waves = c->wg_waves;
+    if (c->watchdog_ms) r.watchdog_ms = c->watchdog_ms;
+    r.spin_limit = c->spin_limit;
+    r.diag = c->diag & 1u;
+    r.notify = c->notify & 1u;
+    if (c->idle_sleep) r.idle_sleep = c->idle_sleep;
+  }
+  return r;
+}
+
+tg_status check_config(const Config& c) {
+  if (c.mapping != TG_MAP_WAVE && c.mapping != TG_MAP_WORKGROUP) return fail(TG_EINVAL, "mapping must be 1 or 2");
+  if (c.window < 1 || c.window > 64) return fail(TG_EINVAL, "window must be in [1, 64]");
+  if (c.idle_sleep < 1 || c.idle_sleep > 64) return fail(TG_EINVAL, "idle_sleep must be in [1, 64]");
+  if (c.wg_waves < 1 || c.wg_waves > 16) return fail(TG_EINVAL, "wg_waves must be in [1, 16]");
+  return TG_OK;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- layout
+
+struct Layout {
+  Config cfg;
+  uint32_t nworkers = 0, grid_blocks = 0, npos = 0, last_started = 0;
+  DevBuf rec, pred_addr, succ_pos, indeg, cnt, wbase, gtab, reqs, ctrl, execs, wprog, owner, bell, tstamp, wstamp;
+  std::vector<std::vector<uint32_t>> pos_of;  // per graph: task id -> position
+  ExecParams params{};
+};
+
+struct tg_graph_s {
+  uint32_t mode = 0, n = 0;
+  uint64_t space = 0, seed = 0;
+  // as built
+  std::vector<uint64_t> pred_ptr{0};
+  std::vector<uint32_t> preds;
+  std::vector<uint32_t> rounds;
+  std::vector<uint64_t> req_ptr{0};
+  std::vector<tg_region_req> reqs;
+  // compiled
+  bool finalized = false;
+  std::vector<uint64_t> dpred_ptr;  // distinct predecessors (explicit) or inferred (implicit)
+  std::vector<uint32_t> dpred;
+  std::vector<uint64_t> succ_ptr;
+  std::vector<uint32_t> succ;
+  std::vector<uint32_t> level;
+  std::vector<uint32_t> rw_base;  // implicit: per requirement, ordinal of its first written element
+  DevBuf payload, data, digest;
+  std::unique_ptr<Layout> solo;
+  // execution state
+  bool inflight = false;
+  Layout* last_layout = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double compile_ms = 0, infer_ms = 0, exec_ms = 0;
+  // comparator hipGraph
+  hipGraph_t hg = nullptr;
+  hipGraphExec_t hgx = nullptr;
+  uint32_t N() const { return mode == TG_EXPLICIT ? (uint32_t)(pred_ptr.size() - 1) : (uint32_t)(req_ptr.size() - 1); }
+};
+
+struct tg_batch_s {
+  std::vector<tg_graph> graphs;
+  std::unique_ptr<Layout> lay;
+  bool inflight = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+// Largest number of workers of a kernel variant that are proven co-resident
+// on the current device.  The occupancy query is only an upper bound (it has
+// been observed to over-count on gfx950), so the executor kernel itself is
+// launched in probe mode with decreasing blocks-per-CU until every worker
+// sees every other worker checked in.  Results are cached per device and
+// variant.
+struct ResidencyKey {
+  int dev;
+  uint32_t mapping, wg_waves;
+  bool operator<(const ResidencyKey& o) const {
+    return std::tie(dev, mapping, wg_waves) < std::tie(o.dev, o.mapping, o.wg_waves);
+  }
+};
+std::mutex g_res_mu;
+std::map<ResidencyKey, uint32_t> g_res_cache;
+
+tg_status resident_workers(uint32_t mapping, uint32_t wg_waves, uint32_t* out) {
+  DevInfo di;
+  tg_status s = device_info(di);
+  if (s != TG_OK) return s;
+  ResidencyKey key{di.dev, mapping, wg_waves};
+  {
+    std::lock_guard<std::mutex> lk(g_res_mu);
+    auto it = g_res_cache.find(key);
+    if (it != g_res_cache.end()) {
+      *out = it->second;
+      return TG_OK;
+    }
+  }
+  int bpc = tg::exec_blocks_per_cu(mapping, wg_waves);
+  if (bpc <= 0) return fail(TG_EDEVICE, "occupancy query failed");
+  const uint32_t per_block = mapping == TG_MAP_WAVE ? 4u : 1u;
+  DevBuf ctrl;
+  if ((s = ctrl.alloc(sizeof(tg::Ctrl))) != TG_OK) return s;
+  uint32_t found = 0;
+  for (int b = bpc; b >= 1 && !found; --b) {
+    const uint32_t blocks = (uint32_t)b * (uint32_t)di.cus;
+    HIPCHK(hipMemset(ctrl.p, 0, sizeof(tg::Ctrl)));
+    ExecParams P;
+    memset(&P, 0, sizeof(P));
+    P.ctrl = ctrl.as<tg::Ctrl>();
+    P.nworkers = blocks * per_block;
+    P.residency_probe = 1;
+    P.watchdog_ticks = 20ull * 100000ull;  // 20 ms
+    HIPCHK(tg::launch_exec(P, mapping, wg_waves, blocks, nullptr));
+    HIPCHK(hipDeviceSynchronize());
+    tg::Ctrl c;
+    HIPCHK(hipMemcpy(&c, ctrl.p, sizeof(c), hipMemcpyDeviceToHost));
+    if (c.resident == P.nworkers) found = P.nworkers;
+  }
+  if (!found) return fail(TG_EDEVICE, "no co-resident worker count found");
+  std::lock_guard<std::mutex> lk(g_res_mu);
+  g_res_cache[key] = found;
+  *out = found;
+  return TG_OK;
+}
+
+// Host part of the layout: everything the kernels read, built on the CPU.
+struct HostLayout {
+  uint32_t N = 0, nw = 0;
+  std::vector<uint32_t> wbase;
+  std::vector<TaskRec> rec;
+  std::vector<uint64_t> pred_addr;
+  std::vector<uint32_t> succ_pos;
+  std::vector<uint32_t> indeg;
+  std::vector<GraphEnt> gtab;
+  std::vector<ReqDev> reqs;
+  std::vector<std::vector<uint32_t>> pos_of;
+};
+
+// Schedule a set of finalised graphs onto nw workers: sort all tasks by
+// (dependence level, graph, id), deal the sorted sequence round-robin to the
+// workers, and store each worker's tasks contiguously in that order.
+tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, HostLayout& H) {
+  uint64_t ntot = 0, npred_tot = 0, nsucc_tot = 0, nreq_tot = 0;
+  uint32_t maxlevel = 0;
+  for (auto g : gs) {
+    ntot += g->N();
+    npred_tot += g->mode == TG_EXPLICIT ? g->dpred.size() : 0;
+    nsucc_tot += g->succ.size();
+    nreq_tot += g->mode == TG_IMPLICIT ? g->reqs.size() : 0;
+    for (uint32_t lv : g->level) maxlevel = std::max(maxlevel, lv);
+  }
+  if (ntot >= 0xFFFFFFFFull || npred_tot >= 0xFFFFFFFFull || nsucc_tot >= 0xFFFFFFFFull || nreq_tot >= 0xFFFFFFFFull)
+    return fail(TG_EINVAL, "layout too large: %llu tasks, %llu edges", (unsigned long long)ntot,
+                (unsigned long long)nsucc_tot);
+  const uint32_t N = (uint32_t)ntot;
+  uint64_t nw = nw_req;
+  if (nw > N) nw = N ? N : 1;
+  if (nw == 0) nw = 1;
+  H.N = N;
+  H.nw = (uint32_t)nw;
+  // schedule: stable counting sort by level; ties by (graph, id)
+  std::vector<uint64_t> lstart((size_t)maxlevel + 2, 0);
+  for (auto g : gs)
+    for (uint32_t lv : g->level) lstart[lv + 1]++;
+  for (size_t i = 1; i < lstart.size(); ++i) lstart[i] += lstart[i - 1];
+  std::vector<uint64_t> sched(N);  // (graph << 32) | id
+  for (uint32_t gi = 0; gi < gs.size(); ++gi) {
+    const auto& lv = gs[gi]->level;
+    for (uint32_t v = 0; v < lv.size(); ++v) sched[lstart[lv[v]]++] = ((uint64_t)gi << 32) | v;
+  }
+  // worker w takes schedule entries w, w + nw, ...; its positions are contiguous
+  H.wbase.assign((size_t)nw + 1, 0);
+  for (uint64_t w = 0; w < nw; ++w) H.wbase[w + 1] = H.wbase[w] + (uint32_t)((N > w) ? (N - w + nw - 1) / nw : 0);
+  H.pos_of.assign(gs.size(), {});
+  for (uint32_t gi = 0; gi < gs.size(); ++gi) H.pos_of[gi].assign(gs[gi]->N(), 0);
+  std::vector<uint64_t> at_pos(N);
+  for (uint64_t si = 0; si < N; ++si) {
+    const uint64_t w = si % nw, j = si / nw;
+    const uint32_t pos = H.wbase[w] + (uint32_t)j;
+    at_pos[pos] = sched[si];
+    H.pos_of[sched[si] >> 32][(uint32_t)sched[si]] = pos;
+  }
+  sched.clear();
+  sched.shrink_to_fit();
+  // records and edge arrays in position order
+  H.rec.assign(N, TaskRec());
+  H.pred_addr.clear();
+  H.pred_addr.reserve(npred_tot);
+  H.succ_pos.clear();
+  H.succ_pos.reserve(nsucc_tot);
+  H.indeg.assign(N, 0);
+  std::vector<uint64_t> req_base(gs.size(), 0);
+  {
+    uint64_t rb = 0;
+    for (uint32_t gi = 0; gi < gs.size(); ++gi) {
+      req_base[gi] = rb;
+      if (gs[gi]->mode == TG_IMPLICIT) rb += gs[gi]->reqs.size();
+    }
+  }
+  for (uint32_t pos = 0; pos < N; ++pos) {
+    const uint32_t gi = (uint32_t)(at_pos[pos] >> 32), v = (uint32_t)at_pos[pos];
+    const tg_graph g = gs[gi];
+    TaskRec& r = H.rec[pos];
+    memset(&r, 0, sizeof(r));
+    r.tid = v;
+    r.graph = gi;
+    r.rounds = g->rounds[v];
+    r.npred = (uint32_t)(g->dpred_ptr[v + 1] - g->dpred_ptr[v]);
+    r.pred_beg = (uint32_t)H.pred_addr.size();
+    if (g->mode == TG_EXPLICIT) {
+      const uint64_t base = (uint64_t)g->payload.p;
+      r.out = base + (uint64_t)v * g->n * 4ull;
+      for (uint64_t j = g->dpred_ptr[v]; j < g->dpred_ptr[v + 1]; ++j)
+        H.pred_addr.push_back(base + (uint64_t)g->dpred[j] * g->n * 4ull);
+    } else {
+      r.out = req_base[gi] + g->req_ptr[v];
+      r.nreq = (uint32_t)(g->req_ptr[v + 1] - g->req_ptr[v]);
+    }
+    r.succ_beg = (uint32_t)H.succ_pos.size();
+    r.nsucc = (uint32_t)(g->succ_ptr[v + 1] - g->succ_ptr[v]);
+    for (uint64_t j = g->succ_ptr[v]; j < g->succ_ptr[v + 1]; ++j) H.succ_pos.push_back(H.pos_of[gi][g->succ[j]]);
+    H.indeg[pos] = r.npred;
+  }
+  H.gtab.assign(gs.size(), GraphEnt());
+  H.reqs.clear();
+  H.reqs.reserve(nreq_tot);
+  for (uint32_t gi = 0; gi < gs.size(); ++gi) {
+    const tg_graph g = gs[gi];
+    GraphEnt& e = H.gtab[gi];
+    memset(&e, 0, sizeof(e));
+    e.key1 = sm64_host(g->seed ^ (1ull << 32));
+    e.key2 = sm64_host(g->seed ^ (2ull << 32));
+    e.digest = g->digest.as<uint32_t>();
+    e.data = g->data.as<uint32_t>();
+    e.n = g->n;
+    e.mode = g->mode;
+    if (g->mode == TG_IMPLICIT)
+      for (size_t i = 0; i < g->reqs.size(); ++i) {
+        ReqDev q;
+        memset(&q, 0, sizeof(q));
+        q.lo = g->reqs[i].lo;
+        q.hi = g->reqs[i].hi;
+        q.priv = g->reqs[i].priv;
+        q.rw_base = g->rw_base[i];
+        H.reqs.push_back(q);
+      }
+  }
+  return TG_OK;
+}
+
+tg_status ensure_device(tg_graph g);
+
+// Schedule and upload the layout of a set of finalised graphs.
+tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::unique_ptr<Layout>& out) {
+  tg_status s = check_config(cfg);
+  if (s != TG_OK) return s;
+  for (auto g : gs)
+    if ((s = ensure_device(g)) != TG_OK) return s;
+  uint32_t cap32 = 0;
+  if ((s = resident_workers(cfg.mapping, cfg.wg_waves, &cap32)) != TG_OK) return s;
+  const uint64_t cap_workers = cap32;
+  uint64_t nw = cfg.workers ? cfg.workers : cap_workers;
+  if (nw > cap_workers) nw = cap_workers;  // every worker must be co-resident
+  HostLayout H;
+  if ((s = plan_layout(gs, nw, H)) != TG_OK) return s;
+  auto L = std::make_unique<Layout>();
+  L->cfg = cfg;
+  L->npos = H.N;
+  L->nworkers = H.nw;
+  L->grid_blocks = cfg.mapping == TG_MAP_WAVE ? (H.nw + 3) / 4 : H.nw;
+  L->pos_of = std::move(H.pos_of);
+  const uint32_t N = H.N;
+  if ((s = upload(L->rec, H.rec)) != TG_OK) return s;
+  if ((s = upload(L->pred_addr, H.pred_addr)) != TG_OK) return s;
+  if ((s = upload(L->succ_pos, H.succ_pos)) != TG_OK) return s;
+  if ((s = upload(L->indeg, H.indeg)) != TG_OK) return s;
+  if ((s = L->cnt.alloc((size_t)N * 4)) != TG_OK) return s;
+  if ((s = upload(L->wbase, H.wbase)) != TG_OK) return s;
+  if ((s = upload(L->gtab, H.gtab)) != TG_OK) return s;
+  if ((s = upload(L->reqs, H.reqs)) != TG_OK) return s;
+  if ((s = L->ctrl.alloc(sizeof(tg::Ctrl))) != TG_OK) return s;
+  HIPCHK(hipMemset(L->ctrl.p, 0, sizeof(tg::Ctrl)));
+  {
+    std::vector<uint32_t> own(N);
+    for (uint32_t w = 0; w < H.nw; ++w)
+      for (uint32_t p = H.wbase[w]; p < H.wbase[w + 1]; ++p) own[p] = w;
+    if ((s = upload(L->owner, own)) != TG_OK) return s;
+  }
+  if ((s = L->bell.alloc((size_t)H.nw * tg::kBellStride * 4)) != TG_OK) return s;
+  HIPCHK(hipMemset(L->bell.p, 0, (size_t)H.nw * tg::kBellStride * 4));
+  ExecParams& P = L->params;
+  P.rec = L->rec.as<TaskRec>();
+  P.pred_addr = L->pred_addr.as<uint64_t>();
+  P.succ_pos = L->succ_pos.as<uint32_t>();
+  P.indeg = L->indeg.as<uint32_t>();
+  P.cnt = L->cnt.as<uint32_t>();
+  P.wbase = L->wbase.as<uint32_t>();
+  P.gtab = L->gtab.as<GraphEnt>();
+  P.reqs = L->reqs.as<ReqDev>();
+  P.ctrl = L->ctrl.as<tg::Ctrl>();
+  P.owner = L->owner.as<uint32_t>();
+  P.bell = L->bell.as<uint32_t>();
+  P.npos = N;
+  P.nworkers = L->nworkers;
+  P.window = cfg.window;
+  P.spin_limit = cfg.spin_limit;
+  P.watchdog_ticks = (uint64_t)cfg.watchdog_ms * 100000ull;
+  out = std::move(L);
+  return TG_OK;
+}
+
+// CPU model of the persistent worker loop: the same state machine as the
+// kernels' next_task (ready window of `window` entries, ready tasks taken in
+// list order, window slid past the finished prefix), used to check a layout
+// for exactly-once execution, precedence and freedom from deadlock without a
+// GPU.  Workers take steps in a seeded pseudo-random order; a step either
+// runs one task or performs one empty scan.
+tg_status emulate_layout(const HostLayout& H, uint32_t window, uint64_t seed, uint32_t* order, uint64_t* executed) {
+  const uint32_t N = H.N, nw = H.nw;
+  struct St {
+    uint32_t h = 0;
+    uint64_t done = 0, pend = 0;
+  };
+  std::vector<uint32_t> cnt(H.indeg);
+  std::vector<St> st(nw);
+  std::vector<uint32_t> active;
+  for (uint32_t w = 0; w < nw; ++w)
+    if (H.wbase[w + 1] > H.wbase[w]) active.push_back(w);
+  uint64_t ex = 0, rng = seed * 0x9E3779B97F4A7C15ull + 1, idle = 0;
+  auto scan = [&](uint32_t w) {
+    St& x = st[w];
+    const uint32_t wb = H.wbase[w], wcnt = H.wbase[w + 1] - wb;
+    uint64_t ready = 0;
+    for (uint32_t lane = 0; lane < 64; ++lane) {
+      const uint32_t idx = x.h + lane;
+      const bool valid = lane < window && idx < wcnt && !((x.done >> lane) & 1ull);
+      if (valid && cnt[wb + idx] == 0) ready |= 1ull << lane;
+    }
+    return ready;
+  };
+  while (!active.empty()) {
+    rng ^= rng << 13;
+    rng ^= rng >> 7;
+    rng ^= rng << 17;
+    const size_t ai = (size_t)(rng % active.size());
+    const uint32_t w = active[ai];
+    St& x = st[w];
+    const uint32_t wb = H.wbase[w], wcnt = H.wbase[w + 1] - wb;
+    if (!x.pend) {
+      const uint32_t adv = (~x.done == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~x.done);
+      x.h += adv;
+      x.done = adv >= 64u ? 0ull : (x.done >> adv);
+      if (x.h >= wcnt) {
+        active[ai] = active.back();
+        active.pop_back();
+        continue;
+      }
+      x.pend = scan(w);
+      if (!x.pend) {
+        if (++idle > 64ull * active.size() + 1024) {
+          bool any = false;
+          for (uint32_t w2 : active)
+            if (st[w2].pend || scan(w2)) any = true;
+          if (!any) {
+            *executed = ex;
+            return fail(TG_ETIMEOUT, "schedule deadlocks after %llu of %u tasks", (unsigned long long)ex, N);
+          }
+          idle = 0;
+        }
+        continue;
+      }
+    }
+    idle = 0;
+    const uint32_t b = (uint32_t)__builtin_ctzll(x.pend);
+    x.pend &= x.pend - 1;
+    x.done |= 1ull << b;
+    const uint32_t pos = wb + x.h + b;
+    const TaskRec& r = H.rec[pos];
+    if (order) order[ex] = pos;
+    ++ex;
+    for (uint32_t j = 0; j < r.nsucc; ++j) {
+      uint32_t& c = cnt[H.succ_pos[r.succ_beg + j]];
+      if (c == 0) return fail(TG_EINVAL, "counter underflow at position %u", H.succ_pos[r.succ_beg + j]);
+      --c;
+    }
+  }
+  *executed = ex;
+  return ex == N ? TG_OK : fail(TG_EINVAL, "executed %llu of %u tasks", (unsigned long long)ex, N);
+}
+
+bool same_layout(const Config& a, const Config& b) {
+  return a.mapping == b.mapping && a.workers == b.workers && a.wg_waves == b.wg_waves;
+}
+
+// Launch reset + persistent executor for a layout.
+tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph>& gs, hipStream_t st) {
+  ExecParams P = L.params;
+  P.window = cfg.window;
+  P.spin_limit = cfg.spin_limit;
+  P.diag = cfg.diag;
+  P.idle_sleep = cfg.idle_sleep;
+  P.notify = cfg.notify;
+  P.watchdog_ticks = (uint64_t)cfg.watchdog_ms * 100000ull;
+  P.execs = nullptr;
+  P.wprog = nullptr;
+  P.tstamp = nullptr;
+  P.wstamp = nullptr;
+  if (cfg.diag) {
+    tg_status s;
+    if (!L.execs.p && (s = L.execs.alloc((size_t)L.npos * 4)) != TG_OK) return s;
+    if (!L.wprog.p && (s = L.wprog.alloc((size_t)L.nworkers * 4)) != TG_OK) return s;
+    if (!L.tstamp.p && (s = L.tstamp.alloc((size_t)L.npos * 16)) != TG_OK) return s;
+    if (!L.wstamp.p && (s = L.wstamp.alloc((size_t)L.nworkers * 32)) != TG_OK) return s;
+    P.execs = L.execs.as<uint32_t>();
+    P.wprog = L.wprog.as<uint32_t>();
+    P.tstamp = L.tstamp.as<uint64_t>();
+    P.wstamp = L.wstamp.as<uint64_t>();
+  }
+  for (auto g : gs)
+    if (g->mode == TG_IMPLICIT) {
+      HIPCHK(tg_launch_init_data(g->data.as<uint32_t>(), g->space, sm64_host(g->seed ^ (2ull << 32)), st));
+    }
+  HIPCHK(tg::launch_reset(P, st));
+  if (L.npos) HIPCHK(tg::launch_exec(P, cfg.mapping, cfg.wg_waves, L.grid_blocks, st));
+  return TG_OK;
+}
+
+tg_status check_abort(Layout* L) {
+  if (!L) return TG_OK;
+  tg::Ctrl c;
+  HIPCHK(hipMemcpy(&c, L->ctrl.p, sizeof(c), hipMemcpyDeviceToHost));
+  L->last_started = c.started;
+  if (c.abort)
+    return fail(TG_ETIMEOUT,
+                "executor watchdog aborted the launch (no progress): worker %u of %u stuck at list entry %u/%u "
+                "(position %u, pending in-edges %u); workers started %u",
+                c.stuck_worker, L->nworkers, c.stuck_h, c.stuck_wcnt, c.stuck_pos, c.stuck_cnt, c.started);
+  return TG_OK;
+}
+
+tg_status graph_wait(tg_graph g) {
+  if (!g->inflight) return TG_OK;
+  g->inflight = false;
+  HIPCHK(hipEventSynchronize(g->ev1));
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, g->ev0, g->ev1) == hipSuccess) g->exec_ms = ms;
+  (void)hipGetLastError();
+  return check_abort(g->last_layout);
+}
+
+tg_status finalize_explicit(tg_graph g) {
+  const uint32_t N = g->N();
+  // distinct predecessor sets
+  g->dpred_ptr.assign((size_t)N + 1, 0);
+  g->dpred.clear();
+  g->dpred.reserve(g->preds.size());
+  std::vector<uint32_t> tmp;
+  for (uint32_t v = 0; v < N; ++v) {
+    tmp.assign(g->preds.begin() + g->pred_ptr[v], g->preds.begin() + g->pred_ptr[v + 1]);
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    g->dpred.insert(g->dpred.end(), tmp.begin(), tmp.end());
+    g->dpred_ptr[v + 1] = g->dpred.size();
+  }
+  // out-edge CSR, rows ascending (ids are appended in increasing v)
+  g->succ_ptr.assign((size_t)N + 1, 0);
+  for (uint32_t p : g->dpred) g->succ_ptr[p + 1]++;
+  for (uint32_t v = 0; v < N; ++v) g->succ_ptr[v + 1] += g->succ_ptr[v];
+  g->succ.assign(g->dpred.size(), 0);
+  {
+    std::vector<uint64_t> fill(g->succ_ptr.begin(), g->succ_ptr.end() - 1);
+    for (uint32_t v = 0; v < N; ++v)
+      for (uint64_t j = g->dpred_ptr[v]; j < g->dpred_ptr[v + 1]; ++j) g->succ[fill[g->dpred[j]]++] = v;
+  }
+  // dependence levels (creation order is topological)
+  g->level.assign(N, 0);
+  for (uint32_t v = 0; v < N; ++v) {
+    uint32_t lv = 0;
+    for (uint64_t j = g->dpred_ptr[v]; j < g->dpred_ptr[v + 1]; ++j) lv = std::max(lv, g->level[g->dpred[j]] + 1);
+    g->level[v] = lv;
+  }
+  return TG_OK;
+}
+
+// Device buffers of a graph are allocated on first use, so graphs can be
+// built and compiled on a machine without a GPU.
+tg_status ensure_device(tg_graph g) {
+  const uint32_t N = g->N();
+  tg_status s;
+  if (g->mode == TG_EXPLICIT && !g->payload.p) {
+    if ((s = g->payload.alloc((size_t)N * g->n * 4)) != TG_OK) return s;
+  }
+  if (!g->digest.p) {
+    if ((s = g->digest.alloc((size_t)N * 4)) != TG_OK) return s;
+    HIPCHK(hipMemset(g->digest.p, 0, (size_t)N * 4));
+  }
+  if (!g->ev0) HIPCHK(hipEventCreate(&g->ev0));
+  if (!g->ev1) HIPCHK(hipEventCreate(&g->ev1));
+  return TG_OK;
+}
+
+}  // namespace
+
+// Implicit mode: infer the conflict DAG on the device, then derive the
+// predecessor sets and levels on the host exactly as for explicit graphs.
+static tg_status tg_finalize_implicit(tg_graph g) {
+  const uint32_t N = g->N();
+  // ordinal of each read-write interval's first element among its task's
+  // written elements (digest weights follow declaration order)
+  g->rw_base.assign(g->reqs.size(), 0);
+  for (uint32_t k = 0; k < N; ++k) {
+    uint64_t run = 0;
+    for (uint64_t a = g->req_ptr[k]; a < g->req_ptr[k + 1]; ++a) {
+      g->rw_base[a] = (uint32_t)run;
+      if (g->reqs[a].priv == TG_RW) run += g->reqs[a].hi - g->reqs[a].lo;
+    }
+    if (run > 0xFFFFFFFFull) return fail(TG_EINVAL, "task %u writes more than 2^32 elements", k);
+  }
+  InferResult res;
+  std::string err;
+  hipError_t e = tg_infer_dag_raw(N, g->req_ptr.data(), g->reqs.data(), g->reqs.size(), g->space, res, err);
+  if (e != hipSuccess) return fail(TG_EDEVICE, "dependence inference failed at %s: %s", err.c_str(), hipGetErrorString(e));
+  g->infer_ms = res.ms;
+  g->succ_ptr = std::move(res.row_ptr);
+  g->succ = std::move(res.col);
+  // predecessor sets: transpose, rows ascending because j is visited in order
+  g->dpred_ptr.assign((size_t)N + 1, 0);
+  for (uint32_t k : g->succ) g->dpred_ptr[k + 1]++;
+  for (uint32_t k = 0; k < N; ++k) g->dpred_ptr[k + 1] += g->dpred_ptr[k];
+  g->dpred.assign(g->succ.size(), 0);
+  {
+    std::vector<uint64_t> fill(g->dpred_ptr.begin(), g->dpred_ptr.end() - 1);
+    for (uint32_t j = 0; j < N; ++j)
+      for (uint64_t x = g->succ_ptr[j]; x < g->succ_ptr[j + 1]; ++x) g->dpred[fill[g->succ[x]]++] = j;
+  }
+  g->level.assign(N, 0);
+  for (uint32_t k = 0; k < N; ++k) {
+    uint32_t lv = 0;
+    for (uint64_t x = g->dpred_ptr[k]; x < g->dpred_ptr[k + 1]; ++x) lv = std::max(lv, g->level[g->dpred[x]] + 1);
+    g->level[k] = lv;
+  }
+  tg_status s;
+  if ((s = g->data.alloc((size_t)g->space * 4)) != TG_OK) return s;
+  return TG_OK;
+}
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char* tg_status_str(tg_status s) {
+  switch (s) {
+    case TG_OK: return "TG_OK";
+    case TG_EINVAL: return "TG_EINVAL";
+    case TG_ENOMEM: return "TG_ENOMEM";
+    case TG_EBUSY: return "TG_EBUSY";
+    case TG_EDEVICE: return "TG_EDEVICE";
+    case TG_ETIMEOUT: return "TG_ETIMEOUT";
+    case TG_ESTATE: return "TG_ESTATE";
+    default: return "TG_UNKNOWN";
+  }
+}
+
+const char* tg_last_error(void) { return g_err.c_str(); }
+
+const char* tg_version(void) { return "taskgraph-gfx950 0.1"; }
+
+tg_status tg_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr)) return fail(TG_EINVAL, "alloc and free must both be set or both NULL");
+  if (g_live.load() != 0) return fail(TG_EBUSY, "device buffers are alive; set the allocator first");
+  g_alloc = alloc;
+  g_free = free_;
+  g_ctx = ctx;
+  return TG_OK;
+}
+
+tg_status tg_graph_create(tg_graph* out, uint32_t mode, uint32_t payload_words, uint64_t index_space, uint64_t seed) {
+  if (!out) return fail(TG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (mode == TG_EXPLICIT) {
+    if (payload_words < 64 || payload_words > 65536 || (payload_words & (payload_words - 1)))
+      return fail(TG_EINVAL, "payload_words must be a power of two in [64, 65536]");
+  } else if (mode == TG_IMPLICIT) {
+    if (index_space == 0 || index_space > (1ull << 36)) return fail(TG_EINVAL, "index_space must be in [1, 2^36]");
+  } else {
+    return fail(TG_EINVAL, "unknown mode %u", mode);
+  }
+  tg_graph g = new (std::nothrow) tg_graph_s();
+  if (!g) return fail(TG_ENOMEM, "host allocation failed");
+  g->mode = mode;
+  g->n = mode == TG_EXPLICIT ? payload_words : 0;
+  g->space = mode == TG_IMPLICIT ? index_space : 0;
+  g->seed = seed;
+  *out = g;
+  return TG_OK;
+}
+
+tg_status tg_task_add_many(tg_graph g, uint32_t ntasks, const uint64_t* pred_ptr, const tg_event* preds,
+                           const uint32_t* mix_rounds, uint32_t uniform_rounds, tg_event* first_event) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (g->mode != TG_EXPLICIT) return fail(TG_EINVAL, "graph is not in explicit mode");
+  if (g->finalized) return fail(TG_EBUSY, "graph already finalised");
+  if (ntasks && !pred_ptr) return fail(TG_EINVAL, "pred_ptr is NULL");
+  const uint64_t N0 = g->N();
+  if (N0 + ntasks >= 0xFFFFFFFFull) return fail(TG_EINVAL, "too many tasks");
+  if (ntasks && pred_ptr[0] != 0) return fail(TG_EINVAL, "pred_ptr[0] must be 0");
+  for (uint32_t i = 0; i < ntasks; ++i) {
+    if (pred_ptr[i + 1] < pred_ptr[i]) return fail(TG_EINVAL, "pred_ptr not monotone at %u", i);
+    for (uint64_t j = pred_ptr[i]; j < pred_ptr[i + 1]; ++j)
+      if ((uint64_t)preds[j] >= N0 + i) return fail(TG_EINVAL, "task %llu names unknown event %u", (unsigned long long)(N0 + i), preds[j]);
+  }
+  const uint64_t E = ntasks ? pred_ptr[ntasks] : 0;
+  const uint64_t base = g->preds.size();
+  g->preds.insert(g->preds.end(), preds, preds + E);
+  g->pred_ptr.reserve(g->pred_ptr.size() + ntasks);
+  for (uint32_t i = 0; i < ntasks; ++i) g->pred_ptr.push_back(base + pred_ptr[i + 1]);
+  for (uint32_t i = 0; i < ntasks; ++i) g->rounds.push_back(mix_rounds ? mix_rounds[i] : uniform_rounds);
+  if (first_event) *first_event = (tg_event)N0;
+  return TG_OK;
+}
+
+tg_status tg_task_add(tg_graph g, const tg_event* preds, uint32_t npreds, uint32_t mix_rounds, tg_event* out_event) {
+  if (!out_event) return fail(TG_EINVAL, "out_event is NULL");
+  if (npreds && !preds) return fail(TG_EINVAL, "preds is NULL");
+  uint64_t ptr[2] = {0, npreds};
+  return tg_task_add_many(g, 1, ptr, preds, nullptr, mix_rounds, out_event);
+}
+
+tg_status tg_task_add_regions_many(tg_graph g, uint32_t ntasks, const uint64_t* req_ptr, const tg_region_req* reqs,
+                                   const uint32_t* mix_rounds, uint32_t uniform_rounds, tg_event* first_event) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (g->mode != TG_IMPLICIT) return fail(TG_EINVAL, "graph is not in implicit mode");
+  if (g->finalized) return fail(TG_EBUSY, "graph already finalised");
+  if (ntasks && !req_ptr) return fail(TG_EINVAL, "req_ptr is NULL");
+  const uint64_t N0 = g->N();
+  if (N0 + ntasks >= 0xFFFFFFFFull) return fail(TG_EINVAL, "too many tasks");
+  if (ntasks && req_ptr[0] != 0) return fail(TG_EINVAL, "req_ptr[0] must be 0");
+  for (uint32_t i = 0; i < ntasks; ++i) {
+    if (req_ptr[i + 1] < req_ptr[i]) return fail(TG_EINVAL, "req_ptr not monotone at %u", i);
+    for (uint64_t a = req_ptr[i]; a < req_ptr[i + 1]; ++a) {
+      const tg_region_req& q = reqs[a];
+      if (q.lo > q.hi || q.hi > g->space) return fail(TG_EINVAL, "task %llu: interval [%llu,%llu) outside index space",
+                                                      (unsigned long long)(N0 + i), (unsigned long long)q.lo, (unsigned long long)q.hi);
+      if (q.priv != TG_RO && q.priv != TG_RW) return fail(TG_EINVAL, "task %llu: bad privilege %u", (unsigned long long)(N0 + i), q.priv);
+      for (uint64_t b = req_ptr[i]; b < req_ptr[i + 1]; ++b) {
+        if (a == b) continue;
+        const tg_region_req& r = reqs[b];
+        if ((q.priv == TG_RW || r.priv == TG_RW) && q.lo < q.hi && r.lo < r.hi && q.lo < r.hi && r.lo < q.hi)
+          return fail(TG_EINVAL, "task %llu: a read-write interval overlaps another interval of the same task",
+                      (unsigned long long)(N0 + i));
+      }
+    }
+  }
+  const uint64_t M = ntasks ? req_ptr[ntasks] : 0;
+  const uint64_t base = g->reqs.size();
+  g->reqs.insert(g->reqs.end(), reqs, reqs + M);
+  for (uint32_t i = 0; i < ntasks; ++i) g->req_ptr.push_back(base + req_ptr[i + 1]);
+  for (uint32_t i = 0; i < ntasks; ++i) g->rounds.push_back(mix_rounds ? mix_rounds[i] : uniform_rounds);
+  if (first_event) *first_event = (tg_event)N0;
+  return TG_OK;
+}
+
+tg_status tg_task_add_regions(tg_graph g, const tg_region_req* reqs, uint32_t nreqs, uint32_t mix_rounds,
+                              tg_event* out_event) {
+  if (!out_event) return fail(TG_EINVAL, "out_event is NULL");
+  if (nreqs && !reqs) return fail(TG_EINVAL, "reqs is NULL");
+  uint64_t ptr[2] = {0, nreqs};
+  return tg_task_add_regions_many(g, 1, ptr, reqs, nullptr, mix_rounds, out_event);
+}
+
+tg_status tg_graph_finalize(tg_graph g) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (g->finalized) return TG_OK;
+  auto t0 = std::chrono::steady_clock::now();
+  tg_status s = g->mode == TG_EXPLICIT ? finalize_explicit(g) : tg_finalize_implicit(g);
+  if (s != TG_OK) return s;
+  g->finalized = true;
+  g->compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() - g->infer_ms;
+  return TG_OK;
+}
+
+tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfgp, void* stream) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  if (g->inflight) return fail(TG_EBUSY, "previous execution not waited for");
+  Config cfg = resolve(cfgp);
+  tg_status s = check_config(cfg);
+  if (s != TG_OK) return s;
+  if (!g->solo || !same_layout(g->solo->cfg, cfg)) {
+    g->solo.reset();
+    std::vector<tg_graph> gs{g};
+    if ((s = build_layout(gs, cfg, g->solo)) != TG_OK) return s;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipEventRecord(g->ev0, st));
+  std::vector<tg_graph> gs{g};
+  if ((s = launch_layout(*g->solo, cfg, gs, st)) != TG_OK) return s;
+  HIPCHK(hipEventRecord(g->ev1, st));
+  g->inflight = true;
+  g->last_layout = g->solo.get();
+  return TG_OK;
+}
+
+tg_status tg_graph_wait(tg_graph g) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  return graph_wait(g);
+}
+
+tg_status tg_graph_num_tasks(tg_graph g, uint64_t* n) {
+  if (!g || !n) return fail(TG_EINVAL, "NULL argument");
+  *n = g->N();
+  return TG_OK;
+}
+
+tg_status tg_graph_num_edges(tg_graph g, uint64_t* e) {
+  if (!g || !e) return fail(TG_EINVAL, "NULL argument");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  *e = g->succ.size();
+  return TG_OK;
+}
+
+tg_status tg_graph_read_digests(tg_graph g, uint32_t* host_out, uint64_t n) {
+  if (!g || !host_out) return fail(TG_EINVAL, "NULL argument");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  if (n != g->N()) return fail(TG_EINVAL, "n must equal the task count %u", g->N());
+  if (!g->digest.p) return fail(TG_ESTATE, "graph was never executed");
+  tg_status s = graph_wait(g);
+  if (s != TG_OK) return s;
+  if (n) HIPCHK(hipMemcpy(host_out, g->digest.p, n * 4, hipMemcpyDeviceToHost));
+  return TG_OK;
+}
+
+tg_status tg_graph_read_payload(tg_graph g, tg_event v, uint32_t* host_out, uint32_t n) {
+  if (!g || !host_out) return fail(TG_EINVAL, "NULL argument");
+  if (g->mode != TG_EXPLICIT) return fail(TG_EINVAL, "payloads exist in explicit mode only");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  if (v >= g->N() || n != g->n) return fail(TG_EINVAL, "bad event or payload size");
+  if (!g->payload.p) return fail(TG_ESTATE, "graph was never executed");
+  tg_status s = graph_wait(g);
+  if (s != TG_OK) return s;
+  HIPCHK(hipMemcpy(host_out, g->payload.as<uint32_t>() + (size_t)v * g->n, (size_t)n * 4, hipMemcpyDeviceToHost));
+  return TG_OK;
+}
+
+tg_status tg_graph_read_data(tg_graph g, uint32_t* host_out, uint64_t lo, uint64_t hi) {
+  if (!g || !host_out) return fail(TG_EINVAL, "NULL argument");
+  if (g->mode != TG_IMPLICIT) return fail(TG_EINVAL, "the shared array exists in implicit mode only");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  if (lo > hi || hi > g->space) return fail(TG_EINVAL, "range outside the index space");
+  tg_status s = graph_wait(g);
+  if (s != TG_OK) return s;
+  if (hi > lo) HIPCHK(hipMemcpy(host_out, g->data.as<uint32_t>() + lo, (hi - lo) * 4, hipMemcpyDeviceToHost));
+  return TG_OK;
+}
+
+tg_status tg_graph_checksum(tg_graph g, uint64_t* out) {
+  if (!g || !out) return fail(TG_EINVAL, "NULL argument");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  std::vector<uint32_t> d(g->N());
+  tg_status s = tg_graph_read_digests(g, d.data(), d.size());
+  if (s != TG_OK) return s;
+  uint64_t c = 0;
+  for (uint64_t v = 0; v < d.size(); ++v) c += (uint64_t)d[v] * (2ull * v + 1ull);
+  *out = c;
+  return TG_OK;
+}
+
+tg_status tg_graph_read_dag(tg_graph g, uint64_t* row_ptr, uint32_t* col, uint64_t cap_e, uint64_t* e) {
+  if (!g || !row_ptr || !e) return fail(TG_EINVAL, "NULL argument");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  *e = g->succ.size();
+  memcpy(row_ptr, g->succ_ptr.data(), g->succ_ptr.size() * sizeof(uint64_t));
+  if (g->succ.size() > cap_e) return fail(TG_ENOMEM, "col capacity %llu < %zu edges", (unsigned long long)cap_e, g->succ.size());
+  if (!g->succ.empty()) {
+    if (!col) return fail(TG_EINVAL, "col is NULL");
+    memcpy(col, g->succ.data(), g->succ.size() * 4);
+  }
+  return TG_OK;
+}
+
+tg_status tg_graph_timings(tg_graph g, double* compile_ms, double* infer_ms, double* exec_ms) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (compile_ms) *compile_ms = g->compile_ms;
+  if (infer_ms) *infer_ms = g->infer_ms;
+  if (exec_ms) *exec_ms = g->exec_ms;
+  return TG_OK;
+}
+
+tg_status tg_graph_destroy(tg_graph g) {
+  if (!g) return TG_OK;
+  (void)graph_wait(g);
+  if (g->hgx) (void)hipGraphExecDestroy(g->hgx);
+  if (g->hg) (void)hipGraphDestroy(g->hg);
+  if (g->ev0) (void)hipEventDestroy(g->ev0);
+  if (g->ev1) (void)hipEventDestroy(g->ev1);
+  delete g;
+  return TG_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+tg_status tg_batch_create(tg_batch* out, const tg_graph* graphs, uint32_t n, const tg_exec_config* cfgp) {
+  if (!out || (n && !graphs)) return fail(TG_EINVAL, "NULL argument");
+  *out = nullptr;
+  std::vector<tg_graph> gs(graphs, graphs + n);
+  for (auto g : gs) {
+    if (!g) return fail(TG_EINVAL, "NULL graph in batch");
+    if (!g->finalized) return fail(TG_ESTATE, "every graph of a batch must be finalised");
+  }
+  Config cfg = resolve(cfgp);
+  auto b = std::make_unique<tg_batch_s>();
+  b->graphs = gs;
+  tg_status s = build_layout(gs, cfg, b->lay);
+  if (s != TG_OK) return s;
+  HIPCHK(hipEventCreate(&b->ev0));
+  HIPCHK(hipEventCreate(&b->ev1));
+  *out = b.release();
+  return TG_OK;
+}
+
+tg_status tg_batch_execute(tg_batch b, void* stream) {
+  if (!b) return fail(TG_EINVAL, "batch is NULL");
+  if (b->inflight) return fail(TG_EBUSY, "previous execution not waited for");
+  for (auto g : b->graphs) {
+    tg_status s = graph_wait(g);
+    if (s != TG_OK) return s;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipEventRecord(b->ev0, st));
+  tg_status s = launch_layout(*b->lay, b->lay->cfg, b->graphs, st);
+  if (s != TG_OK) return s;
+  HIPCHK(hipEventRecord(b->ev1, st));
+  b->inflight = true;
+  return TG_OK;
+}
+
+tg_status tg_batch_wait(tg_batch b) {
+  if (!b) return fail(TG_EINVAL, "batch is NULL");
+  if (!b->inflight) return TG_OK;
+  b->inflight = false;
+  HIPCHK(hipEventSynchronize(b->ev1));
+  return check_abort(b->lay.get());
+}
+
+tg_status tg_batch_time_ms(tg_batch b, double* ms) {
+  if (!b || !ms) return fail(TG_EINVAL, "NULL argument");
+  float f = 0;
+  HIPCHK(hipEventElapsedTime(&f, b->ev0, b->ev1));
+  *ms = f;
+  return TG_OK;
+}
+
+tg_status tg_batch_destroy(tg_batch b) {
+  if (!b) return TG_OK;
+  (void)tg_batch_wait(b);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  delete b;
+  return TG_OK;
+}
+
+// ------------------------------------------------------------ comparators
+
+tg_status tg_exec_occupancy(uint32_t mapping, uint32_t wg_waves, uint32_t* blocks_per_cu, uint32_t* cus,
+                            uint32_t* resident) {
+  if (!blocks_per_cu || !cus) return fail(TG_EINVAL, "NULL argument");
+  if (mapping != TG_MAP_WAVE && mapping != TG_MAP_WORKGROUP) return fail(TG_EINVAL, "mapping must be 1 or 2");
+  if (wg_waves < 1 || wg_waves > 16) return fail(TG_EINVAL, "wg_waves must be in [1, 16]");
+  DevInfo di;
+  tg_status s = device_info(di);
+  if (s != TG_OK) return s;
+  int b = tg::exec_blocks_per_cu(mapping, wg_waves);
+  if (b <= 0) return fail(TG_EDEVICE, "occupancy query failed");
+  *blocks_per_cu = (uint32_t)b;
+  *cus = (uint32_t)di.cus;
+  if (resident) return resident_workers(mapping, wg_waves, resident);
+  return TG_OK;
+}
+
+tg_status tg_graph_debug_times(tg_graph g, uint64_t* task_times, uint64_t* worker_stamps, uint32_t nworkers) {
+  if (!g || !task_times) return fail(TG_EINVAL, "NULL argument");
+  if (!g->solo || !g->solo->tstamp.p) return fail(TG_ESTATE, "no diagnostic launch");
+  Layout& L = *g->solo;
+  (void)hipDeviceSynchronize();
+  std::vector<uint64_t> t((size_t)L.npos * 2);
+  HIPCHK(hipMemcpy(t.data(), L.tstamp.p, t.size() * 8, hipMemcpyDeviceToHost));
+  for (uint32_t v = 0; v < g->N(); ++v) {
+    task_times[2 * v] = t[2 * L.pos_of[0][v]];
+    task_times[2 * v + 1] = t[2 * L.pos_of[0][v] + 1];
+  }
+  if (worker_stamps) {
+    if (nworkers != L.nworkers) return fail(TG_EINVAL, "nworkers must be %u", L.nworkers);
+    HIPCHK(hipMemcpy(worker_stamps, L.wstamp.p, (size_t)L.nworkers * 32, hipMemcpyDeviceToHost));
+  }
+  return TG_OK;
+}
+
+tg_status tg_graph_debug_state(tg_graph g, uint32_t* pending, uint32_t* execs, uint32_t* owner, uint32_t* entry,
+                               uint32_t* wprog, uint32_t nworkers) {
+  if (!g || !pending || !execs || !owner || !entry) return fail(TG_EINVAL, "NULL argument");
+  if (!g->solo) return fail(TG_ESTATE, "graph was never executed");
+  Layout& L = *g->solo;
+  if (!L.execs.p) return fail(TG_ESTATE, "last launch was not a diagnostic launch");
+  (void)hipStreamSynchronize(nullptr);
+  (void)hipDeviceSynchronize();
+  const uint32_t N = g->N();
+  std::vector<uint32_t> c(L.npos), x(L.npos), wb(L.nworkers + 1);
+  HIPCHK(hipMemcpy(c.data(), L.cnt.p, (size_t)L.npos * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(x.data(), L.execs.p, (size_t)L.npos * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(wb.data(), L.wbase.p, wb.size() * 4, hipMemcpyDeviceToHost));
+  for (uint32_t v = 0; v < N; ++v) {
+    const uint32_t pos = L.pos_of[0][v];
+    pending[v] = c[pos];
+    execs[v] = x[pos];
+    uint32_t w = (uint32_t)(std::upper_bound(wb.begin(), wb.end(), pos) - wb.begin()) - 1;
+    owner[v] = w;
+    entry[v] = pos - wb[w];
+  }
+  if (wprog) {
+    if (nworkers != L.nworkers) return fail(TG_EINVAL, "nworkers must be %u", L.nworkers);
+    HIPCHK(hipMemcpy(wprog, L.wprog.p, (size_t)L.nworkers * 4, hipMemcpyDeviceToHost));
+  }
+  return TG_OK;
+}
+
+tg_status tg_graph_emulate_schedule(tg_graph g, uint32_t nworkers, uint32_t window, uint64_t seed, uint32_t* order,
+                                    uint64_t* executed) {
+  if (!g || !order || !executed) return fail(TG_EINVAL, "NULL argument");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  if (window < 1 || window > 64 || nworkers == 0) return fail(TG_EINVAL, "window in [1,64], nworkers >= 1");
+  HostLayout H;
+  std::vector<tg_graph> gs{g};
+  tg_status s = plan_layout(gs, nworkers, H);
+  if (s != TG_OK) return s;
+  std::vector<uint32_t> ord(H.N);
+  s = emulate_layout(H, window, seed, ord.data(), executed);
+  // report task ids, not positions
+  std::vector<uint32_t> tid_of(H.N);
+  for (uint32_t v = 0; v < g->N(); ++v) tid_of[H.pos_of[0][v]] = v;
+  for (uint64_t i = 0; i < *executed; ++i) order[i] = tid_of[ord[i]];
+  return s;
+}
+
+tg_status tg_graph_exec_info(tg_graph g, uint32_t* workers, uint32_t* started) {
+  if (!g || !workers || !started) return fail(TG_EINVAL, "NULL argument");
+  if (!g->solo) return fail(TG_ESTATE, "graph was never executed");
+  *workers = g->solo->nworkers;
+  *started = g->solo->last_started;
+  return TG_OK;
+}
+
+tg_status tg_graph_execute_comparator(tg_graph g, uint32_t mode, void* stream) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  if (g->inflight) return fail(TG_EBUSY, "previous execution not waited for");
+  if (mode != TG_CMP_PER_TASK && mode != TG_CMP_HIPGRAPH) return fail(TG_EINVAL, "unknown comparator %u", mode);
+  tg_status s;
+  if (!g->solo) {
+    std::vector<tg_graph> gs{g};
+    if ((s = build_layout(gs, Config(), g->solo)) != TG_OK) return s;
+  }
+  Layout& L = *g->solo;
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t N = g->N();
+  ExecParams P = L.params;
+  HIPCHK(hipEventRecord(g->ev0, st));
+  if (g->mode == TG_IMPLICIT) {
+    HIPCHK(tg_launch_init_data(g->data.as<uint32_t>(), g->space, sm64_host(g->seed ^ (2ull << 32)), st));
+  }
+  if (mode == TG_CMP_PER_TASK) {
+    for (uint32_t v = 0; v < N; ++v) HIPCHK(tg::launch_one_task(P, L.pos_of[0][v], st));
+  } else {
+    if (!g->hgx) {
+      HIPCHK(hipGraphCreate(&g->hg, 0));
+      std::vector<hipGraphNode_t> node(N);
+      std::vector<hipGraphNode_t> deps;
+      for (uint32_t v = 0; v < N; ++v) {
+        uint32_t pos = L.pos_of[0][v];
+        void* args[2] = {(void*)&P, (void*)&pos};
+        hipKernelNodeParams kp;
+        memset(&kp, 0, sizeof(kp));
+        kp.func = (void*)tg::one_task_kernel();
+        kp.gridDim = dim3(1);
+        kp.blockDim = dim3(64);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        deps.clear();
+        for (uint64_t j = g->dpred_ptr[v]; j < g->dpred_ptr[v + 1]; ++j) deps.push_back(node[g->dpred[j]]);
+        HIPCHK(hipGraphAddKernelNode(&node[v], g->hg, deps.empty() ? nullptr : deps.data(), deps.size(), &kp));
+      }
+      HIPCHK(hipGraphInstantiate(&g->hgx, g->hg, nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(g->hgx, st));
+  }
+  HIPCHK(hipEventRecord(g->ev1, st));
+  g->inflight = true;
+  g->last_layout = nullptr;
+  return TG_OK;
+}
+
+}  // extern "C"

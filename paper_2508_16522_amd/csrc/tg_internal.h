@@ -1,0 +1,113 @@
+// Internal layout shared by the host compiler (tg_host.cpp) and the kernels.
+//
+// A "layout" is a compiled schedule (Algorithm 1, Compile) of one or more
+// graphs for one launch configuration.  Every task of every graph gets a
+// position; positions are grouped per worker (a wavefront or a workgroup, the
+// GPU counterpart of the paper's per-resource worker actor), and within a
+// worker they are ordered by dependence level.  Each position owns one u32
+// counter of pending in-edges (Algorithm 1's per-vertex counter) and an O(1)
+// out-edge list of successor positions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tg {
+
+// Per-graph constants.
+struct GraphEnt {
+  uint64_t key1;     // sm64(seed ^ (1 << 32)): explicit initial payload key
+  uint64_t key2;     // sm64(seed ^ (2 << 32)): implicit initial array key
+  uint32_t* digest;  // digest[task id]
+  uint32_t* data;    // implicit: shared array A (index space words)
+  uint32_t n;        // explicit: payload words per task (power of two)
+  uint32_t mode;     // 1 explicit, 2 implicit
+  uint32_t pad[2];
+};
+
+// Per-position task record (48 bytes, read with scalar loads).
+struct alignas(16) TaskRec {
+  uint64_t out;       // explicit: device address of this task's payload
+                      // implicit: index of its first region requirement
+  uint32_t tid;       // task id inside its graph (creation index)
+  uint32_t graph;     // index into the graph table
+  uint32_t pred_beg;  // explicit: first entry in pred_addr[]
+  uint32_t npred;     // number of distinct predecessors (= in-degree)
+  uint32_t succ_beg;  // first entry in succ_pos[]
+  uint32_t nsucc;     // number of successors
+  uint32_t rounds;    // mix rounds
+  uint32_t nreq;      // implicit: number of region requirements
+  uint32_t pad[2];
+};
+
+// Region requirement on the device (implicit mode).
+struct alignas(16) ReqDev {
+  uint64_t lo, hi;  // [lo, hi)
+  uint32_t priv;    // 1 RO, 2 RW
+  uint32_t rw_base; // ordinal of this interval's first element among the
+                    // task's written elements (digest weights)
+  uint32_t pad[2];
+};
+
+// Control block written by the kernels.
+struct Ctrl {
+  uint32_t abort;      // set when a worker's watchdog fired
+  uint32_t started;    // workers that began (diagnostic launches only)
+  uint32_t stuck_worker, stuck_pos, stuck_cnt, stuck_h, stuck_wcnt;  // first abort
+  uint32_t resident;   // residency probe: workers that saw every worker check in
+  uint32_t pad[56];
+};
+
+struct ExecParams {
+  const TaskRec* rec;
+  const uint64_t* pred_addr;   // payload addresses of predecessors
+  const uint32_t* succ_pos;    // successor positions
+  const uint32_t* indeg;       // initial counter values
+  uint32_t* cnt;               // pending in-edge counters
+  const uint32_t* wbase;       // worker w owns positions [wbase[w], wbase[w+1])
+  const GraphEnt* gtab;
+  const ReqDev* reqs;
+  Ctrl* ctrl;
+  const uint32_t* owner;       // worker of every position
+  uint32_t* bell;              // per-worker doorbell, one per 128-byte line
+  uint32_t* execs;             // diagnostics: executions per position (or null)
+  uint32_t* wprog;             // diagnostics: list entries finished per worker (or null)
+  uint64_t* tstamp;            // diagnostics: per position [start, end] realtime (or null)
+  uint64_t* wstamp;            // diagnostics: per worker [first poll, last scan, scans, bell reads]
+  uint32_t npos;
+  uint32_t nworkers;
+  uint32_t window;             // 1..64
+  uint32_t spin_limit;         // 0 = no limit
+  uint32_t diag;               // 1: count started workers
+  uint32_t idle_sleep;         // s_sleep(2) steps between empty polls after 64 of them
+  uint32_t notify;             // 1: zeroing decrements ring the owner's doorbell
+  uint32_t residency_probe;    // 1: check in, wait for all workers (bounded), exit
+  uint64_t watchdog_ticks;     // s_memrealtime ticks (100 MHz)
+};
+
+constexpr uint32_t kBellStride = 32;  // u32 words between doorbells (128 bytes)
+
+// Launchers (tg_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_reset(const ExecParams& p, hipStream_t s);
+hipError_t launch_exec(const ExecParams& p, uint32_t mapping, uint32_t wg_waves, uint32_t grid_blocks,
+                       hipStream_t s);
+// Occupancy: blocks per CU for the executor kernel of this mapping.
+int exec_blocks_per_cu(uint32_t mapping, uint32_t wg_waves);
+// One task per launch (comparator): runs position `pos` with no counters.
+hipError_t launch_one_task(const ExecParams& p, uint32_t pos, hipStream_t s);
+const void* one_task_kernel();
+
+}  // namespace tg
+
+#include <string>
+#include <vector>
+
+// Result of device dependence inference: out-edge CSR, rows ascending.
+struct InferResult {
+  std::vector<uint64_t> row_ptr;
+  std::vector<uint32_t> col;
+  double ms = 0;  // device time of the inference kernels
+};
+// Defined in tg_infer.hip.  reqs points at n_reqs tg_region_req records.
+hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr, const void* reqs, uint64_t n_reqs, uint64_t space,
+                            InferResult& res, std::string& err);
+hipError_t tg_launch_init_data(uint32_t* A, uint64_t space, uint64_t key2, hipStream_t s);

@@ -1,0 +1,544 @@
+// Persistent task-DAG executor for gfx950 (MI355X).
+//
+// Algorithm 1 of the paper compiles a fixed graph into per-resource worker
+// actors: each vertex keeps an atomic counter of pending in-edges, a finished
+// vertex sends one COMPLETED_EDGE per out-edge (an atomic decrement), and a
+// vertex runs once its counter reaches zero.  Here a worker is a wavefront
+// (mapping 1) or a workgroup (mapping 2) of one persistent launch.
+//
+//  * Event subsystem: one u32 counter per task in HBM, reset from the
+//    in-degree before each execution and decremented once per edge with a
+//    device-scope atomic.  A task is ready exactly when its counter is 0.
+//  * Ready subsystem: the compiler hands every worker its own list of
+//    positions in dependence-level order.  A worker polls the counters of
+//    the next `window` (<= 64) unfinished positions of its list with one
+//    lane per position, compacts the ready ones with a wave ballot, runs them
+//    in list order and slides the window past the finished prefix.  No
+//    address is shared between workers except the counters of real edges,
+//    so there is no contended queue head or tail (a single-address device
+//    atomic costs about 11 ns on this part; distinct addresses sustain
+//    about 27 G atomics/s).
+//  * Publication: payload and array writes use device-coherent (sc1)
+//    stores; before the first out-edge decrement the worker waits for all
+//    its stores to complete (s_waitcnt vmcnt(0)).  Readers load with sc1.
+//    This avoids the L2 write-back that an agent-scope release fence issues
+//    on gfx950, which costs about 13 ns per publication device-wide.
+//  * Every wait is bounded: a worker that sees no progress for the watchdog
+//    interval raises the abort flag and returns, and every other worker
+//    returns when it sees the flag.
+#include "tg_internal.h"
+
+namespace tg {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kSC1 = 16;  // buffer cache policy: device-scope coherent access
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, nbytes, 0x00020000);
+}
+
+// Wait until every outstanding vector memory operation of this wave has
+// completed; the memory clobber keeps the compiler from moving memory
+// operations across it.
+__device__ __forceinline__ void vm_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Read-only tables (records, graph table, predecessor addresses, requirement
+// lists) are read through the constant address space so that wave-uniform
+// accesses become scalar loads.
+// (The host compilation pass sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using cptr = const T __attribute__((address_space(4)))*;
+#else
+template <class T>
+using cptr = const T*;
+#endif
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)p;
+}
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ uint32_t ld_coherent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- hashing
+
+__device__ __forceinline__ uint64_t sm64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// low 32 bits of sm64(key ^ idx), key = sm64(seed ^ (stream << 32))
+__device__ __forceinline__ uint32_t h32k(uint64_t key, uint64_t idx) { return (uint32_t)sm64(key ^ idx); }
+
+template <class V>
+__device__ __forceinline__ V mix_rounds(V x, uint32_t R) {
+  for (uint32_t r = 0; r < R; ++r) {
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    x = x * 0x9E3779B1u + 0x7F4A7C15u;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ teams
+
+// A team is the set of lanes that executes one task: one wavefront or one
+// workgroup.  sum() returns the wrap-around sum of v over the team to every
+// lane; sync() is a team-wide barrier.
+struct WaveTeam {
+  uint32_t t;
+  static constexpr uint32_t S = 64;
+  __device__ __forceinline__ uint32_t size() const { return 64; }
+  __device__ __forceinline__ uint32_t sum(uint32_t v) const { return wave_sum(v); }
+  __device__ __forceinline__ void sync() const {}
+  __device__ __forceinline__ bool leader() const { return t == 0; }
+};
+
+struct BlockTeam {
+  uint32_t t, n;
+  uint32_t* lds;  // >= 17 words
+  __device__ __forceinline__ uint32_t size() const { return n; }
+  __device__ __forceinline__ void sync() const { __syncthreads(); }
+  __device__ __forceinline__ bool leader() const { return t == 0; }
+  __device__ uint32_t sum(uint32_t v) const {
+    v = wave_sum(v);
+    const uint32_t w = t >> 6;
+    __syncthreads();
+    if ((t & 63) == 0) lds[w] = v;
+    __syncthreads();
+    uint32_t s = 0;
+    for (uint32_t i = 0; i < (n >> 6); ++i) s += lds[i];
+    return s;
+  }
+};
+
+// ------------------------------------------------------------------ bodies
+
+template <int VEC>
+struct VecT;
+template <>
+struct VecT<1> { typedef uint32_t T; };
+template <>
+struct VecT<2> { typedef u32x2 T; };
+template <>
+struct VecT<4> { typedef u32x4 T; };
+
+template <int VEC>
+__device__ __forceinline__ typename VecT<VEC>::T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  if constexpr (VEC == 4) return __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, kSC1);
+  else if constexpr (VEC == 2) return __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, kSC1);
+  else return __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, kSC1);
+}
+template <int VEC>
+__device__ __forceinline__ void buf_store(typename VecT<VEC>::T v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  if constexpr (VEC == 4) __builtin_amdgcn_raw_buffer_store_b128(v, r, byte_off, 0, kSC1);
+  else if constexpr (VEC == 2) __builtin_amdgcn_raw_buffer_store_b64(v, r, byte_off, 0, kSC1);
+  else __builtin_amdgcn_raw_buffer_store_b32(v, r, byte_off, 0, kSC1);
+}
+
+template <int VEC>
+__device__ __forceinline__ uint32_t elem(typename VecT<VEC>::T v, int i) {
+  if constexpr (VEC == 1) return v;
+  else return v[i];
+}
+
+// Explicit body over words k = k0, k0 + VEC*S, ... handled VEC at a time.
+template <int VEC, class Team>
+__device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecParams& P, const TaskRec& r,
+                                                   const GraphEnt& G) {
+  typedef typename VecT<VEC>::T V;
+  const uint32_t n = G.n, S = tm.size();
+  const uint32_t nbytes = n * 4u;
+  const cptr<uint64_t> pa = as_const(P.pred_addr) + r.pred_beg;
+  const uint32_t npred = r.npred;
+  const __amdgpu_buffer_rsrc_t wr = make_rsrc((const void*)r.out, nbytes);
+  uint32_t dsum = 0;
+  for (uint32_t k0 = tm.t * VEC; k0 < n; k0 += VEC * S) {
+    V acc;
+    if (npred == 0) {
+      // source: initial payload from the graph seed
+      if constexpr (VEC == 1) {
+        acc = h32k(G.key1, ((uint64_t)r.tid << 16) | k0);
+      } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] = h32k(G.key1, ((uint64_t)r.tid << 16) | (k0 + i));
+      }
+    } else {
+      acc = V(0);
+      uint32_t j = 0;
+      for (; j + 4 <= npred; j += 4) {
+        V a0 = buf_load<VEC>(make_rsrc((const void*)pa[j + 0], nbytes), k0 * 4);
+        V a1 = buf_load<VEC>(make_rsrc((const void*)pa[j + 1], nbytes), k0 * 4);
+        V a2 = buf_load<VEC>(make_rsrc((const void*)pa[j + 2], nbytes), k0 * 4);
+        V a3 = buf_load<VEC>(make_rsrc((const void*)pa[j + 3], nbytes), k0 * 4);
+        acc += (a0 + a1) + (a2 + a3);
+      }
+      for (; j < npred; ++j) acc += buf_load<VEC>(make_rsrc((const void*)pa[j], nbytes), k0 * 4);
+    }
+    V x = mix_rounds<V>(acc ^ r.tid, r.rounds);
+    buf_store<VEC>(x, wr, k0 * 4);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) dsum += elem<VEC>(x, i) * (2u * (k0 + i) + 1u);
+  }
+  return dsum;
+}
+
+template <class Team>
+__device__ __forceinline__ void body_explicit(const Team& tm, const ExecParams& P, const TaskRec& r,
+                                              const GraphEnt& G) {
+  const uint32_t n = G.n, S = tm.size();
+  uint32_t dsum;
+  if (n >= 4 * S) dsum = explicit_words<4>(tm, P, r, G);
+  else if (n >= 2 * S) dsum = explicit_words<2>(tm, P, r, G);
+  else dsum = explicit_words<1>(tm, P, r, G);
+  const uint32_t d = tm.sum(dsum);
+  if (tm.leader()) G.digest[r.tid] = d;
+}
+
+template <class Team>
+__device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& P, const TaskRec& r,
+                                              const GraphEnt& G) {
+  const cptr<ReqDev> rq = as_const(P.reqs) + r.out;
+  uint32_t* A = G.data;
+  const uint32_t S = tm.size();
+  // read-only elements: their wrap sum c
+  uint32_t part = 0;
+  for (uint32_t i = 0; i < r.nreq; ++i) {
+    const ReqDev q = rq[i];
+    if (q.priv != 1) continue;
+    for (uint64_t e = q.lo + tm.t; e < q.hi; e += S) part += ld_coherent(A + e);
+  }
+  const uint32_t key = tm.sum(part) ^ r.tid;
+  const uint32_t R = r.rounds;
+  uint32_t dsum = 0;
+  for (uint32_t i = 0; i < r.nreq; ++i) {
+    const ReqDev q = rq[i];
+    if (q.priv != 2) continue;
+    const uint64_t len = q.hi - q.lo;
+    uint64_t o = tm.t;
+    // four independent elements per lane per step
+    for (; o + 3 * (uint64_t)S < len; o += 4 * (uint64_t)S) {
+      u32x4 x;
+      x[0] = ld_coherent(A + q.lo + o);
+      x[1] = ld_coherent(A + q.lo + o + S);
+      x[2] = ld_coherent(A + q.lo + o + 2 * S);
+      x[3] = ld_coherent(A + q.lo + o + 3 * S);
+      x = mix_rounds<u32x4>(x ^ key, R);
+      st_coherent(A + q.lo + o, x[0]);
+      st_coherent(A + q.lo + o + S, x[1]);
+      st_coherent(A + q.lo + o + 2 * S, x[2]);
+      st_coherent(A + q.lo + o + 3 * S, x[3]);
+      const uint32_t j = q.rw_base + (uint32_t)o;
+      dsum += x[0] * (2u * j + 1u) + x[1] * (2u * (j + S) + 1u) + x[2] * (2u * (j + 2 * S) + 1u) +
+              x[3] * (2u * (j + 3 * S) + 1u);
+    }
+    for (; o < len; o += S) {
+      uint32_t x = mix_rounds<uint32_t>(ld_coherent(A + q.lo + o) ^ key, R);
+      st_coherent(A + q.lo + o, x);
+      dsum += x * (2u * (q.rw_base + (uint32_t)o) + 1u);
+    }
+  }
+  const uint32_t d = tm.sum(dsum);
+  if (tm.leader()) G.digest[r.tid] = d;
+}
+
+template <class Team>
+__device__ __forceinline__ void run_body(const Team& tm, const ExecParams& P, uint32_t pos, TaskRec& r) {
+  r = as_const(P.rec)[pos];
+  const GraphEnt G = as_const(P.gtab)[r.graph];
+  if (P.tstamp && tm.leader()) P.tstamp[2 * pos] = __builtin_amdgcn_s_memrealtime();
+  if (G.mode == 1) body_explicit(tm, P, r, G);
+  else body_implicit(tm, P, r, G);
+  if (P.execs && tm.leader()) __hip_atomic_fetch_add(P.execs + pos, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Signal every out-edge of a finished task (COMPLETED_EDGE).
+template <class Team>
+__device__ __forceinline__ void complete_edges(const Team& tm, const ExecParams& P, const TaskRec& r) {
+  vm_drain();  // this lane's payload stores are complete
+  tm.sync();   // ... and so are every other lane's of the team
+  const uint32_t* sp = P.succ_pos + r.succ_beg;
+  if (P.notify) {
+    // COMPLETED_EDGE plus, for the edge that empties a counter, the message
+    // that starts the task at its owner: the owner's doorbell is rung only
+    // after the decrement has been performed (its old value has returned).
+    for (uint32_t j = tm.t; j < r.nsucc; j += tm.size()) {
+      const uint32_t dst = sp[j];
+      const uint32_t old = __hip_atomic_fetch_sub(P.cnt + dst, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old == 1u)
+        __hip_atomic_fetch_add(P.bell + P.owner[dst] * kBellStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else {
+    for (uint32_t j = tm.t; j < r.nsucc; j += tm.size())
+      __hip_atomic_fetch_sub(P.cnt + sp[j], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ------------------------------------------------------------ worker loop
+
+constexpr uint32_t kExit = 0xFFFFFFFFu;
+
+// Per-worker scheduling state; every field holds the same value in all
+// lanes of the wave that runs the state machine.
+struct WorkerState {
+  uint32_t worker, wb, wcnt;  // list of positions [wb, wb + wcnt)
+  uint32_t h;                 // first unfinished list entry
+  uint64_t done;              // bit i: entry h + i already taken
+  uint64_t pend;              // ready entries found by the last scan, not yet taken
+  uint32_t seen;              // last doorbell value read
+  uint32_t spins;             // consecutive empty polls
+  uint64_t last;              // time of the last task taken (realtime counter)
+  bool rescan;                // the window must be scanned before waiting
+};
+
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+  return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+
+__device__ __forceinline__ uint64_t ready_scan(uint32_t lane, const ExecParams& P, const WorkerState& w) {
+  const uint32_t idx = w.h + lane;
+  const bool valid = lane < P.window && idx < w.wcnt && !((w.done >> lane) & 1ull);
+  uint32_t c = 1u;
+  if (valid) c = ld_coherent(P.cnt + w.wb + idx);
+  return uni64(__ballot(valid && c == 0u));
+}
+
+// One empty poll: back off, and every 64 polls check the abort flag and the
+// watchdog.  Returns false when the worker must stop.
+__device__ __forceinline__ bool idle_step(const ExecParams& P, WorkerState& w, uint32_t lane) {
+  ++w.spins;
+  const uint32_t nap = w.spins < 64 ? 1u : P.idle_sleep;
+  for (uint32_t i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(2);
+  if ((w.spins & 63u) != 0u) return true;
+  if (uni(ld_coherent(&P.ctrl->abort)) != 0u) return false;
+  const uint64_t now = __builtin_amdgcn_s_memrealtime();
+  if (now - w.last > P.watchdog_ticks || (P.spin_limit != 0u && w.spins >= P.spin_limit)) {
+    if (lane == 0) {
+      const uint32_t prev = __hip_atomic_fetch_add(&P.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == 0u) {
+        st_coherent(&P.ctrl->stuck_worker, w.worker);
+        st_coherent(&P.ctrl->stuck_pos, w.wb + w.h);
+        st_coherent(&P.ctrl->stuck_cnt, ld_coherent(P.cnt + w.wb + w.h));
+        st_coherent(&P.ctrl->stuck_h, w.h);
+        st_coherent(&P.ctrl->stuck_wcnt, w.wcnt);
+      }
+    }
+    return false;
+  }
+  return true;
+}
+
+// Returns the position of the worker's next ready task, or kExit when its
+// list is finished or the launch is being aborted.  Run by one whole wave.
+__device__ uint32_t next_task(const ExecParams& P, WorkerState& w, uint32_t lane) {
+  for (;;) {
+    if (w.pend) {
+      const uint32_t b = (uint32_t)__builtin_ctzll(w.pend);
+      w.pend &= w.pend - 1;
+      w.done |= 1ull << b;
+      w.spins = 0;
+      w.last = __builtin_amdgcn_s_memrealtime();
+      return w.wb + w.h + b;
+    }
+    // slide the window past the finished prefix
+    const uint32_t adv = (~w.done == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~w.done);
+    w.h += adv;
+    w.done = adv >= 64u ? 0ull : (w.done >> adv);
+    if (adv) w.rescan = true;
+    if (w.h >= w.wcnt) return kExit;
+    if (P.notify && !w.rescan) {
+      // wait for a message: one word per poll instead of the whole window
+      const uint32_t b = uni(ld_coherent(P.bell + w.worker * kBellStride));
+      if (b == w.seen) {
+        if (!idle_step(P, w, lane)) return kExit;
+        continue;
+      }
+      w.seen = b;
+    }
+    w.pend = ready_scan(lane, P, w);
+    if (P.wstamp && lane == 0) {
+      uint64_t* ws = P.wstamp + 4 * w.worker;
+      const uint64_t now = __builtin_amdgcn_s_memrealtime();
+      if (ws[0] == 0) ws[0] = now;
+      ws[1] = now;
+      ws[2] += 1;
+    }
+    if (w.pend) {
+      w.rescan = true;
+      continue;
+    }
+    w.rescan = false;
+    if (P.notify) continue;
+    if (!idle_step(P, w, lane)) return kExit;
+  }
+}
+
+// Residency probe: every worker checks in and then waits (for at most the
+// watchdog interval) until all nworkers have checked in.  A worker that saw
+// all of them counts itself as resident; the host accepts the worker count
+// only if every worker did.  The same kernel (same resources) as the
+// executor is used, so the answer holds for the real launch.
+__device__ void residency_probe(const ExecParams& P, bool lead) {
+  if (lead) __hip_atomic_fetch_add(&P.ctrl->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (;;) {
+    const uint32_t n = uni(ld_coherent(&P.ctrl->started));
+    if (n >= P.nworkers) {
+      if (lead) __hip_atomic_fetch_add(&P.ctrl->resident, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    if (__builtin_amdgcn_s_memrealtime() - t0 > P.watchdog_ticks) return;
+    __builtin_amdgcn_s_sleep(8);
+  }
+}
+
+__device__ __forceinline__ void worker_init(WorkerState& w, const ExecParams& P, uint32_t worker) {
+  w.worker = worker;
+  w.wb = as_const(P.wbase)[worker];
+  w.wcnt = as_const(P.wbase)[worker + 1] - w.wb;
+  w.h = 0;
+  w.done = 0;
+  w.pend = 0;
+  w.seen = 0;
+  w.spins = 0;
+  w.last = __builtin_amdgcn_s_memrealtime();
+  w.rescan = true;
+}
+
+__global__ __launch_bounds__(256) void k_exec_wave(ExecParams P) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t worker = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (worker >= P.nworkers) return;
+  const WaveTeam tm{lane};
+  if (P.residency_probe) {
+    residency_probe(P, lane == 0);
+    return;
+  }
+  if (P.diag && lane == 0) __hip_atomic_fetch_add(&P.ctrl->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  WorkerState w;
+  worker_init(w, P, worker);
+  for (;;) {
+    const uint32_t pos = next_task(P, w, lane);
+    if (pos == kExit) break;
+    TaskRec r;
+    run_body(tm, P, pos, r);
+    complete_edges(tm, P, r);
+    if (P.tstamp && lane == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
+  }
+  if (P.wprog && lane == 0) P.wprog[worker] = w.h;
+}
+
+// One workgroup per task: wave 0 runs the scheduling state machine and
+// stages the chosen position in LDS; every wave then executes the same
+// sequence of barriers for each task.
+__global__ __launch_bounds__(1024) void k_exec_block(ExecParams P) {
+  __shared__ uint32_t lds[32];
+  __shared__ uint32_t cmd;
+  const uint32_t worker = blockIdx.x;
+  if (worker >= P.nworkers) return;
+  const BlockTeam tm{threadIdx.x, blockDim.x, lds};
+  const uint32_t lane = threadIdx.x & 63u;
+  if (P.residency_probe) {
+    // every wave stays until the probe is over, so the probe occupies
+    // exactly what a real launch occupies
+    if (threadIdx.x < 64) residency_probe(P, lane == 0);
+    __syncthreads();
+    return;
+  }
+  if (P.diag && threadIdx.x == 0)
+    __hip_atomic_fetch_add(&P.ctrl->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  WorkerState w;
+  worker_init(w, P, worker);
+  for (;;) {
+    if (threadIdx.x < 64) {
+      const uint32_t pos = next_task(P, w, lane);
+      if (lane == 0) cmd = pos;
+    }
+    __syncthreads();
+    const uint32_t pos = uni(cmd);
+    __syncthreads();
+    if (pos == kExit) break;
+    TaskRec r;
+    run_body(tm, P, pos, r);
+    complete_edges(tm, P, r);
+    if (P.tstamp && threadIdx.x == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
+    __syncthreads();
+  }
+  if (P.wprog && threadIdx.x == 0) P.wprog[worker] = w.h;
+}
+
+__global__ __launch_bounds__(256) void k_reset(ExecParams P) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P.npos; i += stride) {
+    P.cnt[i] = P.indeg[i];
+    if (P.execs) P.execs[i] = 0;
+  }
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P.nworkers; i += stride) {
+    P.bell[i * kBellStride] = 0;
+    if (P.wprog) P.wprog[i] = 0xFFFFFFFFu;
+    if (P.wstamp)
+      for (int k = 0; k < 4; ++k) P.wstamp[4 * i + k] = 0;
+  }
+  if (P.tstamp)
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * P.npos; i += stride) P.tstamp[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 8) (&P.ctrl->abort)[threadIdx.x] = 0;
+}
+
+// Comparator: one launch runs one task; ordering comes from the stream or
+// from the hipGraph's dependency edges, so no counter is touched.
+__global__ __launch_bounds__(64) void k_one_task(ExecParams P, uint32_t pos) {
+  const WaveTeam tm{threadIdx.x};
+  TaskRec r;
+  run_body(tm, P, pos, r);
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_reset(const ExecParams& p, hipStream_t s) {
+  uint32_t blocks = (p.npos + 255u) / 256u;
+  if (blocks > 4096u) blocks = 4096u;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_exec(const ExecParams& p, uint32_t mapping, uint32_t wg_waves, uint32_t grid_blocks,
+                       hipStream_t s) {
+  if (mapping == 1) hipLaunchKernelGGL(k_exec_wave, dim3(grid_blocks), dim3(256), 0, s, p);
+  else hipLaunchKernelGGL(k_exec_block, dim3(grid_blocks), dim3(wg_waves * 64u), 0, s, p);
+  return hipGetLastError();
+}
+
+int exec_blocks_per_cu(uint32_t mapping, uint32_t wg_waves) {
+  int nb = 0;
+  hipError_t e;
+  if (mapping == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_exec_wave, 256, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_exec_block, (int)(wg_waves * 64u), 0);
+  if (e != hipSuccess) return -1;
+  return nb;
+}
+
+hipError_t launch_one_task(const ExecParams& p, uint32_t pos, hipStream_t s) {
+  hipLaunchKernelGGL(k_one_task, dim3(1), dim3(64), 0, s, p, pos);
+  return hipGetLastError();
+}
+
+const void* one_task_kernel() { return (const void*)k_one_task; }
+
+}  // namespace tg

@@ -1,0 +1,419 @@
+"""ctypes binding of libtaskgraph.so (argument marshalling only).
+
+Every function below has the name of the C entry point it calls and adds no
+computation of its own: numpy arrays are passed as host pointers, streams as
+hipStream_t handles (PyTorch's current stream by default), and device memory
+is obtained through PyTorch's caching allocator when PyTorch sees a GPU.  If
+the shared library has not been built the import fails loudly; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtaskgraph.so")
+
+TG_OK, TG_EINVAL, TG_ENOMEM, TG_EBUSY, TG_EDEVICE, TG_ETIMEOUT, TG_ESTATE = 0, -1, -2, -3, -4, -5, -6
+TG_EXPLICIT, TG_IMPLICIT = 1, 2
+TG_RO, TG_RW = 1, 2
+TG_MAP_WAVE, TG_MAP_WORKGROUP = 1, 2
+TG_CMP_PER_TASK, TG_CMP_HIPGRAPH = 1, 2
+
+# Every symbol the header declares; the CPU test-suite checks the library
+# exports all of them.
+EXPORTS = (
+    "tg_status_str", "tg_last_error", "tg_version", "tg_set_allocator",
+    "tg_graph_create", "tg_task_add", "tg_task_add_many", "tg_task_add_regions", "tg_task_add_regions_many",
+    "tg_graph_finalize", "tg_graph_execute", "tg_graph_wait", "tg_graph_num_tasks", "tg_graph_num_edges",
+    "tg_graph_read_digests", "tg_graph_read_payload", "tg_graph_read_data", "tg_graph_checksum",
+    "tg_graph_read_dag", "tg_graph_timings", "tg_graph_destroy",
+    "tg_batch_create", "tg_batch_execute", "tg_batch_wait", "tg_batch_time_ms", "tg_batch_destroy",
+    "tg_graph_execute_comparator", "tg_exec_occupancy", "tg_graph_exec_info", "tg_graph_debug_state", "tg_graph_emulate_schedule", "tg_graph_debug_times",
+)
+
+
+class TaskGraphError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {status_name(status)} ({status}): {message}")
+        self.status = status
+
+
+class tg_region_req(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64), ("priv", ctypes.c_uint32),
+                ("_pad", ctypes.c_uint32)]
+
+
+class tg_exec_config(ctypes.Structure):
+    _fields_ = [("mapping", ctypes.c_uint32), ("workers", ctypes.c_uint32), ("window", ctypes.c_uint32),
+                ("wg_waves", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32), ("spin_limit", ctypes.c_uint32),
+                ("diag", ctypes.c_uint32), ("notify", ctypes.c_uint32), ("idle_sleep", ctypes.c_uint32)]
+
+
+REQ_DTYPE = np.dtype([("lo", np.uint64), ("hi", np.uint64), ("priv", np.uint32), ("_pad", np.uint32)])
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the shared library; raise if it was never built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2508_16522_amd.build.build_library()")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, u32, u64, P = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+    G = ctypes.c_void_p
+    sig = {
+        "tg_status_str": (ctypes.c_char_p, [i32]),
+        "tg_last_error": (ctypes.c_char_p, []),
+        "tg_version": (ctypes.c_char_p, []),
+        "tg_set_allocator": (i32, [P, P, P]),
+        "tg_graph_create": (i32, [ctypes.POINTER(G), u32, u32, u64, u64]),
+        "tg_task_add": (i32, [G, P, u32, u32, P]),
+        "tg_task_add_many": (i32, [G, u32, P, P, P, u32, P]),
+        "tg_task_add_regions": (i32, [G, P, u32, u32, P]),
+        "tg_task_add_regions_many": (i32, [G, u32, P, P, P, u32, P]),
+        "tg_graph_finalize": (i32, [G]),
+        "tg_graph_execute": (i32, [G, P, P]),
+        "tg_graph_wait": (i32, [G]),
+        "tg_graph_num_tasks": (i32, [G, P]),
+        "tg_graph_num_edges": (i32, [G, P]),
+        "tg_graph_read_digests": (i32, [G, P, u64]),
+        "tg_graph_read_payload": (i32, [G, u32, P, u32]),
+        "tg_graph_read_data": (i32, [G, P, u64, u64]),
+        "tg_graph_checksum": (i32, [G, P]),
+        "tg_graph_read_dag": (i32, [G, P, P, u64, P]),
+        "tg_graph_timings": (i32, [G, P, P, P]),
+        "tg_graph_destroy": (i32, [G]),
+        "tg_batch_create": (i32, [ctypes.POINTER(G), P, u32, P]),
+        "tg_batch_execute": (i32, [G, P]),
+        "tg_batch_wait": (i32, [G]),
+        "tg_batch_time_ms": (i32, [G, P]),
+        "tg_batch_destroy": (i32, [G]),
+        "tg_graph_execute_comparator": (i32, [G, u32, P]),
+        "tg_exec_occupancy": (i32, [u32, u32, P, P, P]),
+        "tg_graph_exec_info": (i32, [G, P, P]),
+        "tg_graph_debug_state": (i32, [G, P, P, P, P, P, u32]),
+        "tg_graph_emulate_schedule": (i32, [G, u32, u32, u64, P, P]),
+        "tg_graph_debug_times": (i32, [G, P, P, u32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype, fn.argtypes = res, args
+    _lib = L
+    return L
+
+
+def status_name(s: int) -> str:
+    return load().tg_status_str(s).decode()
+
+
+def _check(status: int, where: str):
+    if status != TG_OK:
+        raise TaskGraphError(status, where, load().tg_last_error().decode(errors="replace"))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------- allocator
+
+_alloc_cb = None
+_free_cb = None
+
+
+def use_torch_allocator() -> bool:
+    """Route the library's device allocations through PyTorch's caching
+    allocator (only when PyTorch sees a GPU)."""
+    global _alloc_cb, _free_cb
+    try:
+        import torch
+    except ImportError:
+        return False
+    if not torch.cuda.is_available():
+        return False
+    if _alloc_cb is not None:
+        return True
+    ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+    FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+    def _alloc(nbytes, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:  # out of memory -> the library reports TG_ENOMEM
+            return None
+
+    def _free(ptr, _ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a, f = ALLOC(_alloc), FREE(_free)
+    _check(load().tg_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p), None),
+           "tg_set_allocator")
+    _alloc_cb, _free_cb = a, f
+    return True
+
+
+# --------------------------------------------------------------- graphs
+
+
+def tg_graph_create(mode: int, payload_words: int = 0, index_space: int = 0, seed: int = 0):
+    use_torch_allocator()
+    g = ctypes.c_void_p()
+    _check(load().tg_graph_create(ctypes.byref(g), mode, payload_words, index_space, seed), "tg_graph_create")
+    return g
+
+
+def tg_task_add(g, preds, mix_rounds: int) -> int:
+    p = np.ascontiguousarray(preds, dtype=np.uint32)
+    ev = ctypes.c_uint32()
+    _check(load().tg_task_add(g, _ptr(p) if p.size else None, p.size, mix_rounds, ctypes.byref(ev)), "tg_task_add")
+    return ev.value
+
+
+def tg_task_add_many(g, pred_ptr, preds, mix_rounds=None, uniform_rounds: int = 0) -> int:
+    pp = np.ascontiguousarray(pred_ptr, dtype=np.uint64)
+    pr = np.ascontiguousarray(preds, dtype=np.uint32)
+    if pr.size == 0:
+        pr = np.zeros(1, np.uint32)
+    r = None if mix_rounds is None else np.ascontiguousarray(mix_rounds, dtype=np.uint32)
+    ev = ctypes.c_uint32()
+    _check(load().tg_task_add_many(g, pp.size - 1, _ptr(pp), _ptr(pr), _ptr(r) if r is not None else None,
+                                   uniform_rounds, ctypes.byref(ev)), "tg_task_add_many")
+    return ev.value
+
+
+def reqs_array(lo, hi, priv) -> np.ndarray:
+    a = np.zeros(len(lo), REQ_DTYPE)
+    a["lo"], a["hi"], a["priv"] = lo, hi, priv
+    return a
+
+
+def tg_task_add_regions(g, reqs: np.ndarray, mix_rounds: int) -> int:
+    r = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    ev = ctypes.c_uint32()
+    _check(load().tg_task_add_regions(g, _ptr(r) if r.size else None, r.size, mix_rounds, ctypes.byref(ev)),
+           "tg_task_add_regions")
+    return ev.value
+
+
+def tg_task_add_regions_many(g, req_ptr, reqs: np.ndarray, mix_rounds=None, uniform_rounds: int = 0) -> int:
+    rp = np.ascontiguousarray(req_ptr, dtype=np.uint64)
+    r = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    if r.size == 0:
+        r = np.zeros(1, REQ_DTYPE)
+    mr = None if mix_rounds is None else np.ascontiguousarray(mix_rounds, dtype=np.uint32)
+    ev = ctypes.c_uint32()
+    _check(load().tg_task_add_regions_many(g, rp.size - 1, _ptr(rp), _ptr(r), _ptr(mr) if mr is not None else None,
+                                           uniform_rounds, ctypes.byref(ev)), "tg_task_add_regions_many")
+    return ev.value
+
+
+def tg_graph_finalize(g):
+    _check(load().tg_graph_finalize(g), "tg_graph_finalize")
+
+
+def make_config(mapping=0, workers=0, window=0, wg_waves=0, watchdog_ms=0, spin_limit=0, diag=0, notify=0,
+                idle_sleep=0) -> tg_exec_config:
+    return tg_exec_config(mapping, workers, window, wg_waves, watchdog_ms, spin_limit, diag, notify, idle_sleep)
+
+
+def tg_graph_execute(g, cfg: tg_exec_config | None = None, stream=None):
+    _check(load().tg_graph_execute(g, ctypes.byref(cfg) if cfg is not None else None, _stream(stream)),
+           "tg_graph_execute")
+
+
+def tg_graph_wait(g):
+    _check(load().tg_graph_wait(g), "tg_graph_wait")
+
+
+def tg_graph_num_tasks(g) -> int:
+    n = ctypes.c_uint64()
+    _check(load().tg_graph_num_tasks(g, ctypes.byref(n)), "tg_graph_num_tasks")
+    return n.value
+
+
+def tg_graph_num_edges(g) -> int:
+    n = ctypes.c_uint64()
+    _check(load().tg_graph_num_edges(g, ctypes.byref(n)), "tg_graph_num_edges")
+    return n.value
+
+
+def tg_graph_read_digests(g) -> np.ndarray:
+    N = tg_graph_num_tasks(g)
+    out = np.zeros(max(N, 1), np.uint32)
+    _check(load().tg_graph_read_digests(g, _ptr(out), N), "tg_graph_read_digests")
+    return out[:N]
+
+
+def tg_graph_read_payload(g, v: int, n: int) -> np.ndarray:
+    out = np.zeros(n, np.uint32)
+    _check(load().tg_graph_read_payload(g, v, _ptr(out), n), "tg_graph_read_payload")
+    return out
+
+
+def tg_graph_read_data(g, lo: int, hi: int) -> np.ndarray:
+    out = np.zeros(max(hi - lo, 1), np.uint32)
+    _check(load().tg_graph_read_data(g, _ptr(out), lo, hi), "tg_graph_read_data")
+    return out[:hi - lo]
+
+
+def tg_graph_checksum(g) -> int:
+    c = ctypes.c_uint64()
+    _check(load().tg_graph_checksum(g, ctypes.byref(c)), "tg_graph_checksum")
+    return c.value
+
+
+def tg_graph_read_dag(g):
+    N = tg_graph_num_tasks(g)
+    E = tg_graph_num_edges(g)
+    row_ptr = np.zeros(N + 1, np.uint64)
+    col = np.zeros(max(E, 1), np.uint32)
+    e = ctypes.c_uint64()
+    _check(load().tg_graph_read_dag(g, _ptr(row_ptr), _ptr(col), E, ctypes.byref(e)), "tg_graph_read_dag")
+    return row_ptr, col[:e.value]
+
+
+def tg_graph_timings(g):
+    c, i, x = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load().tg_graph_timings(g, ctypes.byref(c), ctypes.byref(i), ctypes.byref(x)), "tg_graph_timings")
+    return {"compile_ms": c.value, "infer_ms": i.value, "exec_ms": x.value}
+
+
+def tg_graph_destroy(g):
+    if g:
+        _check(load().tg_graph_destroy(g), "tg_graph_destroy")
+
+
+def tg_exec_occupancy(mapping: int, wg_waves: int = 4, calibrate: bool = True):
+    b, c, r = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().tg_exec_occupancy(mapping, wg_waves, ctypes.byref(b), ctypes.byref(c),
+                                    ctypes.byref(r) if calibrate else None), "tg_exec_occupancy")
+    return b.value, c.value, (r.value if calibrate else None)
+
+
+def tg_graph_exec_info(g):
+    w, s = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().tg_graph_exec_info(g, ctypes.byref(w), ctypes.byref(s)), "tg_graph_exec_info")
+    return w.value, s.value
+
+
+def tg_graph_debug_state(g):
+    N = tg_graph_num_tasks(g)
+    w, _ = tg_graph_exec_info(g)
+    a = [np.zeros(max(N, 1), np.uint32) for _ in range(4)]
+    wp = np.zeros(max(w, 1), np.uint32)
+    _check(load().tg_graph_debug_state(g, *[_ptr(x) for x in a], _ptr(wp), w), "tg_graph_debug_state")
+    return {"pending": a[0][:N], "execs": a[1][:N], "owner": a[2][:N], "entry": a[3][:N], "wprog": wp[:w]}
+
+
+def tg_graph_debug_times(g):
+    N = tg_graph_num_tasks(g)
+    w, _ = tg_graph_exec_info(g)
+    t = np.zeros(2 * max(N, 1), np.uint64)
+    ws = np.zeros(4 * max(w, 1), np.uint64)
+    _check(load().tg_graph_debug_times(g, _ptr(t), _ptr(ws), w), "tg_graph_debug_times")
+    return t[:2 * N].reshape(N, 2), ws[:4 * w].reshape(w, 4)
+
+
+def tg_graph_emulate_schedule(g, nworkers: int, window: int = 64, seed: int = 0):
+    N = tg_graph_num_tasks(g)
+    order = np.zeros(max(N, 1), np.uint32)
+    ex = ctypes.c_uint64()
+    st = load().tg_graph_emulate_schedule(g, nworkers, window, seed, _ptr(order), ctypes.byref(ex))
+    return st, order[:ex.value]
+
+
+def tg_graph_execute_comparator(g, mode: int, stream=None):
+    _check(load().tg_graph_execute_comparator(g, mode, _stream(stream)), "tg_graph_execute_comparator")
+
+
+# -------------------------------------------------------------- batches
+
+
+def tg_batch_create(graphs, cfg: tg_exec_config | None = None):
+    arr = (ctypes.c_void_p * len(graphs))(*[g.value if isinstance(g, ctypes.c_void_p) else g for g in graphs])
+    b = ctypes.c_void_p()
+    _check(load().tg_batch_create(ctypes.byref(b), arr, len(graphs), ctypes.byref(cfg) if cfg is not None else None),
+           "tg_batch_create")
+    return b
+
+
+def tg_batch_execute(b, stream=None):
+    _check(load().tg_batch_execute(b, _stream(stream)), "tg_batch_execute")
+
+
+def tg_batch_wait(b):
+    _check(load().tg_batch_wait(b), "tg_batch_wait")
+
+
+def tg_batch_time_ms(b) -> float:
+    ms = ctypes.c_double()
+    _check(load().tg_batch_time_ms(b, ctypes.byref(ms)), "tg_batch_time_ms")
+    return ms.value
+
+
+def tg_batch_destroy(b):
+    if b:
+        _check(load().tg_batch_destroy(b), "tg_batch_destroy")
+
+
+# ------------------------------------------------------ convenience layer
+
+
+@dataclass
+class Graph:
+    """Owning wrapper of a tg_graph handle."""
+    handle: ctypes.c_void_p
+    mode: int
+    n: int = 0
+
+    def __del__(self):
+        try:
+            if self.handle:
+                tg_graph_destroy(self.handle)
+                self.handle = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+def graph_from_explicit(eg, finalize: bool = True) -> Graph:
+    """Build a library graph from a workloads.ExplicitGraph (bulk add)."""
+    h = tg_graph_create(TG_EXPLICIT, eg.n, 0, eg.seed)
+    g = Graph(h, TG_EXPLICIT, eg.n)
+    if eg.N:
+        tg_task_add_many(h, eg.pred_ptr, eg.preds, None, eg.rounds)
+    if finalize:
+        tg_graph_finalize(h)
+    return g
+
+
+def graph_from_implicit(ig, finalize: bool = True) -> Graph:
+    """Build a library graph from a workloads.ImplicitGraph (bulk add)."""
+    h = tg_graph_create(TG_IMPLICIT, 0, ig.space, ig.seed)
+    g = Graph(h, TG_IMPLICIT)
+    if ig.N:
+        tg_task_add_regions_many(h, ig.req_ptr, reqs_array(ig.lo, ig.hi, ig.priv), None, ig.rounds)
+    if finalize:
+        tg_graph_finalize(h)
+    return g

@@ -1,0 +1,105 @@
+"""Implicit (region requirement) graphs on the GPU: the inferred DAG equals
+the brute-force conflict DAG, and execution equals sequential program order."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_16522_amd import taskgraph as tg
+from paper_2508_16522_amd import workloads as wl
+from tests import _checks as C
+from tests.gpu_util import run
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_dag(g, ig):
+    row_ptr, col = tg.tg_graph_read_dag(g.handle)
+    ref_ptr, ref_col = oracle.conflict_dag(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv)
+    assert np.array_equal(row_ptr, ref_ptr)
+    assert np.array_equal(col, ref_col)
+
+
+def _check_exec(g, ig, ref):
+    A = tg.tg_graph_read_data(g.handle, 0, ig.space)
+    bad = np.nonzero(A != ref["A"])[0]
+    assert bad.size == 0, f"{bad.size} elements differ, first {bad[:5]}"
+    assert np.array_equal(tg.tg_graph_read_digests(g.handle), ref["digest"])
+    assert tg.tg_graph_checksum(g.handle) == ref["checksum"]
+
+
+def _ref(ig):
+    return oracle.implicit_program_order(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, ig.rounds, ig.space, seed=ig.seed)
+
+
+@pytest.mark.parametrize("mapping", [1, 2])
+@pytest.mark.parametrize("P,S,iters", [(8, 128, 4), (5, 64, 7), (33, 256, 3)])
+def test_halo_small(gpu, P, S, iters, mapping):
+    ig = wl.halo_graph(P, S, iters, seed=2, rounds=3)
+    g = tg.graph_from_implicit(ig)
+    _check_dag(g, ig)
+    run(g, tg.make_config(mapping=mapping))
+    _check_exec(g, ig, _ref(ig))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_regions(gpu, seed):
+    rng = np.random.default_rng(seed)
+    ig = wl.random_regions(80, 300, 4, 40, rng, rounds=2, seed=seed)
+    g = tg.graph_from_implicit(ig)
+    _check_dag(g, ig)
+    for m in (1, 2):
+        run(g, tg.make_config(mapping=m))
+        _check_exec(g, ig, _ref(ig))
+
+
+def test_long_rows_sorted(gpu):
+    # one writer, then 9000 readers of the same word: row 0 has 9000 successors
+    # (longer than the LDS-staged sort) and must come back ascending
+    N = 9001
+    req_ptr = np.arange(N + 1, dtype=np.uint64)
+    lo = np.zeros(N, np.uint64)
+    hi = np.ones(N, np.uint64)
+    priv = np.full(N, 1, np.uint32)
+    priv[0] = 2
+    ig = wl.ImplicitGraph(N=N, req_ptr=req_ptr, lo=lo, hi=hi, priv=priv, space=4, rounds=1)
+    g = tg.graph_from_implicit(ig)
+    row_ptr, col = tg.tg_graph_read_dag(g.handle)
+    assert int(row_ptr[1]) == N - 1 and np.array_equal(col, np.arange(1, N, dtype=np.uint32))
+    run(g)
+    _check_exec(g, ig, _ref(ig))
+
+
+def test_c3_dag_full_size(gpu):
+    # 2^16 tasks over 2^24 elements in 1024 subregions, halos 1..64
+    ig = wl.halo_graph(1024, 16384, 64, seed=0, rounds=64)
+    g = tg.graph_from_implicit(ig)
+    row_ptr, col = tg.tg_graph_read_dag(g.handle)
+    assert col.size == C.halo_edge_count(1024, 64) == 6254592
+    rng = np.random.default_rng(0)
+    rows = list(rng.integers(0, ig.N, size=300)) + [0, 1023, 1024, ig.N - 1]
+    for j in rows:
+        want = oracle.conflict_row(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, int(j))
+        assert np.array_equal(col[int(row_ptr[j]):int(row_ptr[j + 1])], want), f"row {j}"
+
+
+def test_c3_full_size_execution_r0(gpu):
+    ig = wl.halo_graph(1024, 16384, 64, seed=0, rounds=0)
+    g = tg.graph_from_implicit(ig)
+    run(g, tg.make_config(mapping=2))
+    _check_exec(g, ig, _ref(ig))
+
+
+def test_c3_execution_r64_four_sweeps(gpu):
+    ig = wl.halo_graph(1024, 16384, 4, seed=0, rounds=64)
+    g = tg.graph_from_implicit(ig)
+    run(g, tg.make_config(mapping=2))
+    _check_exec(g, ig, _ref(ig))
+
+
+@pytest.mark.parametrize("mode", [tg.TG_CMP_PER_TASK, tg.TG_CMP_HIPGRAPH])
+def test_comparators_implicit(gpu, mode):
+    ig = wl.halo_graph(6, 128, 3, seed=1, rounds=2)
+    g = tg.graph_from_implicit(ig)
+    tg.tg_graph_execute_comparator(g.handle, mode)
+    tg.tg_graph_wait(g.handle)
+    _check_exec(g, ig, _ref(ig))
