@@ -1,0 +1,289 @@
+#!/usr/bin/env python3
+"""Throughput of the task-DAG executor on one MI355X.
+
+Workload (one "step"): the five Task Bench shaped graphs -- no dependences,
+1-D stencil, FFT butterfly, binary tree, random 5-of-33 -- each 1024 wide and
+1000 timesteps deep (1,024,000 tasks, 256-word payloads), every task with 0
+mix rounds, so a step measures the executor's overhead: counter resets,
+ready-window scans, payload hand-off and edge signals for 5,120,000 tasks.
+Graphs are compiled and autotuned once, outside the timed region; inputs are
+resident in HBM when timing starts.
+
+Printed: one JSON line with tasks/s (value), per-task overhead, METG(50)
+from a sweep of mix rounds, the roofline of the executor kernel, the
+comparators (one kernel per task, hipGraph replay) on a capped sub-graph and
+the sequential CPU oracle timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+W, T, NWORDS = 1024, 1000, 256
+SWEEP_ROUNDS = (0, 16, 64, 256, 1024, 4096)
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(eg) -> int:
+    """Bytes the method must move per execution of an explicit graph: every
+    task writes its payload and digest, reads each predecessor's payload,
+    reads its record pointers and out-edge list and touches its counter:
+    N*(4n + 4 + 4 + 8) + E*(4n + 4)."""
+    return eg.N * (4 * eg.n + 16) + eg.E * (4 * eg.n + 4)
+
+
+def metg50(gran_us, eff):
+    """Smallest granularity with efficiency >= 0.5, interpolated in log space
+    between the two sweep points that bracket 0.5 (Task Bench METG(50))."""
+    import math
+    pts = sorted(zip(gran_us, eff))
+    for (g0, e0), (g1, e1) in zip(pts, pts[1:]):
+        if e0 < 0.5 <= e1:
+            t = (0.5 - e0) / (e1 - e0)
+            return math.exp(math.log(g0) + t * (math.log(g1) - math.log(g0)))
+    if pts and pts[0][1] >= 0.5:
+        return pts[0][0]
+    return None
+
+
+def traffic_from_profile(kernel_hash):
+    """HBM bytes per step from the committed counter profile, if it was taken
+    on the current executor kernel source."""
+    path = os.path.join(ROOT, "profiles", "c2_r0_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha1") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_step")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for name in ("tg_kernels.hip", "tg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2508_16522_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the mix-round sweep (METG)")
+    ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--comparator-steps", type=int, default=50, help="timesteps of the comparator sub-graph")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (its executor is single-device); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2508_16522_amd import taskgraph as tg
+    from paper_2508_16522_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    # ---------------------------------------------------------- probes
+    probes = {
+        "mix_word_rounds_per_s": tg.tg_probe(tg.TG_PROBE_MIX_RATE),
+        "copy_bytes_per_s": tg.tg_probe(tg.TG_PROBE_COPY_BW),
+        "atomics_distinct_per_s": tg.tg_probe(tg.TG_PROBE_ATOMIC_DISTINCT),
+        "atomics_contended_per_s": tg.tg_probe(tg.TG_PROBE_ATOMIC_CONTENDED),
+        "launches_per_s": tg.tg_probe(tg.TG_PROBE_LAUNCH_RATE),
+    }
+    log(f"probes: {probes}")
+
+    # --------------------------------------------------------- workload
+    t0 = time.time()
+    egs = [wl.pattern_graph(p, W, T, seed=0, n=NWORDS, rounds=0) for p in wl.PATTERNS]
+    gs = [tg.graph_from_explicit(eg) for eg in egs]
+    tasks_per_step = sum(eg.N for eg in egs)
+    bytes_per_step = sum(algorithmic_bytes(eg) for eg in egs)
+    compile_ms = [tg.tg_graph_timings(g.handle)["compile_ms"] for g in gs]
+    log(f"built {len(gs)} graphs ({tasks_per_step} tasks) in {time.time() - t0:.1f}s; compile ms {compile_ms}")
+
+    tuned = {}
+    for p, g in zip(wl.PATTERNS, gs):
+        if args.no_tune:
+            tuned[p] = None
+        else:
+            cfg, ms = tg.tg_graph_autotune(g.handle, reps=2)
+            tuned[p] = cfg
+            log(f"autotune {p}: {cfg} {ms:.3f} ms")
+
+    def step():
+        for g in gs:
+            tg.tg_graph_execute(g.handle, None, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ------------------------------------------------------ timed steps
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    dev_ms = ev0.elapsed_time(ev1)
+    ms_per_step = dev_ms / args.steps
+    value = tasks_per_step / (ms_per_step * 1e-3)
+
+    # executor-kernel durations of the timed launches (HIP events on `stream`)
+    kern_ms = []
+    for g in gs:
+        kt = tg.tg_graph_kernel_times(g.handle, args.steps)
+        kern_ms.append(float(np.mean(kt)))
+    kernel_ms_per_step = float(sum(kern_ms))
+    achieved_gbs = bytes_per_step / (kernel_ms_per_step * 1e-3) / 1e9
+    log(f"step {ms_per_step:.3f} ms (wall {wall * 1e3 / args.steps:.3f} ms); kernels {kern_ms}")
+
+    # parity of the last timed step against the oracle (digests, checksum)
+    parity = None
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        t_cpu = time.perf_counter()
+        refs = [oracle.exec_explicit(eg.N, eg.n, eg.pred_ptr, eg.preds, eg.rounds, seed=eg.seed, want_payload=False)
+                for eg in egs]
+        cpu_s = time.perf_counter() - t_cpu
+        parity = all(np.array_equal(tg.tg_graph_read_digests(g.handle), r["digest"]) and
+                     tg.tg_graph_checksum(g.handle) == r["checksum"] for g, r in zip(gs, refs))
+        cpu = {"value": tasks_per_step / cpu_s, "unit": "tasks/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full step: the five {W}x{T} graphs ({tasks_per_step} tasks), 0 mix rounds, "
+                         f"sequential C oracle (gcc -O2), one thread; {cpu_s:.1f} s"}
+        log(f"cpu oracle: {cpu_s:.1f} s; parity {parity}")
+
+    # ----------------------------------------------- mix-round sweep (METG)
+    sweep = None
+    if not args.no_sweep:
+        pi = probes["mix_word_rounds_per_s"]
+        rows = []
+        for R in SWEEP_ROUNDS:
+            for g in gs:
+                tg.tg_graph_set_rounds(g.handle, R)
+            step()  # warm
+            reps = 2 if R >= 1024 else 3
+            for _ in range(reps):
+                step()
+            torch.cuda.synchronize()
+            ms = sum(float(np.mean(tg.tg_graph_kernel_times(g.handle, reps))) for g in gs)
+            U = tasks_per_step * NWORDS * R
+            eff = (U / (ms * 1e-3)) / pi if R else 0.0
+            workers = [tg.tg_graph_exec_info(g.handle)[0] for g in gs]
+            # granularity: task run time per concurrent slot (Task Bench METG x-axis)
+            gran_us = ms * 1e3 * (sum(workers) / len(workers)) / tasks_per_step
+            rows.append({"rounds": R, "ms": ms, "efficiency": eff, "granularity_us": gran_us})
+            log(f"sweep R={R}: {ms:.3f} ms eff {eff:.3f} gran {gran_us:.2f} us")
+        for g in gs:
+            tg.tg_graph_set_rounds(g.handle, 0)
+        m = metg50([r["granularity_us"] for r in rows if r["rounds"]], [r["efficiency"] for r in rows if r["rounds"]])
+        sweep = {"rows": rows, "metg50_us": m, "peak_word_rounds_per_s": pi}
+
+    # ------------------------------------------------------- comparators
+    comps = None
+    if not args.no_comparators:
+        eg = wl.pattern_graph("stencil", W, args.comparator_steps, seed=0, n=NWORDS, rounds=0)
+        g = tg.graph_from_explicit(eg)
+        res = {}
+        tg.tg_graph_execute(g.handle, None, stream)
+        tg.tg_graph_wait(g.handle)
+        for name, fn in [("persistent", lambda: tg.tg_graph_execute(g.handle, None, stream)),
+                         ("per_task_launch", lambda: tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_PER_TASK, stream)),
+                         ("hipgraph_replay", lambda: tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_HIPGRAPH, stream))]:
+            t_b = time.perf_counter()
+            fn()  # warm (builds and instantiates the hipGraph the first time)
+            tg.tg_graph_wait(g.handle)
+            build_s = time.perf_counter() - t_b
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            tg.tg_graph_wait(g.handle)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            res[name] = {"ms": ms, "tasks_per_s": eg.N / (ms * 1e-3), "first_call_s": build_s}
+        ref = None
+        try:
+            import oracle
+            ref = oracle.exec_explicit(eg.N, eg.n, eg.pred_ptr, eg.preds, 0, want_payload=False)
+            res["parity"] = bool(np.array_equal(tg.tg_graph_read_digests(g.handle), ref["digest"]))
+        except ImportError:
+            pass
+        comps = {"graph": f"stencil {W}x{args.comparator_steps}, n={NWORDS}, R=0 ({eg.N} tasks)", **res}
+        log(f"comparators: {comps}")
+        del g
+
+    traffic = traffic_from_profile(kernel_source_hash())
+    out = {
+        "metric": "tasks/sec + per-task overhead (ns) + min effective task granularity, 1 GPU",
+        "value": value,
+        "unit": "tasks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"Task Bench shaped graphs none/stencil/fft/tree/random, {W} wide x {T} timesteps, "
+                        f"{NWORDS}-word payloads, 0 mix rounds (one step = the five graphs)",
+            "tasks_per_step": tasks_per_step,
+            "launch": {p: tuned[p] for p in wl.PATTERNS},
+        },
+        "per_task_overhead_ns": 1e9 / value,
+        "metg50_us": sweep["metg50_us"] if sweep else None,
+        "parity": parity,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved_gbs / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_exec_wave / k_exec_block (persistent executor)",
+            "algorithmic_bytes_per_step": bytes_per_step,
+            "kernel_ms_per_step": kernel_ms_per_step,
+        },
+        "cpu_baseline": cpu,
+        "rounds_sweep": sweep,
+        "comparators": comps,
+        "probes": probes,
+        "compile_ms": dict(zip(wl.PATTERNS, compile_ms)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,8 +179,11 @@ tg_status tg_graph_finalize(tg_graph g);
 
 /* Launch one execution of the whole graph on `stream` (Algorithm 1, Execute):
  * counters are reset, so executions repeat with identical results.  Returns
- * without waiting.  cfg may be NULL.  Errors: TG_ESTATE if not finalised,
- * TG_EBUSY if a previous execution has not been waited for. */
+ * without waiting.  cfg may be NULL (the autotuned configuration if one was
+ * chosen, else the defaults).  An execution may be launched while the
+ * previous one is still running if both use the same stream (stream order
+ * serialises them).  Errors: TG_ESTATE if not finalised, TG_EBUSY if a
+ * previous execution on another stream has not been waited for. */
 tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfg, void* stream);
 
 /* Block until the last execution finished; surfaces watchdog aborts
@@ -244,6 +247,35 @@ tg_status tg_graph_debug_state(tg_graph g, uint32_t* pending, uint32_t* execs, u
  * 0 if it never ran); optionally per worker [first scan, last scan, scans,
  * reserved]. */
 tg_status tg_graph_debug_times(tg_graph g, uint64_t* task_times, uint64_t* worker_stamps, uint32_t nworkers);
+
+/* Device time of the executor kernel alone in the last execution (the
+ * counter reset before it excluded), in milliseconds. */
+tg_status tg_graph_kernel_ms(tg_graph g, double* kernel_ms);
+/* Executor-kernel durations (ms, HIP events on the launch stream) of the
+ * graph's most recent launches, oldest first: up to n (at most 64) values
+ * into ms_out, count in *got.  Waits for the last execution. */
+tg_status tg_graph_kernel_times(tg_graph g, double* ms_out, uint32_t n, uint32_t* got);
+/* Give every task of a compiled graph `uniform_rounds` mix rounds (the
+ * schedule is kept; only the task records are rewritten). */
+tg_status tg_graph_set_rounds(tg_graph g, uint32_t uniform_rounds);
+
+/* Autotuner: time the candidate launch configurations (wavefront or
+ * workgroup per task, worker counts, workgroup sizes, doorbell mode) on
+ * this graph, reps executions each, and keep the fastest as the graph's
+ * default (used when tg_graph_execute gets cfg == NULL).  Results never
+ * depend on the configuration.  *best receives the chosen one; best_ms its
+ * mean kernel time. */
+tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, double* best_ms);
+
+/* Roofline probes (run on the current device, synchronous). */
+enum {
+  TG_PROBE_MIX_RATE = 1,         /* word-rounds/s of the body's mix, no dependences */
+  TG_PROBE_COPY_BW = 2,          /* bytes/s read + written by a streaming copy */
+  TG_PROBE_ATOMIC_DISTINCT = 3,  /* device-scope u32 atomics/s on distinct addresses */
+  TG_PROBE_ATOMIC_CONTENDED = 4, /* device-scope u32 atomics/s on one address */
+  TG_PROBE_LAUNCH_RATE = 5       /* empty kernel launches/s, back to back */
+};
+tg_status tg_probe(uint32_t kind, double* value);
 
 /* ------------------------------------------------------- comparators */
 

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtaskgraph.so")
-SOURCES = ["tg_kernels.hip", "tg_infer.hip", "tg_host.cpp"]
+SOURCES = ["tg_kernels.hip", "tg_infer.hip", "tg_probe.hip", "tg_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

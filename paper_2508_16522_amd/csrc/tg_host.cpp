@@ -169,6 +169,7 @@ struct Layout {
   uint32_t nworkers = 0, grid_blocks = 0, npos = 0, last_started = 0;
   DevBuf rec, pred_addr, succ_pos, indeg, cnt, wbase, gtab, reqs, ctrl, execs, wprog, owner, bell, tstamp, wstamp;
   std::vector<std::vector<uint32_t>> pos_of;  // per graph: task id -> position
+  std::vector<TaskRec> rec_host;               // host copy (rounds can be re-set)
   ExecParams params{};
 };
 
@@ -194,8 +195,15 @@ struct tg_graph_s {
   // execution state
   bool inflight = false;
   Layout* last_layout = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  double compile_ms = 0, infer_ms = 0, exec_ms = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evk = nullptr;
+  double compile_ms = 0, infer_ms = 0, exec_ms = 0, kernel_ms = 0;
+  bool has_tuned = false;
+  tg_exec_config tuned{};
+  hipStream_t last_stream = nullptr;
+  // kernel-time ring: events around the executor kernel of recent launches
+  static constexpr uint32_t kRing = 64;
+  hipEvent_t rk0[kRing] = {}, rk1[kRing] = {};
+  uint64_t launches = 0;
   // comparator hipGraph
   hipGraph_t hg = nullptr;
   hipGraphExec_t hgx = nullptr;
@@ -416,6 +424,7 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   L->pos_of = std::move(H.pos_of);
   const uint32_t N = H.N;
   if ((s = upload(L->rec, H.rec)) != TG_OK) return s;
+  L->rec_host = std::move(H.rec);
   if ((s = upload(L->pred_addr, H.pred_addr)) != TG_OK) return s;
   if ((s = upload(L->succ_pos, H.succ_pos)) != TG_OK) return s;
   if ((s = upload(L->indeg, H.indeg)) != TG_OK) return s;
@@ -538,7 +547,8 @@ bool same_layout(const Config& a, const Config& b) {
 }
 
 // Launch reset + persistent executor for a layout.
-tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph>& gs, hipStream_t st) {
+tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph>& gs, hipStream_t st,
+                        hipEvent_t before_kernel = nullptr, hipEvent_t ring0 = nullptr, hipEvent_t ring1 = nullptr) {
   ExecParams P = L.params;
   P.window = cfg.window;
   P.spin_limit = cfg.spin_limit;
@@ -566,7 +576,10 @@ tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph
       HIPCHK(tg_launch_init_data(g->data.as<uint32_t>(), g->space, sm64_host(g->seed ^ (2ull << 32)), st));
     }
   HIPCHK(tg::launch_reset(P, st));
+  if (before_kernel) HIPCHK(hipEventRecord(before_kernel, st));
+  if (ring0) HIPCHK(hipEventRecord(ring0, st));
   if (L.npos) HIPCHK(tg::launch_exec(P, cfg.mapping, cfg.wg_waves, L.grid_blocks, st));
+  if (ring1) HIPCHK(hipEventRecord(ring1, st));
   return TG_OK;
 }
 
@@ -575,11 +588,19 @@ tg_status check_abort(Layout* L) {
   tg::Ctrl c;
   HIPCHK(hipMemcpy(&c, L->ctrl.p, sizeof(c), hipMemcpyDeviceToHost));
   L->last_started = c.started;
+  if (c.sticky || c.abort) {
+    // the host has now seen these aborts: clear them so the next counter
+    // reset does not carry them forward
+    const uint32_t zero[2] = {0, 0};
+    HIPCHK(hipMemcpy(&L->ctrl.as<tg::Ctrl>()->sticky, zero, 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(&L->ctrl.as<tg::Ctrl>()->abort, zero, 4, hipMemcpyHostToDevice));
+  }
   if (c.abort)
     return fail(TG_ETIMEOUT,
                 "executor watchdog aborted the launch (no progress): worker %u of %u stuck at list entry %u/%u "
-                "(position %u, pending in-edges %u); workers started %u",
-                c.stuck_worker, L->nworkers, c.stuck_h, c.stuck_wcnt, c.stuck_pos, c.stuck_cnt, c.started);
+                "(position %u, pending in-edges %u)",
+                c.stuck_worker, L->nworkers, c.stuck_h, c.stuck_wcnt, c.stuck_pos, c.stuck_cnt);
+  if (c.sticky) return fail(TG_ETIMEOUT, "an earlier launch of this layout was aborted by the executor watchdog");
   return TG_OK;
 }
 
@@ -589,6 +610,8 @@ tg_status graph_wait(tg_graph g) {
   HIPCHK(hipEventSynchronize(g->ev1));
   float ms = 0;
   if (hipEventElapsedTime(&ms, g->ev0, g->ev1) == hipSuccess) g->exec_ms = ms;
+  g->kernel_ms = 0;
+  if (g->last_layout && hipEventElapsedTime(&ms, g->evk, g->ev1) == hipSuccess) g->kernel_ms = ms;
   (void)hipGetLastError();
   return check_abort(g->last_layout);
 }
@@ -641,6 +664,12 @@ tg_status ensure_device(tg_graph g) {
   }
   if (!g->ev0) HIPCHK(hipEventCreate(&g->ev0));
   if (!g->ev1) HIPCHK(hipEventCreate(&g->ev1));
+  if (!g->evk) HIPCHK(hipEventCreate(&g->evk));
+  if (!g->rk0[0])
+    for (uint32_t i = 0; i < tg_graph_s::kRing; ++i) {
+      HIPCHK(hipEventCreate(&g->rk0[i]));
+      HIPCHK(hipEventCreate(&g->rk1[i]));
+    }
   return TG_OK;
 }
 
@@ -827,11 +856,15 @@ tg_status tg_graph_finalize(tg_graph g) {
 tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfgp, void* stream) {
   if (!g) return fail(TG_EINVAL, "graph is NULL");
   if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
-  if (g->inflight) return fail(TG_EBUSY, "previous execution not waited for");
-  Config cfg = resolve(cfgp);
+  // a new execution may follow an unwaited one on the same stream (stream
+  // order serialises them); on another stream it must be waited for first
+  if (g->inflight && (hipStream_t)stream != g->last_stream)
+    return fail(TG_EBUSY, "previous execution on another stream not waited for");
+  Config cfg = resolve(cfgp ? cfgp : (g->has_tuned ? &g->tuned : nullptr));
   tg_status s = check_config(cfg);
   if (s != TG_OK) return s;
   if (!g->solo || !same_layout(g->solo->cfg, cfg)) {
+    if (g->inflight && (s = graph_wait(g)) != TG_OK) return s;
     g->solo.reset();
     std::vector<tg_graph> gs{g};
     if ((s = build_layout(gs, cfg, g->solo)) != TG_OK) return s;
@@ -839,9 +872,12 @@ tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfgp, void* stream)
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipEventRecord(g->ev0, st));
   std::vector<tg_graph> gs{g};
-  if ((s = launch_layout(*g->solo, cfg, gs, st)) != TG_OK) return s;
+  const uint32_t slot = (uint32_t)(g->launches % tg_graph_s::kRing);
+  if ((s = launch_layout(*g->solo, cfg, gs, st, g->evk, g->rk0[slot], g->rk1[slot])) != TG_OK) return s;
   HIPCHK(hipEventRecord(g->ev1, st));
+  g->launches++;
   g->inflight = true;
+  g->last_stream = st;
   g->last_layout = g->solo.get();
   return TG_OK;
 }
@@ -931,6 +967,92 @@ tg_status tg_graph_timings(tg_graph g, double* compile_ms, double* infer_ms, dou
   return TG_OK;
 }
 
+tg_status tg_graph_kernel_ms(tg_graph g, double* kernel_ms) {
+  if (!g || !kernel_ms) return fail(TG_EINVAL, "NULL argument");
+  *kernel_ms = g->kernel_ms;
+  return TG_OK;
+}
+
+tg_status tg_graph_kernel_times(tg_graph g, double* ms_out, uint32_t n, uint32_t* got) {
+  if (!g || !ms_out || !got) return fail(TG_EINVAL, "NULL argument");
+  tg_status s = graph_wait(g);
+  if (s != TG_OK) return s;
+  uint64_t have = g->launches < tg_graph_s::kRing ? g->launches : tg_graph_s::kRing;
+  if (n < have) have = n;
+  for (uint64_t i = 0; i < have; ++i) {
+    const uint64_t k = g->launches - have + i;
+    const uint32_t slot = (uint32_t)(k % tg_graph_s::kRing);
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, g->rk0[slot], g->rk1[slot]));
+    ms_out[i] = ms;
+  }
+  *got = (uint32_t)have;
+  return TG_OK;
+}
+
+tg_status tg_graph_set_rounds(tg_graph g, uint32_t uniform_rounds) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  tg_status s = graph_wait(g);
+  if (s != TG_OK) return s;
+  std::fill(g->rounds.begin(), g->rounds.end(), uniform_rounds);
+  if (g->solo) {
+    Layout& L = *g->solo;
+    for (auto& r : L.rec_host) r.rounds = uniform_rounds;
+    if (!L.rec_host.empty())
+      HIPCHK(hipMemcpy(L.rec.p, L.rec_host.data(), L.rec_host.size() * sizeof(TaskRec), hipMemcpyHostToDevice));
+  }
+  return TG_OK;
+}
+
+tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, double* best_ms) {
+  if (!g || !best) return fail(TG_EINVAL, "NULL argument");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  if (reps == 0) reps = 2;
+  tg_status s = graph_wait(g);
+  if (s != TG_OK) return s;
+  // candidate launch configurations
+  std::vector<tg_exec_config> cand;
+  uint32_t rw = 0, rg2 = 0, rg4 = 0;
+  if ((s = resident_workers(TG_MAP_WAVE, 4, &rw)) != TG_OK) return s;
+  if ((s = resident_workers(TG_MAP_WORKGROUP, 2, &rg2)) != TG_OK) return s;
+  if ((s = resident_workers(TG_MAP_WORKGROUP, 4, &rg4)) != TG_OK) return s;
+  auto mk = [](uint32_t m, uint32_t w, uint32_t ww, uint32_t nt) {
+    tg_exec_config c;
+    memset(&c, 0, sizeof(c));
+    c.mapping = m;
+    c.workers = w;
+    c.wg_waves = ww;
+    c.notify = nt;
+    return c;
+  };
+  for (uint32_t w : {rw, rw / 2, rw / 4, rw / 6})
+    if (w) cand.push_back(mk(TG_MAP_WAVE, w, 0, 0));
+  cand.push_back(mk(TG_MAP_WAVE, rw, 0, 1));
+  cand.push_back(mk(TG_MAP_WORKGROUP, rg2, 2, 0));
+  cand.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
+  if (rg4 / 2) cand.push_back(mk(TG_MAP_WORKGROUP, rg4 / 2, 4, 0));
+  double best_t = 1e300;
+  tg_exec_config best_c = cand[0];
+  for (const auto& c : cand) {
+    double tot = 0;
+    for (uint32_t r = 0; r <= reps; ++r) {  // first run warms up
+      if ((s = tg_graph_execute(g, &c, nullptr)) != TG_OK) return s;
+      if ((s = graph_wait(g)) != TG_OK) return s;
+      if (r) tot += g->kernel_ms;
+    }
+    const double mean = tot / reps;
+    if (mean < best_t) {
+      best_t = mean;
+      best_c = c;
+    }
+  }
+  g->tuned = best_c;
+  g->has_tuned = true;
+  *best = best_c;
+  if (best_ms) *best_ms = best_t;
+  return TG_OK;
+}
+
 tg_status tg_graph_destroy(tg_graph g) {
   if (!g) return TG_OK;
   (void)graph_wait(g);
@@ -938,6 +1060,11 @@ tg_status tg_graph_destroy(tg_graph g) {
   if (g->hg) (void)hipGraphDestroy(g->hg);
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
+  if (g->evk) (void)hipEventDestroy(g->evk);
+  for (uint32_t i = 0; i < tg_graph_s::kRing; ++i) {
+    if (g->rk0[i]) (void)hipEventDestroy(g->rk0[i]);
+    if (g->rk1[i]) (void)hipEventDestroy(g->rk1[i]);
+  }
   delete g;
   return TG_OK;
 }

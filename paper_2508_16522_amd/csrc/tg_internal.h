@@ -54,7 +54,8 @@ struct Ctrl {
   uint32_t started;    // workers that began (diagnostic launches only)
   uint32_t stuck_worker, stuck_pos, stuck_cnt, stuck_h, stuck_wcnt;  // first abort
   uint32_t resident;   // residency probe: workers that saw every worker check in
-  uint32_t pad[56];
+  uint32_t sticky;     // aborts of earlier launches since the host last looked
+  uint32_t pad[55];
 };
 
 struct ExecParams {

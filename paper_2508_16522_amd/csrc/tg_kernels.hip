@@ -497,6 +497,9 @@ __global__ __launch_bounds__(256) void k_reset(ExecParams P) {
   }
   if (P.tstamp)
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * P.npos; i += stride) P.tstamp[i] = 0;
+  // an abort of an earlier, not yet inspected launch stays visible
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.ctrl->sticky += P.ctrl->abort;
+  __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x < 8) (&P.ctrl->abort)[threadIdx.x] = 0;
 }
 

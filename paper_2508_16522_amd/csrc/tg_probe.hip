@@ -1,0 +1,142 @@
+// Roofline probes: the denominators of the executor's roofline fractions,
+// measured on the device the library runs on.
+//   mix rate      : word-rounds/s of a dependency-free kernel running the
+//                   task body's mix (the plain integer-VALU peak);
+//   copy bandwidth: HBM bytes/s (read + write) of a streaming copy;
+//   atomics       : device-scope u32 atomic decrements per second on
+//                   distinct addresses and on one contended address;
+//   launch        : back-to-back empty kernel launches per second.
+#include "taskgraph.h"
+#include "tg_internal.h"
+
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void p_mix(uint32_t* a, uint32_t rounds) {
+  const size_t base = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  u32x4 x = {a[base], a[base + 1], a[base + 2], a[base + 3]};
+  for (uint32_t r = 0; r < rounds; ++r) {
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    x = x * 0x9E3779B1u + 0x7F4A7C15u;
+  }
+  a[base] = x[0];
+  a[base + 1] = x[1];
+  a[base + 2] = x[2];
+  a[base + 3] = x[3];
+}
+
+__global__ __launch_bounds__(256) void p_copy(const u32x4* __restrict__ a, u32x4* __restrict__ b, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(a + i), b + i);
+}
+
+__global__ __launch_bounds__(256) void p_atomic_distinct(uint32_t* c, uint32_t mask, uint32_t iters) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint32_t k = 0; k < iters; ++k)
+    __hip_atomic_fetch_sub(c + ((i * 2654435761u + k * 40503u) & mask), 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) void p_atomic_contended(uint32_t* c, uint32_t iters) {
+  if ((threadIdx.x & 63u) == 0)
+    for (uint32_t k = 0; k < iters; ++k) __hip_atomic_fetch_sub(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void p_empty() {}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  Timer() {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  hipError_t start() { return hipEventRecord(a, nullptr); }
+  hipError_t stop(float* ms) {
+    hipError_t e = hipEventRecord(b, nullptr);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventSynchronize(b)) != hipSuccess) return e;
+    return hipEventElapsedTime(ms, a, b);
+  }
+};
+
+}  // namespace
+
+extern "C" tg_status tg_probe(uint32_t kind, double* value) {
+  if (!value) return TG_EINVAL;
+  *value = 0;
+  Timer t;
+  float ms = 0;
+  hipError_t e = hipSuccess;
+  void *a = nullptr, *b = nullptr;
+  switch (kind) {
+    case TG_PROBE_MIX_RATE: {
+      const uint32_t threads = 1u << 22, rounds = 4096;  // 16M words
+      if ((e = hipMalloc(&a, (size_t)threads * 16)) != hipSuccess) break;
+      if ((e = hipMemset(a, 7, (size_t)threads * 16)) != hipSuccess) break;
+      hipLaunchKernelGGL(p_mix, dim3(threads / 256), dim3(256), 0, nullptr, (uint32_t*)a, 64u);  // warm
+      (void)t.start();
+      hipLaunchKernelGGL(p_mix, dim3(threads / 256), dim3(256), 0, nullptr, (uint32_t*)a, rounds);
+      if ((e = t.stop(&ms)) != hipSuccess) break;
+      *value = 4.0 * threads * rounds / (ms * 1e-3);
+      break;
+    }
+    case TG_PROBE_COPY_BW: {
+      const size_t bytes = 1ull << 31;
+      if ((e = hipMalloc(&a, bytes)) != hipSuccess) break;
+      if ((e = hipMalloc(&b, bytes)) != hipSuccess) break;
+      if ((e = hipMemset(a, 1, bytes)) != hipSuccess) break;
+      float best = 1e30f;
+      for (int rep = 0; rep < 4; ++rep) {
+        (void)t.start();
+        hipLaunchKernelGGL(p_copy, dim3(256 * 16), dim3(256), 0, nullptr, (const u32x4*)a, (u32x4*)b, bytes / 16);
+        if ((e = t.stop(&ms)) != hipSuccess) break;
+        best = ms < best ? ms : best;
+      }
+      *value = 2.0 * bytes / (best * 1e-3);
+      break;
+    }
+    case TG_PROBE_ATOMIC_DISTINCT: {
+      const uint32_t words = 1u << 24, threads = 1u << 20, iters = 64;
+      if ((e = hipMalloc(&a, (size_t)words * 4)) != hipSuccess) break;
+      if ((e = hipMemset(a, 0, (size_t)words * 4)) != hipSuccess) break;
+      (void)t.start();
+      hipLaunchKernelGGL(p_atomic_distinct, dim3(threads / 256), dim3(256), 0, nullptr, (uint32_t*)a, words - 1, iters);
+      if ((e = t.stop(&ms)) != hipSuccess) break;
+      *value = (double)threads * iters / (ms * 1e-3);
+      break;
+    }
+    case TG_PROBE_ATOMIC_CONTENDED: {
+      const uint32_t blocks = 1024, iters = 64;
+      if ((e = hipMalloc(&a, 256)) != hipSuccess) break;
+      if ((e = hipMemset(a, 0, 256)) != hipSuccess) break;
+      (void)t.start();
+      hipLaunchKernelGGL(p_atomic_contended, dim3(blocks), dim3(256), 0, nullptr, (uint32_t*)a, iters);
+      if ((e = t.stop(&ms)) != hipSuccess) break;
+      *value = (double)blocks * 4 * iters / (ms * 1e-3);
+      break;
+    }
+    case TG_PROBE_LAUNCH_RATE: {
+      const int n = 20000;
+      for (int i = 0; i < 100; ++i) hipLaunchKernelGGL(p_empty, dim3(1), dim3(64), 0, nullptr);
+      (void)t.start();
+      for (int i = 0; i < n; ++i) hipLaunchKernelGGL(p_empty, dim3(1), dim3(64), 0, nullptr);
+      if ((e = t.stop(&ms)) != hipSuccess) break;
+      *value = n / (ms * 1e-3);
+      break;
+    }
+    default:
+      return TG_EINVAL;
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  if (a) (void)hipFree(a);
+  if (b) (void)hipFree(b);
+  return e == hipSuccess ? TG_OK : TG_EDEVICE;
+}

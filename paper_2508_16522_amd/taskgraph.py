@@ -34,6 +34,7 @@ EXPORTS = (
     "tg_graph_read_dag", "tg_graph_timings", "tg_graph_destroy",
     "tg_batch_create", "tg_batch_execute", "tg_batch_wait", "tg_batch_time_ms", "tg_batch_destroy",
     "tg_graph_execute_comparator", "tg_exec_occupancy", "tg_graph_exec_info", "tg_graph_debug_state", "tg_graph_emulate_schedule", "tg_graph_debug_times",
+    "tg_graph_kernel_ms", "tg_graph_autotune", "tg_probe", "tg_graph_kernel_times", "tg_graph_set_rounds",
 )
 
 
@@ -102,6 +103,11 @@ def load() -> ctypes.CDLL:
         "tg_graph_debug_state": (i32, [G, P, P, P, P, P, u32]),
         "tg_graph_emulate_schedule": (i32, [G, u32, u32, u64, P, P]),
         "tg_graph_debug_times": (i32, [G, P, P, u32]),
+        "tg_graph_kernel_ms": (i32, [G, P]),
+        "tg_graph_autotune": (i32, [G, u32, P, P]),
+        "tg_probe": (i32, [u32, P]),
+        "tg_graph_kernel_times": (i32, [G, P, u32, P]),
+        "tg_graph_set_rounds": (i32, [G, u32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -325,6 +331,39 @@ def tg_graph_debug_state(g):
     wp = np.zeros(max(w, 1), np.uint32)
     _check(load().tg_graph_debug_state(g, *[_ptr(x) for x in a], _ptr(wp), w), "tg_graph_debug_state")
     return {"pending": a[0][:N], "execs": a[1][:N], "owner": a[2][:N], "entry": a[3][:N], "wprog": wp[:w]}
+
+
+TG_PROBE_MIX_RATE, TG_PROBE_COPY_BW, TG_PROBE_ATOMIC_DISTINCT, TG_PROBE_ATOMIC_CONTENDED, TG_PROBE_LAUNCH_RATE = 1, 2, 3, 4, 5
+
+
+def tg_probe(kind: int) -> float:
+    v = ctypes.c_double()
+    _check(load().tg_probe(kind, ctypes.byref(v)), "tg_probe")
+    return v.value
+
+
+def tg_graph_kernel_ms(g) -> float:
+    v = ctypes.c_double()
+    _check(load().tg_graph_kernel_ms(g, ctypes.byref(v)), "tg_graph_kernel_ms")
+    return v.value
+
+
+def tg_graph_kernel_times(g, n: int = 64) -> np.ndarray:
+    out = np.zeros(max(n, 1), np.float64)
+    got = ctypes.c_uint32()
+    _check(load().tg_graph_kernel_times(g, _ptr(out), n, ctypes.byref(got)), "tg_graph_kernel_times")
+    return out[:got.value]
+
+
+def tg_graph_set_rounds(g, rounds: int):
+    _check(load().tg_graph_set_rounds(g, rounds), "tg_graph_set_rounds")
+
+
+def tg_graph_autotune(g, reps: int = 2):
+    c = tg_exec_config()
+    ms = ctypes.c_double()
+    _check(load().tg_graph_autotune(g, reps, ctypes.byref(c), ctypes.byref(ms)), "tg_graph_autotune")
+    return {f: getattr(c, f) for f, _ in tg_exec_config._fields_}, ms.value
 
 
 def tg_graph_debug_times(g):
