@@ -6,8 +6,10 @@ Workload (one "step"): the five Task Bench shaped graphs -- no dependences,
 1000 timesteps deep (1,024,000 tasks, 256-word payloads), every task with 0
 mix rounds, so a step measures the executor's overhead: counter resets,
 ready-window scans, payload hand-off and edge signals for 5,120,000 tasks.
-Graphs are compiled and autotuned once, outside the timed region; inputs are
-resident in HBM when timing starts.
+The five independent graphs of a step run as one batched persistent launch
+(their critical paths overlap); each graph's own launch time is reported
+beside it.  Graphs are compiled and the launch shape autotuned once, outside
+the timed region; inputs are resident in HBM when timing starts.
 
 Printed: one JSON line with tasks/s (value), per-task overhead, METG(50)
 from a sweep of mix rounds, the roofline of the executor kernel, the
@@ -126,18 +128,31 @@ def main():
     compile_ms = [tg.tg_graph_timings(g.handle)["compile_ms"] for g in gs]
     log(f"built {len(gs)} graphs ({tasks_per_step} tasks) in {time.time() - t0:.1f}s; compile ms {compile_ms}")
 
+    # each graph alone (autotuned), for reference
     tuned = {}
+    solo_ms = {}
     for p, g in zip(wl.PATTERNS, gs):
         if args.no_tune:
             tuned[p] = None
+            tg.tg_graph_execute(g.handle, None, stream)
+            tg.tg_graph_wait(g.handle)
         else:
             cfg, ms = tg.tg_graph_autotune(g.handle, reps=2)
             tuned[p] = cfg
-            log(f"autotune {p}: {cfg} {ms:.3f} ms")
+        for _ in range(3):
+            tg.tg_graph_execute(g.handle, None, stream)
+        solo_ms[p] = float(np.mean(tg.tg_graph_kernel_times(g.handle, 3)))
+        log(f"alone {p}: {solo_ms[p]:.3f} ms ({tuned[p]})")
+
+    # the step: one batched launch over the five graphs
+    batch = tg.tg_batch_create([g.handle for g in gs])
+    if not args.no_tune:
+        bcfg, bms = tg.tg_batch_autotune(batch, reps=2)
+        log(f"autotune batch: {bcfg} {bms:.3f} ms")
+    bcfg, _ = tg.tg_batch_info(batch)
 
     def step():
-        for g in gs:
-            tg.tg_graph_execute(g.handle, None, stream)
+        tg.tg_batch_execute(batch, stream)
 
     for _ in range(args.warmup):
         step()
@@ -158,13 +173,10 @@ def main():
     value = tasks_per_step / (ms_per_step * 1e-3)
 
     # executor-kernel durations of the timed launches (HIP events on `stream`)
-    kern_ms = []
-    for g in gs:
-        kt = tg.tg_graph_kernel_times(g.handle, args.steps)
-        kern_ms.append(float(np.mean(kt)))
-    kernel_ms_per_step = float(sum(kern_ms))
+    kt = tg.tg_batch_kernel_times(batch, args.steps)
+    kernel_ms_per_step = float(np.mean(kt))
     achieved_gbs = bytes_per_step / (kernel_ms_per_step * 1e-3) / 1e9
-    log(f"step {ms_per_step:.3f} ms (wall {wall * 1e3 / args.steps:.3f} ms); kernels {kern_ms}")
+    log(f"step {ms_per_step:.3f} ms (wall {wall * 1e3 / args.steps:.3f} ms); kernel {kernel_ms_per_step:.3f} ms")
 
     # parity of the last timed step against the oracle (digests, checksum)
     parity = None
@@ -175,6 +187,7 @@ def main():
         refs = [oracle.exec_explicit(eg.N, eg.n, eg.pred_ptr, eg.preds, eg.rounds, seed=eg.seed, want_payload=False)
                 for eg in egs]
         cpu_s = time.perf_counter() - t_cpu
+        tg.tg_batch_wait(batch)
         parity = all(np.array_equal(tg.tg_graph_read_digests(g.handle), r["digest"]) and
                      tg.tg_graph_checksum(g.handle) == r["checksum"] for g, r in zip(gs, refs))
         cpu = {"value": tasks_per_step / cpu_s, "unit": "tasks/s", "cores": 1, "kind": "oracle",
@@ -187,26 +200,23 @@ def main():
     if not args.no_sweep:
         pi = probes["mix_word_rounds_per_s"]
         rows = []
+        slots = bcfg["workers"]
         for R in SWEEP_ROUNDS:
-            for g in gs:
-                tg.tg_graph_set_rounds(g.handle, R)
+            tg.tg_batch_set_rounds(batch, R)
             step()  # warm
             reps = 2 if R >= 1024 else 3
             for _ in range(reps):
                 step()
-            torch.cuda.synchronize()
-            ms = sum(float(np.mean(tg.tg_graph_kernel_times(g.handle, reps))) for g in gs)
+            ms = float(np.mean(tg.tg_batch_kernel_times(batch, reps)))
             U = tasks_per_step * NWORDS * R
             eff = (U / (ms * 1e-3)) / pi if R else 0.0
-            workers = [tg.tg_graph_exec_info(g.handle)[0] for g in gs]
-            # granularity: task run time per concurrent slot (Task Bench METG x-axis)
-            gran_us = ms * 1e3 * (sum(workers) / len(workers)) / tasks_per_step
+            # granularity: run time per task per concurrent worker (Task Bench METG x-axis)
+            gran_us = ms * 1e3 * slots / tasks_per_step
             rows.append({"rounds": R, "ms": ms, "efficiency": eff, "granularity_us": gran_us})
             log(f"sweep R={R}: {ms:.3f} ms eff {eff:.3f} gran {gran_us:.2f} us")
-        for g in gs:
-            tg.tg_graph_set_rounds(g.handle, 0)
+        tg.tg_batch_set_rounds(batch, 0)
         m = metg50([r["granularity_us"] for r in rows if r["rounds"]], [r["efficiency"] for r in rows if r["rounds"]])
-        sweep = {"rows": rows, "metg50_us": m, "peak_word_rounds_per_s": pi}
+        sweep = {"rows": rows, "metg50_us": m, "peak_word_rounds_per_s": pi, "workers": slots}
 
     # ------------------------------------------------------- comparators
     comps = None
@@ -260,8 +270,10 @@ def main():
             "workload": f"Task Bench shaped graphs none/stencil/fft/tree/random, {W} wide x {T} timesteps, "
                         f"{NWORDS}-word payloads, 0 mix rounds (one step = the five graphs)",
             "tasks_per_step": tasks_per_step,
-            "launch": {p: tuned[p] for p in wl.PATTERNS},
+            "launch": bcfg,
         },
+        "alone_ms": solo_ms,
+        "alone_launch": {p: tuned[p] for p in wl.PATTERNS},
         "per_task_overhead_ns": 1e9 / value,
         "metg50_us": sweep["metg50_us"] if sweep else None,
         "parity": parity,
@@ -282,6 +294,7 @@ def main():
         "probes": probes,
         "compile_ms": dict(zip(wl.PATTERNS, compile_ms)),
     }
+    tg.tg_batch_destroy(batch)
     print(json.dumps(out), flush=True)
 
 

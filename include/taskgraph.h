@@ -215,6 +215,15 @@ tg_status tg_batch_execute(tg_batch b, void* stream);
 tg_status tg_batch_wait(tg_batch b);
 /* Device time of the last batch execution (HIP events), in milliseconds. */
 tg_status tg_batch_time_ms(tg_batch b, double* ms);
+/* Executor-kernel durations of the batch's most recent launches (as
+ * tg_graph_kernel_times). */
+tg_status tg_batch_kernel_times(tg_batch b, double* ms_out, uint32_t n, uint32_t* got);
+/* Give every task of every graph of the batch `uniform_rounds` mix rounds. */
+tg_status tg_batch_set_rounds(tg_batch b, uint32_t uniform_rounds);
+/* Launch shape of the batch (workers = the actual count) and its task count. */
+tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks);
+/* Autotuner for a batch (as tg_graph_autotune); keeps the fastest layout. */
+tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, double* best_ms);
 tg_status tg_batch_destroy(tg_batch b);
 
 /* Residency of the persistent executor.  Every worker of a launch must be
@@ -276,6 +285,28 @@ enum {
   TG_PROBE_LAUNCH_RATE = 5       /* empty kernel launches/s, back to back */
 };
 tg_status tg_probe(uint32_t kind, double* value);
+
+/* ------------------------------------------------------------ serving */
+
+/* A server admits submitted graphs while their device memory fits
+ * budget_bytes, groups the admitted ones (at most max_batch per launch) into
+ * persistent launches on up to `slots` streams (1..4; 0 = 4), and retires
+ * launches as they finish: continuous batching.  Requests arriving while
+ * others run are admitted as soon as a slot and memory free up.  On
+ * completion a request's digests are copied to the host (tg_graph_read_digests
+ * and tg_graph_checksum keep working) and its device memory is released.
+ * A request larger than the whole budget fails with TG_ENOMEM. */
+tg_status tg_server_create(tg_server* out, uint64_t budget_bytes, uint32_t slots, uint32_t max_batch);
+/* Non-blocking.  g must be compiled (finalised) and not executing; the caller
+ * keeps ownership and must not touch g until the ticket is waited for. */
+tg_status tg_server_submit(tg_server srv, tg_graph g, uint64_t* ticket);
+/* Blocks until the request finished; returns its status and the steady-clock
+ * times (ns) of submission, admission and completion.  Each ticket is waited
+ * for once. */
+tg_status tg_server_wait(tg_server srv, uint64_t ticket, uint64_t* submit_ns, uint64_t* admit_ns, uint64_t* done_ns);
+tg_status tg_server_stats(tg_server srv, uint64_t* tasks_done, uint64_t* launches, uint64_t* peak_bytes);
+/* Finishes all submitted work, then stops the server thread. */
+tg_status tg_server_destroy(tg_server srv);
 
 /* ------------------------------------------------------- comparators */
 

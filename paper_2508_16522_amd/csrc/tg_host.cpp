@@ -13,8 +13,12 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <map>
+#include <thread>
 #include <tuple>
+#include <unordered_map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -199,6 +203,9 @@ struct tg_graph_s {
   double compile_ms = 0, infer_ms = 0, exec_ms = 0, kernel_ms = 0;
   bool has_tuned = false;
   tg_exec_config tuned{};
+  // results kept on the host after the device buffers were released
+  bool released = false;
+  std::vector<uint32_t> host_digest;
   hipStream_t last_stream = nullptr;
   // kernel-time ring: events around the executor kernel of recent launches
   static constexpr uint32_t kRing = 64;
@@ -214,7 +221,11 @@ struct tg_batch_s {
   std::vector<tg_graph> graphs;
   std::unique_ptr<Layout> lay;
   bool inflight = false;
+  hipStream_t last_stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  static constexpr uint32_t kRing = 64;
+  hipEvent_t rk0[kRing] = {}, rk1[kRing] = {};
+  uint64_t launches = 0;
 };
 
 namespace {
@@ -655,6 +666,7 @@ tg_status finalize_explicit(tg_graph g) {
 tg_status ensure_device(tg_graph g) {
   const uint32_t N = g->N();
   tg_status s;
+  g->released = false;
   if (g->mode == TG_EXPLICIT && !g->payload.p) {
     if ((s = g->payload.alloc((size_t)N * g->n * 4)) != TG_OK) return s;
   }
@@ -904,6 +916,10 @@ tg_status tg_graph_read_digests(tg_graph g, uint32_t* host_out, uint64_t n) {
   if (!g || !host_out) return fail(TG_EINVAL, "NULL argument");
   if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
   if (n != g->N()) return fail(TG_EINVAL, "n must equal the task count %u", g->N());
+  if (g->released) {
+    if (n) memcpy(host_out, g->host_digest.data(), n * 4);
+    return TG_OK;
+  }
   if (!g->digest.p) return fail(TG_ESTATE, "graph was never executed");
   tg_status s = graph_wait(g);
   if (s != TG_OK) return s;
@@ -1086,23 +1102,32 @@ tg_status tg_batch_create(tg_batch* out, const tg_graph* graphs, uint32_t n, con
   if (s != TG_OK) return s;
   HIPCHK(hipEventCreate(&b->ev0));
   HIPCHK(hipEventCreate(&b->ev1));
+  for (uint32_t i = 0; i < tg_batch_s::kRing; ++i) {
+    HIPCHK(hipEventCreate(&b->rk0[i]));
+    HIPCHK(hipEventCreate(&b->rk1[i]));
+  }
   *out = b.release();
   return TG_OK;
 }
 
 tg_status tg_batch_execute(tg_batch b, void* stream) {
   if (!b) return fail(TG_EINVAL, "batch is NULL");
-  if (b->inflight) return fail(TG_EBUSY, "previous execution not waited for");
-  for (auto g : b->graphs) {
-    tg_status s = graph_wait(g);
-    if (s != TG_OK) return s;
-  }
+  if (b->inflight && (hipStream_t)stream != b->last_stream)
+    return fail(TG_EBUSY, "previous execution on another stream not waited for");
+  if (!b->inflight)
+    for (auto g : b->graphs) {
+      tg_status s = graph_wait(g);
+      if (s != TG_OK) return s;
+    }
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipEventRecord(b->ev0, st));
-  tg_status s = launch_layout(*b->lay, b->lay->cfg, b->graphs, st);
+  const uint32_t slot = (uint32_t)(b->launches % tg_batch_s::kRing);
+  tg_status s = launch_layout(*b->lay, b->lay->cfg, b->graphs, st, nullptr, b->rk0[slot], b->rk1[slot]);
   if (s != TG_OK) return s;
   HIPCHK(hipEventRecord(b->ev1, st));
+  b->launches++;
   b->inflight = true;
+  b->last_stream = st;
   return TG_OK;
 }
 
@@ -1122,11 +1147,111 @@ tg_status tg_batch_time_ms(tg_batch b, double* ms) {
   return TG_OK;
 }
 
+tg_status tg_batch_kernel_times(tg_batch b, double* ms_out, uint32_t n, uint32_t* got) {
+  if (!b || !ms_out || !got) return fail(TG_EINVAL, "NULL argument");
+  tg_status s = tg_batch_wait(b);
+  if (s != TG_OK) return s;
+  uint64_t have = b->launches < tg_batch_s::kRing ? b->launches : tg_batch_s::kRing;
+  if (n < have) have = n;
+  for (uint64_t i = 0; i < have; ++i) {
+    const uint32_t slot = (uint32_t)((b->launches - have + i) % tg_batch_s::kRing);
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, b->rk0[slot], b->rk1[slot]));
+    ms_out[i] = ms;
+  }
+  *got = (uint32_t)have;
+  return TG_OK;
+}
+
+tg_status tg_batch_set_rounds(tg_batch b, uint32_t uniform_rounds) {
+  if (!b) return fail(TG_EINVAL, "batch is NULL");
+  tg_status s = tg_batch_wait(b);
+  if (s != TG_OK) return s;
+  for (auto g : b->graphs) std::fill(g->rounds.begin(), g->rounds.end(), uniform_rounds);
+  Layout& L = *b->lay;
+  for (auto& r : L.rec_host) r.rounds = uniform_rounds;
+  if (!L.rec_host.empty())
+    HIPCHK(hipMemcpy(L.rec.p, L.rec_host.data(), L.rec_host.size() * sizeof(TaskRec), hipMemcpyHostToDevice));
+  return TG_OK;
+}
+
+tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks) {
+  if (!b) return fail(TG_EINVAL, "batch is NULL");
+  if (cfg) {
+    memset(cfg, 0, sizeof(*cfg));
+    const Config& c = b->lay->cfg;
+    cfg->mapping = c.mapping;
+    cfg->workers = b->lay->nworkers;
+    cfg->window = c.window;
+    cfg->wg_waves = c.wg_waves;
+    cfg->watchdog_ms = c.watchdog_ms;
+    cfg->notify = c.notify;
+    cfg->idle_sleep = c.idle_sleep;
+  }
+  if (tasks) *tasks = b->lay->npos;
+  return TG_OK;
+}
+
+// Autotuner for a batch: rebuild the layout for each candidate launch shape,
+// time reps executions, keep the fastest.
+tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, double* best_ms) {
+  if (!b || !best) return fail(TG_EINVAL, "NULL argument");
+  if (reps == 0) reps = 2;
+  tg_status s = tg_batch_wait(b);
+  if (s != TG_OK) return s;
+  uint32_t rw = 0, rg2 = 0, rg4 = 0;
+  if ((s = resident_workers(TG_MAP_WAVE, 4, &rw)) != TG_OK) return s;
+  if ((s = resident_workers(TG_MAP_WORKGROUP, 2, &rg2)) != TG_OK) return s;
+  if ((s = resident_workers(TG_MAP_WORKGROUP, 4, &rg4)) != TG_OK) return s;
+  std::vector<Config> cand;
+  auto mk = [](uint32_t m, uint32_t w, uint32_t ww, uint32_t nt) {
+    Config c;
+    c.mapping = m;
+    c.workers = w;
+    if (ww) c.wg_waves = ww;
+    c.notify = nt;
+    return c;
+  };
+  for (uint32_t w : {rw, rw / 2, rw / 4})
+    if (w) cand.push_back(mk(TG_MAP_WAVE, w, 0, 0));
+  cand.push_back(mk(TG_MAP_WAVE, rw, 0, 1));
+  cand.push_back(mk(TG_MAP_WORKGROUP, rg2, 2, 0));
+  cand.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
+  double best_t = 1e300;
+  Config best_c = cand[0];
+  for (const auto& c : cand) {
+    b->lay.reset();
+    if ((s = build_layout(b->graphs, c, b->lay)) != TG_OK) return s;
+    double tot = 0;
+    for (uint32_t r = 0; r <= reps; ++r) {
+      if ((s = tg_batch_execute(b, nullptr)) != TG_OK) return s;
+      if ((s = tg_batch_wait(b)) != TG_OK) return s;
+      float ms = 0;
+      const uint32_t slot = (uint32_t)((b->launches - 1) % tg_batch_s::kRing);
+      HIPCHK(hipEventElapsedTime(&ms, b->rk0[slot], b->rk1[slot]));
+      if (r) tot += ms;
+    }
+    if (tot / reps < best_t) {
+      best_t = tot / reps;
+      best_c = c;
+    }
+  }
+  b->lay.reset();
+  if ((s = build_layout(b->graphs, best_c, b->lay)) != TG_OK) return s;
+  if ((s = tg_batch_info(b, best, nullptr)) != TG_OK) return s;
+  if (best_ms) *best_ms = best_t;
+  return TG_OK;
+}
+
 tg_status tg_batch_destroy(tg_batch b) {
   if (!b) return TG_OK;
   (void)tg_batch_wait(b);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
+  for (uint32_t i = 0; i < tg_batch_s::kRing; ++i) {
+    if (b->rk0[i]) (void)hipEventDestroy(b->rk0[i]);
+    if (b->rk1[i]) (void)hipEventDestroy(b->rk1[i]);
+  }
   delete b;
   return TG_OK;
 }
@@ -1268,6 +1393,256 @@ tg_status tg_graph_execute_comparator(tg_graph g, uint32_t mode, void* stream) {
   HIPCHK(hipEventRecord(g->ev1, st));
   g->inflight = true;
   g->last_layout = nullptr;
+  return TG_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ serving
+
+// Continuous batching: a server thread admits submitted (compiled) graphs in
+// arrival order while their device memory fits the budget, lays out each
+// admitted group as one persistent launch on one of several streams, and
+// retires launches as their completion events fire -- so requests that
+// arrive while others run are admitted as soon as a launch slot and memory
+// free up, and launches on different streams overlap on the device.  On
+// completion a request's digests are copied to the host and its device
+// memory is released.
+struct tg_server_s {
+  struct Req {
+    tg_graph g = nullptr;
+    uint64_t ticket = 0, bytes = 0;
+    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+    tg_status status = TG_OK;
+    bool done = false;
+  };
+  struct Slot {
+    std::unique_ptr<Layout> lay;
+    std::vector<Req*> reqs;
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+  };
+  uint64_t budget = 0, in_use = 0, next_ticket = 1;
+  uint32_t workers = 0, max_batch = 64;
+  std::vector<Slot> slots;
+  std::deque<Req*> pending;
+  std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
+  std::mutex mu;
+  std::condition_variable cv_done, cv_work;
+  std::thread th;
+  bool stop = false;
+  uint64_t tasks_done = 0, launches = 0, peak_in_use = 0;
+};
+
+namespace {
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// Device bytes a compiled graph occupies while admitted: its payloads (or
+// array) and digests plus its share of a layout.
+uint64_t graph_device_bytes(tg_graph g) {
+  const uint64_t N = g->N(), E = g->succ.size();
+  uint64_t b = N * 4;  // digests
+  b += g->mode == TG_EXPLICIT ? N * g->n * 4ull : g->space * 4ull;
+  b += N * (sizeof(TaskRec) + 4 + 4 + 4 + 4) + E * (8 + 4);
+  return b + 4096;
+}
+
+void release_graph_device(tg_graph g) {
+  const uint32_t N = g->N();
+  g->host_digest.assign(N, 0);
+  if (N && g->digest.p) (void)hipMemcpy(g->host_digest.data(), g->digest.p, (size_t)N * 4, hipMemcpyDeviceToHost);
+  g->payload.release();
+  g->data.release();
+  g->digest.release();
+  g->solo.reset();
+  g->last_layout = nullptr;
+  g->inflight = false;
+  g->released = true;
+}
+
+void server_loop(tg_server srv) {
+  std::unique_lock<std::mutex> lk(srv->mu);
+  while (!srv->stop) {
+    bool progressed = false, busy = false;
+    // retire finished launches
+    for (auto& sl : srv->slots) {
+      if (!sl.busy) continue;
+      busy = true;
+      if (hipEventQuery(sl.ev) != hipSuccess) continue;
+      tg_status st = check_abort(sl.lay.get());
+      const uint64_t t = now_ns();
+      for (auto* r : sl.reqs) {
+        release_graph_device(r->g);
+        srv->in_use -= r->bytes;
+        srv->tasks_done += r->g->N();
+        r->status = st;
+        r->t_done = t;
+        r->done = true;
+      }
+      sl.lay.reset();
+      sl.reqs.clear();
+      sl.busy = false;
+      progressed = true;
+      srv->cv_done.notify_all();
+    }
+    // admit waiting requests into free slots
+    for (auto& sl : srv->slots) {
+      if (sl.busy || srv->pending.empty()) continue;
+      std::vector<tg_server_s::Req*> batch;
+      uint64_t add = 0;
+      while (!srv->pending.empty() && batch.size() < srv->max_batch) {
+        auto* r = srv->pending.front();
+        if (r->bytes > srv->budget) {  // can never fit
+          srv->pending.pop_front();
+          r->status = TG_ENOMEM;
+          r->t_done = now_ns();
+          r->done = true;
+          srv->cv_done.notify_all();
+          continue;
+        }
+        if (srv->in_use + add + r->bytes > srv->budget) break;
+        batch.push_back(r);
+        add += r->bytes;
+        srv->pending.pop_front();
+      }
+      if (batch.empty()) break;
+      srv->in_use += add;
+      if (srv->in_use > srv->peak_in_use) srv->peak_in_use = srv->in_use;
+      const uint64_t t = now_ns();
+      for (auto* r : batch) r->t_admit = t;
+      lk.unlock();
+      std::vector<tg_graph> gs;
+      for (auto* r : batch) gs.push_back(r->g);
+      Config cfg;
+      cfg.workers = srv->workers;
+      tg_status st = build_layout(gs, cfg, sl.lay);
+      if (st == TG_OK) st = launch_layout(*sl.lay, cfg, gs, sl.st);
+      if (st == TG_OK && hipEventRecord(sl.ev, sl.st) != hipSuccess) st = TG_EDEVICE;
+      lk.lock();
+      if (st != TG_OK) {
+        for (auto* r : batch) {
+          release_graph_device(r->g);
+          srv->in_use -= r->bytes;
+          r->status = st;
+          r->t_done = now_ns();
+          r->done = true;
+        }
+        sl.lay.reset();
+        srv->cv_done.notify_all();
+      } else {
+        sl.reqs = batch;
+        sl.busy = true;
+        srv->launches++;
+        busy = true;
+      }
+      progressed = true;
+    }
+    if (!busy && srv->pending.empty()) {
+      srv->cv_work.wait(lk);
+    } else if (!progressed) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+tg_status tg_server_create(tg_server* out, uint64_t budget_bytes, uint32_t slots, uint32_t max_batch) {
+  if (!out) return fail(TG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (slots == 0) slots = 4;
+  if (slots > 4) return fail(TG_EINVAL, "at most 4 launch slots (one hardware queue each)");
+  if (budget_bytes == 0) return fail(TG_EINVAL, "budget must be positive");
+  uint32_t resident = 0;
+  tg_status s = resident_workers(TG_MAP_WAVE, 4, &resident);
+  if (s != TG_OK) return s;
+  auto srv = std::make_unique<tg_server_s>();
+  srv->budget = budget_bytes;
+  srv->workers = resident / slots;  // concurrent launches stay co-resident together
+  srv->max_batch = max_batch ? max_batch : 64;
+  srv->slots.resize(slots);
+  for (auto& sl : srv->slots) {
+    HIPCHK(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+  }
+  tg_server srvp = srv.release();
+  srvp->th = std::thread(server_loop, srvp);
+  *out = srvp;
+  return TG_OK;
+}
+
+tg_status tg_server_submit(tg_server srv, tg_graph g, uint64_t* ticket) {
+  if (!srv || !g || !ticket) return fail(TG_EINVAL, "NULL argument");
+  if (!g->finalized) return fail(TG_ESTATE, "submit compiled graphs (tg_graph_finalize first)");
+  if (g->inflight) return fail(TG_EBUSY, "graph has an execution in flight");
+  auto r = std::make_unique<tg_server_s::Req>();
+  r->g = g;
+  r->bytes = graph_device_bytes(g);
+  r->t_submit = now_ns();
+  std::lock_guard<std::mutex> lk(srv->mu);
+  r->ticket = srv->next_ticket++;
+  *ticket = r->ticket;
+  srv->pending.push_back(r.get());
+  srv->reqs[r->ticket] = std::move(r);
+  srv->cv_work.notify_one();
+  return TG_OK;
+}
+
+tg_status tg_server_wait(tg_server srv, uint64_t ticket, uint64_t* submit_ns, uint64_t* admit_ns, uint64_t* done_ns) {
+  if (!srv) return fail(TG_EINVAL, "server is NULL");
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(ticket);
+  if (it == srv->reqs.end()) return fail(TG_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  tg_server_s::Req* r = it->second.get();
+  srv->cv_done.wait(lk, [&] { return r->done; });
+  if (submit_ns) *submit_ns = r->t_submit;
+  if (admit_ns) *admit_ns = r->t_admit;
+  if (done_ns) *done_ns = r->t_done;
+  const tg_status st = r->status;
+  srv->reqs.erase(it);
+  if (st != TG_OK) return fail(st, "request %llu failed", (unsigned long long)ticket);
+  return TG_OK;
+}
+
+tg_status tg_server_stats(tg_server srv, uint64_t* tasks_done, uint64_t* launches, uint64_t* peak_bytes) {
+  if (!srv) return fail(TG_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (tasks_done) *tasks_done = srv->tasks_done;
+  if (launches) *launches = srv->launches;
+  if (peak_bytes) *peak_bytes = srv->peak_in_use;
+  return TG_OK;
+}
+
+tg_status tg_server_destroy(tg_server srv) {
+  if (!srv) return TG_OK;
+  {
+    std::unique_lock<std::mutex> lk(srv->mu);
+    // let admitted and pending work finish
+    srv->cv_done.wait(lk, [&] {
+      if (!srv->pending.empty()) return false;
+      for (auto& sl : srv->slots)
+        if (sl.busy) return false;
+      return true;
+    });
+    srv->stop = true;
+    srv->cv_work.notify_all();
+  }
+  srv->th.join();
+  for (auto& sl : srv->slots) {
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.st) (void)hipStreamDestroy(sl.st);
+  }
+  delete srv;
   return TG_OK;
 }
 

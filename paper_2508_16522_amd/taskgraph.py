@@ -35,6 +35,8 @@ EXPORTS = (
     "tg_batch_create", "tg_batch_execute", "tg_batch_wait", "tg_batch_time_ms", "tg_batch_destroy",
     "tg_graph_execute_comparator", "tg_exec_occupancy", "tg_graph_exec_info", "tg_graph_debug_state", "tg_graph_emulate_schedule", "tg_graph_debug_times",
     "tg_graph_kernel_ms", "tg_graph_autotune", "tg_probe", "tg_graph_kernel_times", "tg_graph_set_rounds",
+    "tg_server_create", "tg_server_submit", "tg_server_wait", "tg_server_stats", "tg_server_destroy",
+    "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
 )
 
 
@@ -108,6 +110,15 @@ def load() -> ctypes.CDLL:
         "tg_probe": (i32, [u32, P]),
         "tg_graph_kernel_times": (i32, [G, P, u32, P]),
         "tg_graph_set_rounds": (i32, [G, u32]),
+        "tg_server_create": (i32, [ctypes.POINTER(G), u64, u32, u32]),
+        "tg_server_submit": (i32, [G, G, P]),
+        "tg_server_wait": (i32, [G, u64, P, P, P]),
+        "tg_server_stats": (i32, [G, P, P, P]),
+        "tg_server_destroy": (i32, [G]),
+        "tg_batch_kernel_times": (i32, [G, P, u32, P]),
+        "tg_batch_set_rounds": (i32, [G, u32]),
+        "tg_batch_info": (i32, [G, P, P]),
+        "tg_batch_autotune": (i32, [G, u32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -412,9 +423,67 @@ def tg_batch_time_ms(b) -> float:
     return ms.value
 
 
+def tg_batch_kernel_times(b, n: int = 64) -> np.ndarray:
+    out = np.zeros(max(n, 1), np.float64)
+    got = ctypes.c_uint32()
+    _check(load().tg_batch_kernel_times(b, _ptr(out), n, ctypes.byref(got)), "tg_batch_kernel_times")
+    return out[:got.value]
+
+
+def tg_batch_set_rounds(b, rounds: int):
+    _check(load().tg_batch_set_rounds(b, rounds), "tg_batch_set_rounds")
+
+
+def tg_batch_info(b):
+    c = tg_exec_config()
+    n = ctypes.c_uint64()
+    _check(load().tg_batch_info(b, ctypes.byref(c), ctypes.byref(n)), "tg_batch_info")
+    return {f: getattr(c, f) for f, _ in tg_exec_config._fields_}, n.value
+
+
+def tg_batch_autotune(b, reps: int = 2):
+    c = tg_exec_config()
+    ms = ctypes.c_double()
+    _check(load().tg_batch_autotune(b, reps, ctypes.byref(c), ctypes.byref(ms)), "tg_batch_autotune")
+    return {f: getattr(c, f) for f, _ in tg_exec_config._fields_}, ms.value
+
+
 def tg_batch_destroy(b):
     if b:
         _check(load().tg_batch_destroy(b), "tg_batch_destroy")
+
+
+# ------------------------------------------------------------- serving
+
+
+def tg_server_create(budget_bytes: int, slots: int = 4, max_batch: int = 64):
+    use_torch_allocator()
+    srv = ctypes.c_void_p()
+    _check(load().tg_server_create(ctypes.byref(srv), budget_bytes, slots, max_batch), "tg_server_create")
+    return srv
+
+
+def tg_server_submit(srv, g) -> int:
+    t = ctypes.c_uint64()
+    _check(load().tg_server_submit(srv, g, ctypes.byref(t)), "tg_server_submit")
+    return t.value
+
+
+def tg_server_wait(srv, ticket: int):
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load().tg_server_wait(srv, ticket, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "tg_server_wait")
+    return a.value, b.value, c.value
+
+
+def tg_server_stats(srv):
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load().tg_server_stats(srv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "tg_server_stats")
+    return {"tasks_done": a.value, "launches": b.value, "peak_bytes": c.value}
+
+
+def tg_server_destroy(srv):
+    if srv:
+        _check(load().tg_server_destroy(srv), "tg_server_destroy")
 
 
 # ------------------------------------------------------ convenience layer

@@ -128,9 +128,12 @@ def pattern_graph(pattern: str, W: int, T: int, seed: int = 0, n: int = 64, roun
             partner = lanes ^ (1 << (t % L))
             ok = partner < W
             c = 1 + ok.astype(np.int64)
-            pairs = np.stack([np.minimum(lanes, partner), np.maximum(lanes, partner)], 1)
-            out = [pairs[i] if ok[i] else lanes[i:i + 1] for i in range(W)]
-            return c, np.concatenate(out)
+            lo_l = np.minimum(lanes, partner)
+            hi_l = np.maximum(lanes, partner)
+            # two entries per lane, the second dropped where the partner is out of range
+            pairs = np.stack([np.where(ok, lo_l, lanes), hi_l], 1)
+            keep = np.stack([np.ones(W, bool), ok], 1)
+            return c, pairs[keep]
         ptr, flat = _grid_csr(W, T, step)
     elif pattern == "tree":
         L = _log2_floor(W)
@@ -140,18 +143,19 @@ def pattern_graph(pattern: str, W: int, T: int, seed: int = 0, n: int = 64, roun
             if L == 0:
                 return np.ones(W, np.int64), lanes
             p = (t - 1) % (2 * L)
-            c = np.ones(W, np.int64)
-            out = [np.array([i]) for i in range(W)]
+            first = lanes.copy()
+            second = np.full(W, -1, np.int64)
             if p < L:
-                s = 1 << (L - 1 - p)
-                for i in range(0, P, s):
-                    out[i] = np.array([i - (i % (2 * s))])
+                s_ = 1 << (L - 1 - p)
+                act = (lanes < P) & (lanes % s_ == 0)
+                first = np.where(act, lanes - (lanes % (2 * s_)), lanes)
             else:
-                s = 1 << (p - L)
-                for i in range(0, P, 2 * s):
-                    out[i] = np.array([i, i + s])
-                    c[i] = 2
-            return c, np.concatenate(out)
+                s_ = 1 << (p - L)
+                act = (lanes < P) & (lanes % (2 * s_) == 0)
+                second = np.where(act, lanes + s_, -1)
+            c = 1 + (second >= 0).astype(np.int64)
+            pairs = np.stack([first, second], 1)
+            return c, pairs[pairs >= 0]
         ptr, flat = _grid_csr(W, T, step)
     else:  # random
         ptr = np.zeros(N + 1, np.uint64)

@@ -1,0 +1,97 @@
+"""Serving (continuous batching): graphs submitted while others run are
+admitted by device-memory budget into overlapping persistent launches; every
+result is bit-identical to the oracle and to running the graph alone."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_16522_amd import taskgraph as tg
+from paper_2508_16522_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _ref(graph):
+    if isinstance(graph, wl.ImplicitGraph):
+        return oracle.implicit_program_order(graph.N, graph.req_ptr, graph.lo, graph.hi, graph.priv, graph.rounds,
+                                             graph.space, seed=graph.seed)
+    return oracle.exec_explicit(graph.N, graph.n, graph.pred_ptr, graph.preds, graph.rounds, seed=graph.seed,
+                                want_payload=False)
+
+
+def _small_requests(num, seed=0):
+    reqs = wl.serving_manifest(num, rate=2000.0, seed=seed, median=400, max_tasks=4000)
+    for r in reqs:
+        r.rounds = min(r.rounds, 200)
+    return reqs
+
+
+def _build(reqs):
+    graphs = [wl.build_request(r) for r in reqs]
+    handles = [tg.graph_from_implicit(x) if isinstance(x, wl.ImplicitGraph) else tg.graph_from_explicit(x)
+               for x in graphs]
+    return graphs, handles
+
+
+@pytest.mark.parametrize("slots,max_batch", [(4, 8), (1, 1), (2, 64)])
+def test_mix_equals_alone_and_oracle(gpu, slots, max_batch):
+    reqs = _small_requests(40, seed=slots)
+    graphs, handles = _build(reqs)
+    srv = tg.tg_server_create(8 << 30, slots=slots, max_batch=max_batch)
+    try:
+        # submit following the arrival times, from another thread
+        tickets = [None] * len(reqs)
+
+        def client():
+            t0 = time.perf_counter()
+            for i, r in enumerate(reqs):
+                dt = r.arrival_s - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = tg.tg_server_submit(srv, handles[i].handle)
+
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        times = [tg.tg_server_wait(srv, t) for t in tickets]
+        stats = tg.tg_server_stats(srv)
+    finally:
+        tg.tg_server_destroy(srv)
+    assert stats["tasks_done"] == sum(x.N for x in graphs)
+    for (s, a, d) in times:
+        assert s <= a <= d
+    for x, h in zip(graphs, handles):
+        ref = _ref(x)
+        assert np.array_equal(tg.tg_graph_read_digests(h.handle), ref["digest"])
+        assert tg.tg_graph_checksum(h.handle) == ref["checksum"]
+    # the same graphs alone, one at a time
+    for x, h in list(zip(graphs, handles))[:10]:
+        tg.tg_graph_execute(h.handle)
+        tg.tg_graph_wait(h.handle)
+        assert np.array_equal(tg.tg_graph_read_digests(h.handle), _ref(x)["digest"])
+
+
+def test_budget_admission(gpu):
+    # a budget that fits about one request at a time still completes them all,
+    # and a request larger than the whole budget is refused
+    reqs = _small_requests(12, seed=9)
+    graphs, handles = _build(reqs)
+    big = wl.pattern_graph("stencil", 256, 128, seed=1, n=1024, rounds=0)
+    hb = tg.graph_from_explicit(big)
+    srv = tg.tg_server_create(64 << 20, slots=2, max_batch=4)
+    try:
+        tickets = [tg.tg_server_submit(srv, h.handle) for h in handles]
+        tb = tg.tg_server_submit(srv, hb.handle)
+        for t in tickets:
+            tg.tg_server_wait(srv, t)
+        with pytest.raises(tg.TaskGraphError) as ei:
+            tg.tg_server_wait(srv, tb)
+        assert ei.value.status == tg.TG_ENOMEM
+        assert tg.tg_server_stats(srv)["peak_bytes"] <= 64 << 20
+    finally:
+        tg.tg_server_destroy(srv)
+    for x, h in zip(graphs, handles):
+        assert np.array_equal(tg.tg_graph_read_digests(h.handle), _ref(x)["digest"])
