@@ -91,6 +91,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--comparator-steps", type=int, default=50, help="timesteps of the comparator sub-graph")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2 (default): the bench line; c3 implicit, c4 4096-graph batch, c5 serving")
+    ap.add_argument("--graphs", type=int, default=4096, help="c4: number of graphs")
+    ap.add_argument("--requests", type=int, default=10000, help="c5: measured requests")
+    ap.add_argument("--rate", type=float, default=2000.0, help="c5: arrivals per second")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (its executor is single-device); use --gpus 1",
@@ -108,6 +113,11 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload != "c2":
+        import bench_workloads
+        out = getattr(bench_workloads, "run_" + args.workload)(args, stream)
+        print(json.dumps(out), flush=True)
+        return
 
     # ---------------------------------------------------------- probes
     probes = {

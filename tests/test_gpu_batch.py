@@ -35,3 +35,28 @@ def test_mixed_batch(gpu, mapping):
     for g, eg in zip(gs[:5], egs[:5]):
         run(g)
         check_explicit(g, eg, oracle_explicit(eg, want_payload=False))
+
+
+def test_manifest_slice_256_graphs(gpu):
+    # the first 256 graphs of the frozen 4096-graph manifest (their real
+    # widths, depths, payload sizes and log-normal rounds) in one launch;
+    # 24 sampled graphs compared digest by digest with the oracle
+    specs = wl.batch_manifest(4096, seed=0)[:256]
+    egs = [wl.pattern_graph(s.pattern, s.W, s.T, seed=s.seed, n=s.n, rounds=s.rounds) for s in specs]
+    gs = [tg.graph_from_explicit(eg) for eg in egs]
+    b = tg.tg_batch_create([g.handle for g in gs])
+    try:
+        tg.tg_batch_execute(b)
+        tg.tg_batch_wait(b)
+    finally:
+        tg.tg_batch_destroy(b)
+    cost = np.array([eg.N * eg.n * max(eg.rounds, 1) for eg in egs])
+    rng = np.random.default_rng(0)
+    pick = list(np.argsort(cost)[:16]) + list(rng.choice(len(egs), size=8, replace=False))
+    for i in pick:
+        eg = egs[i]
+        if eg.N * eg.n * max(eg.rounds, 1) > 3e9:
+            continue  # keep the oracle within seconds
+        ref = oracle_explicit(eg, want_payload=False)
+        assert np.array_equal(tg.tg_graph_read_digests(gs[i].handle), ref["digest"]), f"graph {i}"
+        assert tg.tg_graph_checksum(gs[i].handle) == ref["checksum"]
