@@ -186,6 +186,15 @@ tg_status tg_graph_finalize(tg_graph g);
  * previous execution on another stream has not been waited for. */
 tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfg, void* stream);
 
+/* External pre- and post-condition vertices (Section 4.1): the execution
+ * starts only after every hipEvent_t in pre[0..npre) (recorded by the caller,
+ * on any stream) has completed, and `post` (a hipEvent_t, may be NULL) is
+ * recorded on `stream` when the whole graph has finished, so compiled graphs
+ * can be stitched into a larger, dynamically built program.  Otherwise as
+ * tg_graph_execute. */
+tg_status tg_graph_execute_after(tg_graph g, const tg_exec_config* cfg, void* stream, void* const* pre, uint32_t npre,
+                                 void* post);
+
 /* Block until the last execution finished; surfaces watchdog aborts
  * (TG_ETIMEOUT) and deferred HIP errors (TG_EDEVICE). */
 tg_status tg_graph_wait(tg_graph g);

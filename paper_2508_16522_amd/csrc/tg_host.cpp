@@ -899,6 +899,21 @@ tg_status tg_graph_wait(tg_graph g) {
   return graph_wait(g);
 }
 
+tg_status tg_graph_execute_after(tg_graph g, const tg_exec_config* cfg, void* stream, void* const* pre, uint32_t npre,
+                                 void* post) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (npre && !pre) return fail(TG_EINVAL, "pre is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  for (uint32_t i = 0; i < npre; ++i) {
+    if (!pre[i]) return fail(TG_EINVAL, "pre[%u] is NULL", i);
+    HIPCHK(hipStreamWaitEvent(st, (hipEvent_t)pre[i], 0));
+  }
+  tg_status s = tg_graph_execute(g, cfg, stream);
+  if (s != TG_OK) return s;
+  if (post) HIPCHK(hipEventRecord((hipEvent_t)post, st));
+  return TG_OK;
+}
+
 tg_status tg_graph_num_tasks(tg_graph g, uint64_t* n) {
   if (!g || !n) return fail(TG_EINVAL, "NULL argument");
   *n = g->N();

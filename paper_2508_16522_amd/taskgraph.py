@@ -37,6 +37,7 @@ EXPORTS = (
     "tg_graph_kernel_ms", "tg_graph_autotune", "tg_probe", "tg_graph_kernel_times", "tg_graph_set_rounds",
     "tg_server_create", "tg_server_submit", "tg_server_wait", "tg_server_stats", "tg_server_destroy",
     "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
+    "tg_graph_execute_after",
 )
 
 
@@ -119,6 +120,7 @@ def load() -> ctypes.CDLL:
         "tg_batch_set_rounds": (i32, [G, u32]),
         "tg_batch_info": (i32, [G, P, P]),
         "tg_batch_autotune": (i32, [G, u32, P, P]),
+        "tg_graph_execute_after": (i32, [G, P, P, P, u32, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -258,6 +260,16 @@ def make_config(mapping=0, workers=0, window=0, wg_waves=0, watchdog_ms=0, spin_
 def tg_graph_execute(g, cfg: tg_exec_config | None = None, stream=None):
     _check(load().tg_graph_execute(g, ctypes.byref(cfg) if cfg is not None else None, _stream(stream)),
            "tg_graph_execute")
+
+
+def tg_graph_execute_after(g, pre_events=(), post_event=None, cfg: tg_exec_config | None = None, stream=None):
+    """pre_events / post_event: torch.cuda.Event objects (their hipEvent_t
+    handles are passed through)."""
+    handles = [ctypes.c_void_p(e.cuda_event) for e in pre_events]
+    arr = (ctypes.c_void_p * max(len(handles), 1))(*handles)
+    post = ctypes.c_void_p(post_event.cuda_event) if post_event is not None else None
+    _check(load().tg_graph_execute_after(g, ctypes.byref(cfg) if cfg is not None else None, _stream(stream),
+                                         arr if handles else None, len(handles), post), "tg_graph_execute_after")
 
 
 def tg_graph_wait(g):

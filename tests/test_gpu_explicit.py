@@ -186,3 +186,26 @@ def test_watchdog_path_then_recovery(gpu):
     assert ei.value.status == tg.TG_ETIMEOUT
     run(g)
     check_explicit(g, eg, oracle_explicit(eg))
+
+
+def test_external_pre_and_post_conditions(gpu):
+    # graph B may start only after graph A's post-condition event; B runs on
+    # another stream; both results stay bit-exact
+    import torch
+    ea = wl.pattern_graph("stencil", 64, 40, seed=1, n=256, rounds=50)
+    eb = wl.pattern_graph("fft", 64, 30, seed=2, n=128, rounds=5)
+    ga, gb = tg.graph_from_explicit(ea), tg.graph_from_explicit(eb)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a_done = torch.cuda.Event(enable_timing=True)
+    b_done = torch.cuda.Event(enable_timing=True)
+    gate = torch.cuda.Event(enable_timing=True)
+    gate.record(s1)
+    tg.tg_graph_execute_after(ga.handle, pre_events=[gate], post_event=a_done, stream=s1)
+    tg.tg_graph_execute_after(gb.handle, pre_events=[a_done], post_event=b_done, stream=s2)
+    b_done.synchronize()
+    assert a_done.query() and b_done.query()
+    assert gate.elapsed_time(a_done) > 0 and a_done.elapsed_time(b_done) > 0
+    tg.tg_graph_wait(ga.handle)
+    tg.tg_graph_wait(gb.handle)
+    check_explicit(ga, ea, oracle_explicit(ea, want_payload=False))
+    check_explicit(gb, eb, oracle_explicit(eb, want_payload=False))
