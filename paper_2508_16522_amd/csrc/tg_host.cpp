@@ -103,6 +103,16 @@ struct DevBuf {
   T* as() const { return (T*)p; }
 };
 
+// Host-to-device copies and memsets here run on the NULL stream; for
+// pageable host memory a copy may still be in flight when hipMemcpy returns,
+// and the NULL stream is not ordered with the non-blocking streams kernels
+// may be launched on.  Every function that prepares device data for a launch
+// therefore ends with this fence.
+tg_status null_stream_fence() {
+  HIPCHK(hipStreamSynchronize(nullptr));
+  return TG_OK;
+}
+
 template <class T>
 tg_status upload(DevBuf& d, const std::vector<T>& h) {
   tg_status s = d.alloc(h.size() * sizeof(T));
@@ -205,6 +215,7 @@ struct tg_graph_s {
   tg_exec_config tuned{};
   // results kept on the host after the device buffers were released
   bool released = false;
+  uint64_t dev_gen = 0;  // bumped whenever the device buffers are (re)allocated
   std::vector<uint32_t> host_digest;
   hipStream_t last_stream = nullptr;
   // kernel-time ring: events around the executor kernel of recent launches
@@ -219,6 +230,7 @@ struct tg_graph_s {
 
 struct tg_batch_s {
   std::vector<tg_graph> graphs;
+  std::vector<uint64_t> gens;  // device-buffer generation of each graph at layout time
   std::unique_ptr<Layout> lay;
   bool inflight = false;
   hipStream_t last_stream = nullptr;
@@ -470,6 +482,7 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   P.window = cfg.window;
   P.spin_limit = cfg.spin_limit;
   P.watchdog_ticks = (uint64_t)cfg.watchdog_ms * 100000ull;
+  if ((s = null_stream_fence()) != TG_OK) return s;
   out = std::move(L);
   return TG_OK;
 }
@@ -605,6 +618,8 @@ tg_status check_abort(Layout* L) {
     const uint32_t zero[2] = {0, 0};
     HIPCHK(hipMemcpy(&L->ctrl.as<tg::Ctrl>()->sticky, zero, 4, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(&L->ctrl.as<tg::Ctrl>()->abort, zero, 4, hipMemcpyHostToDevice));
+    tg_status s = null_stream_fence();
+    if (s != TG_OK) return s;
   }
   if (c.abort)
     return fail(TG_ETIMEOUT,
@@ -667,8 +682,12 @@ tg_status ensure_device(tg_graph g) {
   const uint32_t N = g->N();
   tg_status s;
   g->released = false;
+  if ((g->mode == TG_EXPLICIT && !g->payload.p) || (g->mode == TG_IMPLICIT && !g->data.p) || !g->digest.p) g->dev_gen++;
   if (g->mode == TG_EXPLICIT && !g->payload.p) {
     if ((s = g->payload.alloc((size_t)N * g->n * 4)) != TG_OK) return s;
+  }
+  if (g->mode == TG_IMPLICIT && !g->data.p) {
+    if ((s = g->data.alloc((size_t)g->space * 4)) != TG_OK) return s;
   }
   if (!g->digest.p) {
     if ((s = g->digest.alloc((size_t)N * 4)) != TG_OK) return s;
@@ -682,7 +701,7 @@ tg_status ensure_device(tg_graph g) {
       HIPCHK(hipEventCreate(&g->rk0[i]));
       HIPCHK(hipEventCreate(&g->rk1[i]));
     }
-  return TG_OK;
+  return null_stream_fence();
 }
 
 }  // namespace
@@ -725,8 +744,6 @@ static tg_status tg_finalize_implicit(tg_graph g) {
     for (uint64_t x = g->dpred_ptr[k]; x < g->dpred_ptr[k + 1]; ++x) lv = std::max(lv, g->level[g->dpred[x]] + 1);
     g->level[k] = lv;
   }
-  tg_status s;
-  if ((s = g->data.alloc((size_t)g->space * 4)) != TG_OK) return s;
   return TG_OK;
 }
 
@@ -959,6 +976,7 @@ tg_status tg_graph_read_data(tg_graph g, uint32_t* host_out, uint64_t lo, uint64
   if (g->mode != TG_IMPLICIT) return fail(TG_EINVAL, "the shared array exists in implicit mode only");
   if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
   if (lo > hi || hi > g->space) return fail(TG_EINVAL, "range outside the index space");
+  if (!g->data.p) return fail(TG_ESTATE, "the array is not on the device (never executed, or released)");
   tg_status s = graph_wait(g);
   if (s != TG_OK) return s;
   if (hi > lo) HIPCHK(hipMemcpy(host_out, g->data.as<uint32_t>() + lo, (hi - lo) * 4, hipMemcpyDeviceToHost));
@@ -1032,7 +1050,7 @@ tg_status tg_graph_set_rounds(tg_graph g, uint32_t uniform_rounds) {
     if (!L.rec_host.empty())
       HIPCHK(hipMemcpy(L.rec.p, L.rec_host.data(), L.rec_host.size() * sizeof(TaskRec), hipMemcpyHostToDevice));
   }
-  return TG_OK;
+  return null_stream_fence();
 }
 
 tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, double* best_ms) {
@@ -1115,6 +1133,7 @@ tg_status tg_batch_create(tg_batch* out, const tg_graph* graphs, uint32_t n, con
   b->graphs = gs;
   tg_status s = build_layout(gs, cfg, b->lay);
   if (s != TG_OK) return s;
+  for (auto g : gs) b->gens.push_back(g->dev_gen);
   HIPCHK(hipEventCreate(&b->ev0));
   HIPCHK(hipEventCreate(&b->ev1));
   for (uint32_t i = 0; i < tg_batch_s::kRing; ++i) {
@@ -1134,6 +1153,11 @@ tg_status tg_batch_execute(tg_batch b, void* stream) {
       tg_status s = graph_wait(g);
       if (s != TG_OK) return s;
     }
+  // the layout holds the graphs' device addresses: refuse to run if any
+  // graph's buffers were released or reallocated since
+  for (size_t i = 0; i < b->graphs.size(); ++i)
+    if (b->graphs[i]->dev_gen != b->gens[i] || b->graphs[i]->released)
+      return fail(TG_ESTATE, "graph %zu of the batch lost its device buffers; create the batch again", i);
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipEventRecord(b->ev0, st));
   const uint32_t slot = (uint32_t)(b->launches % tg_batch_s::kRing);
@@ -1187,7 +1211,7 @@ tg_status tg_batch_set_rounds(tg_batch b, uint32_t uniform_rounds) {
   for (auto& r : L.rec_host) r.rounds = uniform_rounds;
   if (!L.rec_host.empty())
     HIPCHK(hipMemcpy(L.rec.p, L.rec_host.data(), L.rec_host.size() * sizeof(TaskRec), hipMemcpyHostToDevice));
-  return TG_OK;
+  return null_stream_fence();
 }
 
 tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks) {
@@ -1253,6 +1277,8 @@ tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, dou
   }
   b->lay.reset();
   if ((s = build_layout(b->graphs, best_c, b->lay)) != TG_OK) return s;
+  b->gens.clear();
+  for (auto g : b->graphs) b->gens.push_back(g->dev_gen);
   if ((s = tg_batch_info(b, best, nullptr)) != TG_OK) return s;
   if (best_ms) *best_ms = best_t;
   return TG_OK;

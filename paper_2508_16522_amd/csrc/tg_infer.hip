@@ -377,7 +377,10 @@ hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr_p, const void* r
     }
   hipStream_t st;
   hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess) {
+    err = "hipStreamCreateWithFlags (an earlier launch may have failed)";
+    return e;
+  }
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
@@ -399,8 +402,10 @@ hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr_p, const void* r
   ICHK(hipMalloc(&d_bptr, (nbuckets + 1) * 8));
   ICHK(hipMalloc(&d_rcnt, (size_t)N * 4));
   ICHK(hipMalloc(&d_row, ((size_t)N + 1) * 8));
-  ICHK(hipMemcpy(d_iv, iv.data(), iv.size() * sizeof(IvDev), hipMemcpyHostToDevice));
-  ICHK(hipMemcpy(d_req, req_ptr.data(), req_ptr.size() * 8, hipMemcpyHostToDevice));
+  // uploads are ordered on the inference stream itself (the host vectors
+  // outlive the final stream synchronisation)
+  ICHK(hipMemcpyAsync(d_iv, iv.data(), iv.size() * sizeof(IvDev), hipMemcpyHostToDevice, st));
+  ICHK(hipMemcpyAsync(d_req, req_ptr.data(), req_ptr.size() * 8, hipMemcpyHostToDevice, st));
   ICHK(hipEventRecord(e0, st));
   ICHK(hipMemsetAsync(d_bcnt, 0, nbuckets * 4, st));
   if (M32) {

@@ -264,10 +264,18 @@ def tg_graph_execute(g, cfg: tg_exec_config | None = None, stream=None):
 
 def tg_graph_execute_after(g, pre_events=(), post_event=None, cfg: tg_exec_config | None = None, stream=None):
     """pre_events / post_event: torch.cuda.Event objects (their hipEvent_t
-    handles are passed through)."""
-    handles = [ctypes.c_void_p(e.cuda_event) for e in pre_events]
+    handles are passed through).  PyTorch creates an event's HIP handle at its
+    first record: a pre-condition never recorded has nothing to wait for and
+    is skipped; a post-condition is recorded once on the launch stream first
+    so that it has a handle (the library records it again after the graph)."""
+    handles = [ctypes.c_void_p(e.cuda_event) for e in pre_events if e.cuda_event]
     arr = (ctypes.c_void_p * max(len(handles), 1))(*handles)
-    post = ctypes.c_void_p(post_event.cuda_event) if post_event is not None else None
+    post = None
+    if post_event is not None:
+        if not post_event.cuda_event:
+            import torch
+            post_event.record(stream if stream is not None else torch.cuda.current_stream())
+        post = ctypes.c_void_p(post_event.cuda_event)
     _check(load().tg_graph_execute_after(g, ctypes.byref(cfg) if cfg is not None else None, _stream(stream),
                                          arr if handles else None, len(handles), post), "tg_graph_execute_after")
 
