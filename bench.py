@@ -159,7 +159,8 @@ def main():
     if not args.no_tune:
         bcfg, bms = tg.tg_batch_autotune(batch, reps=2)
         log(f"autotune batch: {bcfg} {bms:.3f} ms")
-    bcfg, _ = tg.tg_batch_info(batch)
+    bcfg, _, btimes = tg.tg_batch_info(batch, with_times=True)
+    log(f"batch layout: plan {btimes['plan_ms']:.0f} ms, build {btimes['build_ms']:.0f} ms")
 
     def step():
         tg.tg_batch_execute(batch, stream)
@@ -210,9 +211,15 @@ def main():
     if not args.no_sweep:
         pi = probes["mix_word_rounds_per_s"]
         rows = []
-        slots = bcfg["workers"]
         for R in SWEEP_ROUNDS:
             tg.tg_batch_set_rounds(batch, R)
+            # the launch shape is re-tuned for each task size up to 256 rounds;
+            # larger sizes keep the shape tuned at 256
+            if not args.no_tune and 0 < R <= 256:
+                tcfg, tms = tg.tg_batch_autotune(batch, reps=1)
+                log(f"sweep R={R}: autotuned {tcfg} {tms:.3f} ms")
+            rcfg, _ = tg.tg_batch_info(batch)
+            slots = rcfg["workers"]
             step()  # warm
             reps = 2 if R >= 1024 else 3
             for _ in range(reps):
@@ -222,11 +229,12 @@ def main():
             eff = (U / (ms * 1e-3)) / pi if R else 0.0
             # granularity: run time per task per concurrent worker (Task Bench METG x-axis)
             gran_us = ms * 1e3 * slots / tasks_per_step
-            rows.append({"rounds": R, "ms": ms, "efficiency": eff, "granularity_us": gran_us})
+            rows.append({"rounds": R, "ms": ms, "efficiency": eff, "granularity_us": gran_us,
+                         "launch": {k: rcfg[k] for k in ("mapping", "workers", "wg_waves", "notify", "schedule")}})
             log(f"sweep R={R}: {ms:.3f} ms eff {eff:.3f} gran {gran_us:.2f} us")
         tg.tg_batch_set_rounds(batch, 0)
         m = metg50([r["granularity_us"] for r in rows if r["rounds"]], [r["efficiency"] for r in rows if r["rounds"]])
-        sweep = {"rows": rows, "metg50_us": m, "peak_word_rounds_per_s": pi, "workers": slots}
+        sweep = {"rows": rows, "metg50_us": m, "peak_word_rounds_per_s": pi}
 
     # ------------------------------------------------------- comparators
     comps = None
@@ -303,6 +311,7 @@ def main():
         "comparators": comps,
         "probes": probes,
         "compile_ms": dict(zip(wl.PATTERNS, compile_ms)),
+        "batch_layout_ms": btimes,
     }
     tg.tg_batch_destroy(batch)
     print(json.dumps(out), flush=True)

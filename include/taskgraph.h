@@ -101,7 +101,12 @@ typedef struct {
  *                  owning worker's doorbell, and idle workers poll only their
  *                  doorbell (fewer polls, one more hop per task).
  *   idle_sleep   : back-off of an idle worker, in units of 128 cycles
- *                  (1..64, default 2). */
+ *                  (1..64, default 2).
+ *   schedule     : how tasks are partitioned over the workers' lists
+ *                  (Algorithm 1, Compile): TG_SCHED_LIST (default) simulates
+ *                  the workers with estimated task costs and starts ready
+ *                  tasks longest-remaining-path first; TG_SCHED_LEVEL sorts
+ *                  by dependence level and deals round-robin. */
 typedef struct {
   uint32_t mapping;
   uint32_t workers;
@@ -112,9 +117,11 @@ typedef struct {
   uint32_t diag;
   uint32_t notify;
   uint32_t idle_sleep;
+  uint32_t schedule;
 } tg_exec_config;
 
 enum { TG_MAP_WAVE = 1, TG_MAP_WORKGROUP = 2 };
+enum { TG_SCHED_LIST = 1, TG_SCHED_LEVEL = 2 };
 
 /* ------------------------------------------------------------- status */
 const char* tg_status_str(tg_status s);
@@ -229,8 +236,11 @@ tg_status tg_batch_time_ms(tg_batch b, double* ms);
 tg_status tg_batch_kernel_times(tg_batch b, double* ms_out, uint32_t n, uint32_t* got);
 /* Give every task of every graph of the batch `uniform_rounds` mix rounds. */
 tg_status tg_batch_set_rounds(tg_batch b, uint32_t uniform_rounds);
-/* Launch shape of the batch (workers = the actual count) and its task count. */
-tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks);
+/* Launch shape of the batch (workers = the actual count), its task count,
+ * and the host time spent building its current layout: plan_ms for the
+ * schedule and task records, build_ms for all of it including the upload
+ * (Algorithm 1, Compile).  Any output pointer may be NULL. */
+tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks, double* plan_ms, double* build_ms);
 /* Autotuner for a batch (as tg_graph_autotune); keeps the fastest layout. */
 tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, double* best_ms);
 tg_status tg_batch_destroy(tg_batch b);
@@ -247,13 +257,19 @@ tg_status tg_exec_occupancy(uint32_t mapping, uint32_t wg_waves, uint32_t* block
 /* Workers of the graph's last launch and, for a diagnostic launch (diag=1),
  * how many of them started. */
 tg_status tg_graph_exec_info(tg_graph g, uint32_t* workers, uint32_t* started);
-/* Host-only model of a launch (no GPU needed): compiles the worker layout
- * for nworkers workers and steps the same ready-window loop as the kernels
- * in a seeded order.  order (#tasks entries) receives the execution order by
- * event, *executed the number of tasks run; TG_ETIMEOUT if the schedule
- * would deadlock. */
-tg_status tg_graph_emulate_schedule(tg_graph g, uint32_t nworkers, uint32_t window, uint64_t seed, uint32_t* order,
-                                    uint64_t* executed);
+/* Host-only model of a launch of graphs[0..ngraphs) together (one graph
+ * alone, or a batch), no GPU needed: compiles the worker layout for nworkers
+ * workers with the given schedule (0 = default) and steps the same
+ * ready-window loop as the kernels in a seeded order.  order (total #tasks
+ * entries) receives the execution order as (graph index << 32 | event),
+ * *executed the number of tasks run; TG_ETIMEOUT if the layout would
+ * deadlock.  If makespan and bound are not NULL, the layout is also run in a
+ * timed model (each task takes the cost the scheduler estimates for it):
+ * *makespan is its finishing time and *bound the lower bound
+ * max(longest path, total cost / workers), both in the same cost units. */
+tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t nworkers, uint32_t window,
+                              uint32_t schedule, uint64_t seed, uint64_t* order, uint64_t* executed, uint64_t* makespan,
+                              uint64_t* bound);
 /* After a diagnostic launch (diag=1) of the graph on its own: per task (by
  * event) the pending in-edge counter, the number of times it ran, its worker
  * and its entry in that worker's list; optionally (wprog != NULL, nworkers =

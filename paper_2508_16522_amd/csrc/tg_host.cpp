@@ -3,10 +3,13 @@
 //
 // Compilation follows Algorithm 1 (Compile): the graph's vertices are
 // partitioned over workers, every vertex gets a counter of pending in-edges
-// and an O(1) list of out-edges.  The partition used here is a
-// dependence-level schedule: vertices are sorted by (level, graph, id) and
-// dealt round-robin to the workers, so every worker's list is topologically
-// ordered and consecutive list entries tend to be independent.
+// and an O(1) list of out-edges.  The partition is a static list schedule:
+// a simulation of the workers with estimated task costs assigns each ready
+// vertex, longest remaining path first, to the next free worker, and each
+// worker's list holds its vertices in simulated start order (a dependence-
+// level order dealt round-robin is kept as the alternative).  Either way
+// every list is topologically ordered, which is what makes the executor
+// deadlock-free for any ready-window length.
 #include "taskgraph.h"
 #include "tg_internal.h"
 
@@ -24,6 +27,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -147,7 +151,7 @@ tg_status device_info(DevInfo& di) {
 
 struct Config {
   uint32_t mapping = 1, workers = 0, window = 64, wg_waves = 4, watchdog_ms = 5000, spin_limit = 0, diag = 0;
-  uint32_t idle_sleep = 2, notify = 0;
+  uint32_t idle_sleep = 2, notify = 0, schedule = TG_SCHED_LIST;
 };
 
 Config resolve(const tg_exec_config* c) {
@@ -162,6 +166,7 @@ Config resolve(const tg_exec_config* c) {
     r.diag = c->diag & 1u;
     r.notify = c->notify & 1u;
     if (c->idle_sleep) r.idle_sleep = c->idle_sleep;
+    if (c->schedule) r.schedule = c->schedule;
   }
   return r;
 }
@@ -171,6 +176,7 @@ tg_status check_config(const Config& c) {
   if (c.window < 1 || c.window > 64) return fail(TG_EINVAL, "window must be in [1, 64]");
   if (c.idle_sleep < 1 || c.idle_sleep > 64) return fail(TG_EINVAL, "idle_sleep must be in [1, 64]");
   if (c.wg_waves < 1 || c.wg_waves > 16) return fail(TG_EINVAL, "wg_waves must be in [1, 16]");
+  if (c.schedule != TG_SCHED_LIST && c.schedule != TG_SCHED_LEVEL) return fail(TG_EINVAL, "schedule must be 1 or 2");
   return TG_OK;
 }
 
@@ -185,6 +191,7 @@ struct Layout {
   std::vector<std::vector<uint32_t>> pos_of;  // per graph: task id -> position
   std::vector<TaskRec> rec_host;               // host copy (rounds can be re-set)
   ExecParams params{};
+  double plan_ms = 0, build_ms = 0;  // host time: schedule + records, whole layout incl. upload
 };
 
 struct tg_graph_s {
@@ -228,10 +235,15 @@ struct tg_graph_s {
   uint32_t N() const { return mode == TG_EXPLICIT ? (uint32_t)(pred_ptr.size() - 1) : (uint32_t)(req_ptr.size() - 1); }
 };
 
+namespace {
+struct PlanCache;
+}  // namespace
+
 struct tg_batch_s {
   std::vector<tg_graph> graphs;
   std::vector<uint64_t> gens;  // device-buffer generation of each graph at layout time
   std::unique_ptr<Layout> lay;
+  std::shared_ptr<PlanCache> plans;
   bool inflight = false;
   hipStream_t last_stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -312,52 +324,215 @@ struct HostLayout {
   std::vector<std::vector<uint32_t>> pos_of;
 };
 
-// Schedule a set of finalised graphs onto nw workers: sort all tasks by
-// (dependence level, graph, id), deal the sorted sequence round-robin to the
-// workers, and store each worker's tasks contiguously in that order.
-tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, HostLayout& H) {
-  uint64_t ntot = 0, npred_tot = 0, nsucc_tot = 0, nreq_tot = 0;
+// Estimated cost of a task, in lane-steps of one wavefront: a fixed latency
+// term (counter poll, payload hand-off, edge signals) plus the words it
+// touches times the mix rounds.  Only the schedule uses it; it is never 0.
+uint64_t task_cost(const tg_graph g, uint32_t v) {
+  constexpr uint64_t kLatency = 64;
+  const uint64_t R = g->rounds[v];
+  if (g->mode == TG_EXPLICIT) {
+    const uint64_t npred = g->dpred_ptr[v + 1] - g->dpred_ptr[v];
+    return kLatency + (uint64_t)g->n / 64 * (R + npred + 1);
+  }
+  uint64_t ro = 0, rw = 0;
+  for (uint64_t i = g->req_ptr[v]; i < g->req_ptr[v + 1]; ++i) {
+    const tg_region_req& q = g->reqs[i];
+    const uint64_t len = q.hi > q.lo ? q.hi - q.lo : 0;
+    (q.priv == TG_RW ? rw : ro) += len;
+  }
+  return kLatency + (ro + rw * (R + 2)) / 64;
+}
+
+// Dependence-level order: all tasks sorted by (level, graph, id) and dealt
+// round-robin, so worker w takes entries w, w + nw, ...
+void schedule_levels(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw, std::vector<uint32_t>& wlen,
+                     std::vector<uint64_t>& seq) {
   uint32_t maxlevel = 0;
+  for (auto g : gs)
+    for (uint32_t lv : g->level) maxlevel = std::max(maxlevel, lv);
+  std::vector<uint64_t> lstart((size_t)maxlevel + 2, 0);
+  for (auto g : gs)
+    for (uint32_t lv : g->level) lstart[lv + 1]++;
+  for (size_t i = 1; i < lstart.size(); ++i) lstart[i] += lstart[i - 1];
+  std::vector<uint64_t> sorted(N);
+  for (uint32_t gi = 0; gi < gs.size(); ++gi) {
+    const auto& lv = gs[gi]->level;
+    for (uint32_t v = 0; v < lv.size(); ++v) sorted[lstart[lv[v]]++] = ((uint64_t)gi << 32) | v;
+  }
+  wlen.assign(nw, 0);
+  for (uint32_t w = 0; w < nw; ++w) wlen[w] = (N > w) ? (N - w + nw - 1) / nw : 0;
+  // seq lists worker 0's tasks, then worker 1's, ...
+  std::vector<uint64_t> off(nw + 1, 0);
+  for (uint32_t w = 0; w < nw; ++w) off[w + 1] = off[w] + wlen[w];
+  seq.assign(N, 0);
+  for (uint64_t si = 0; si < N; ++si) seq[off[si % nw] + si / nw] = sorted[si];
+}
+
+// List schedule: simulate nw identical workers.  Whenever workers are free,
+// the ready tasks with the longest remaining path (sum of estimated costs to
+// a sink) start on them, in the order the workers became free; a task's
+// successors become ready when its simulated run ends.  Ready tasks are kept
+// in a bucket queue over the quantised path length (FIFO inside a bucket),
+// busy workers in a heap of finish times.  Each worker's list is its tasks in
+// simulated start order; since costs are positive, a task starts strictly
+// after each of its predecessors, so the lists are topologically ordered.
+tg_status schedule_list(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw, std::vector<uint32_t>& wlen,
+                        std::vector<uint64_t>& seq) {
+  const uint32_t G = (uint32_t)gs.size();
+  std::vector<uint32_t> gbase(G + 1, 0);
+  for (uint32_t gi = 0; gi < G; ++gi) gbase[gi + 1] = gbase[gi] + gs[gi]->N();
+  std::vector<uint32_t> gof(N);
+  for (uint32_t gi = 0; gi < G; ++gi)
+    for (uint32_t v = 0; v < gs[gi]->N(); ++v) gof[gbase[gi] + v] = gi;
+  // costs and longest remaining paths (ids are a topological order)
+  std::vector<uint64_t> cost(N), path(N);
+  uint64_t pmax = 1;
+  for (uint32_t gi = 0; gi < G; ++gi) {
+    const tg_graph g = gs[gi];
+    for (uint32_t v = g->N(); v-- > 0;) {
+      const uint32_t x = gbase[gi] + v;
+      cost[x] = task_cost(g, v);
+      uint64_t m = 0;
+      for (uint64_t j = g->succ_ptr[v]; j < g->succ_ptr[v + 1]; ++j) m = std::max(m, path[gbase[gi] + g->succ[j]]);
+      path[x] = cost[x] + m;
+      pmax = std::max(pmax, path[x]);
+    }
+  }
+  // bucket queue: higher bucket = longer path
+  constexpr uint32_t kBuckets = 1u << 16;
+  std::vector<uint32_t> head(kBuckets, 0xFFFFFFFFu), tail(kBuckets, 0xFFFFFFFFu), next(N, 0xFFFFFFFFu);
+  std::vector<uint64_t> nonempty(kBuckets / 64, 0);
+  auto bucket_of = [&](uint32_t x) {
+    return (uint32_t)(((unsigned __int128)path[x] * (kBuckets - 1)) / pmax);
+  };
+  auto push = [&](uint32_t x) {
+    const uint32_t b = bucket_of(x);
+    if (head[b] == 0xFFFFFFFFu) {
+      head[b] = x;
+      nonempty[b >> 6] |= 1ull << (b & 63);
+    } else {
+      next[tail[b]] = x;
+    }
+    tail[b] = x;
+    next[x] = 0xFFFFFFFFu;
+  };
+  int64_t top_word = kBuckets / 64 - 1;
+  auto pop = [&]() -> uint32_t {  // highest non-empty bucket, or none
+    for (int64_t wi = top_word; wi >= 0; --wi) {
+      if (!nonempty[wi]) continue;
+      top_word = wi;
+      const uint32_t b = (uint32_t)wi * 64 + (63 - __builtin_clzll(nonempty[wi]));
+      const uint32_t x = head[b];
+      head[b] = next[x];
+      if (head[b] == 0xFFFFFFFFu) {
+        tail[b] = 0xFFFFFFFFu;
+        nonempty[wi] &= ~(1ull << (b & 63));
+      }
+      return x;
+    }
+    top_word = 0;
+    return 0xFFFFFFFFu;
+  };
+  std::vector<uint32_t> pend(N);
+  for (uint32_t gi = 0; gi < G; ++gi) {
+    const tg_graph g = gs[gi];
+    for (uint32_t v = 0; v < g->N(); ++v) {
+      pend[gbase[gi] + v] = (uint32_t)(g->dpred_ptr[v + 1] - g->dpred_ptr[v]);
+      if (pend[gbase[gi] + v] == 0) push(gbase[gi] + v);
+    }
+  }
+  auto raise_top = [&](uint32_t x) { top_word = std::max<int64_t>(top_word, bucket_of(x) >> 6); };
+  // free workers in the order they became free; busy ones by finish time
+  std::vector<uint32_t> freeq(nw);
+  for (uint32_t w = 0; w < nw; ++w) freeq[w] = w;
+  size_t fq_head = 0;
+  typedef std::pair<uint64_t, uint32_t> Busy;  // (finish time, worker)
+  std::priority_queue<Busy, std::vector<Busy>, std::greater<Busy>> busy;
+  std::vector<uint32_t> running(nw, 0xFFFFFFFFu);
+  std::vector<uint32_t> owner(N), order_in(N);
+  wlen.assign(nw, 0);
+  uint64_t now = 0, started = 0;
+  while (started < N) {
+    while (fq_head < freeq.size()) {
+      const uint32_t x = pop();
+      if (x == 0xFFFFFFFFu) break;
+      const uint32_t w = freeq[fq_head++];
+      owner[x] = w;
+      order_in[x] = wlen[w]++;
+      running[w] = x;
+      busy.push(Busy(now + cost[x], w));
+      ++started;
+    }
+    if (fq_head > nw) {  // drop the consumed prefix of the free queue
+      freeq.erase(freeq.begin(), freeq.begin() + (ptrdiff_t)fq_head);
+      fq_head = 0;
+    }
+    if (busy.empty()) break;  // nothing runs and nothing is ready: a cycle
+    now = busy.top().first;
+    while (!busy.empty() && busy.top().first == now) {
+      const uint32_t w = busy.top().second;
+      busy.pop();
+      const uint32_t x = running[w];
+      running[w] = 0xFFFFFFFFu;
+      freeq.push_back(w);
+      const uint32_t gi = gof[x];
+      const tg_graph g = gs[gi];
+      const uint32_t v = x - gbase[gi];
+      for (uint64_t j = g->succ_ptr[v]; j < g->succ_ptr[v + 1]; ++j) {
+        const uint32_t y = gbase[gi] + g->succ[j];
+        if (--pend[y] == 0) {
+          push(y);
+          raise_top(y);
+        }
+      }
+    }
+  }
+  if (started < N) return fail(TG_EINVAL, "dependence cycle: %llu of %u tasks schedulable",
+                               (unsigned long long)started, N);
+  std::vector<uint64_t> off(nw + 1, 0);
+  for (uint32_t w = 0; w < nw; ++w) off[w + 1] = off[w] + wlen[w];
+  seq.assign(N, 0);
+  for (uint32_t x = 0; x < N; ++x) {
+    const uint32_t gi = gof[x];
+    seq[off[owner[x]] + order_in[x]] = ((uint64_t)gi << 32) | (x - gbase[gi]);
+  }
+  return TG_OK;
+}
+
+// Schedule a set of finalised graphs onto nw workers (list schedule or
+// dependence-level order) and store each worker's tasks contiguously in the
+// order it is to run them.
+tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t schedule, HostLayout& H) {
+  uint64_t ntot = 0, npred_tot = 0, nsucc_tot = 0, nreq_tot = 0;
   for (auto g : gs) {
     ntot += g->N();
     npred_tot += g->mode == TG_EXPLICIT ? g->dpred.size() : 0;
     nsucc_tot += g->succ.size();
     nreq_tot += g->mode == TG_IMPLICIT ? g->reqs.size() : 0;
-    for (uint32_t lv : g->level) maxlevel = std::max(maxlevel, lv);
   }
   if (ntot >= 0xFFFFFFFFull || npred_tot >= 0xFFFFFFFFull || nsucc_tot >= 0xFFFFFFFFull || nreq_tot >= 0xFFFFFFFFull)
     return fail(TG_EINVAL, "layout too large: %llu tasks, %llu edges", (unsigned long long)ntot,
                 (unsigned long long)nsucc_tot);
+  if (schedule != TG_SCHED_LIST && schedule != TG_SCHED_LEVEL) return fail(TG_EINVAL, "schedule must be 1 or 2");
   const uint32_t N = (uint32_t)ntot;
   uint64_t nw = nw_req;
   if (nw > N) nw = N ? N : 1;
   if (nw == 0) nw = 1;
   H.N = N;
   H.nw = (uint32_t)nw;
-  // schedule: stable counting sort by level; ties by (graph, id)
-  std::vector<uint64_t> lstart((size_t)maxlevel + 2, 0);
-  for (auto g : gs)
-    for (uint32_t lv : g->level) lstart[lv + 1]++;
-  for (size_t i = 1; i < lstart.size(); ++i) lstart[i] += lstart[i - 1];
-  std::vector<uint64_t> sched(N);  // (graph << 32) | id
-  for (uint32_t gi = 0; gi < gs.size(); ++gi) {
-    const auto& lv = gs[gi]->level;
-    for (uint32_t v = 0; v < lv.size(); ++v) sched[lstart[lv[v]]++] = ((uint64_t)gi << 32) | v;
+  std::vector<uint32_t> wlen;
+  std::vector<uint64_t> at_pos;  // (graph << 32) | id, by position
+  if (schedule == TG_SCHED_LIST) {
+    tg_status st = schedule_list(gs, N, (uint32_t)nw, wlen, at_pos);
+    if (st != TG_OK) return st;
+  } else {
+    schedule_levels(gs, N, (uint32_t)nw, wlen, at_pos);
   }
-  // worker w takes schedule entries w, w + nw, ...; its positions are contiguous
   H.wbase.assign((size_t)nw + 1, 0);
-  for (uint64_t w = 0; w < nw; ++w) H.wbase[w + 1] = H.wbase[w] + (uint32_t)((N > w) ? (N - w + nw - 1) / nw : 0);
+  for (uint64_t w = 0; w < nw; ++w) H.wbase[w + 1] = H.wbase[w] + wlen[w];
   H.pos_of.assign(gs.size(), {});
   for (uint32_t gi = 0; gi < gs.size(); ++gi) H.pos_of[gi].assign(gs[gi]->N(), 0);
-  std::vector<uint64_t> at_pos(N);
-  for (uint64_t si = 0; si < N; ++si) {
-    const uint64_t w = si % nw, j = si / nw;
-    const uint32_t pos = H.wbase[w] + (uint32_t)j;
-    at_pos[pos] = sched[si];
-    H.pos_of[sched[si] >> 32][(uint32_t)sched[si]] = pos;
-  }
-  sched.clear();
-  sched.shrink_to_fit();
+  for (uint32_t pos = 0; pos < N; ++pos) H.pos_of[at_pos[pos] >> 32][(uint32_t)at_pos[pos]] = pos;
   // records and edge arrays in position order
   H.rec.assign(N, TaskRec());
   H.pred_addr.clear();
@@ -427,7 +602,19 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, HostLayo
 tg_status ensure_device(tg_graph g);
 
 // Schedule and upload the layout of a set of finalised graphs.
-tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::unique_ptr<Layout>& out) {
+// Host layouts already planned for a set of graphs, by (workers, schedule):
+// launch shapes with the same worker count share one plan, so an autotuner
+// pass re-plans only for new worker counts.  Records are refreshed from the
+// graphs' current mix rounds whenever a plan is reused.
+struct PlanCache {
+  static constexpr uint64_t kMaxTasks = 1ull << 24;  // larger layouts are not kept
+  static constexpr size_t kMaxEntries = 6;
+  std::map<std::pair<uint32_t, uint32_t>, std::shared_ptr<const HostLayout>> m;
+};
+
+tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::unique_ptr<Layout>& out,
+                       PlanCache* cache = nullptr) {
+  const auto t_build = std::chrono::steady_clock::now();
   tg_status s = check_config(cfg);
   if (s != TG_OK) return s;
   for (auto g : gs)
@@ -438,7 +625,18 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   uint64_t nw = cfg.workers ? cfg.workers : cap_workers;
   if (nw > cap_workers) nw = cap_workers;  // every worker must be co-resident
   HostLayout H;
-  if ((s = plan_layout(gs, nw, H)) != TG_OK) return s;
+  const auto t_plan = std::chrono::steady_clock::now();
+  const std::pair<uint32_t, uint32_t> key((uint32_t)nw, cfg.schedule);
+  auto hit = cache ? cache->m.find(key) : decltype(cache->m.end()){};
+  if (cache && hit != cache->m.end()) {
+    H = *hit->second;
+    for (auto& r : H.rec) r.rounds = gs[r.graph]->rounds[r.tid];
+  } else {
+    if ((s = plan_layout(gs, nw, cfg.schedule, H)) != TG_OK) return s;
+    if (cache && H.N <= PlanCache::kMaxTasks && cache->m.size() < PlanCache::kMaxEntries)
+      cache->m[key] = std::make_shared<const HostLayout>(H);
+  }
+  const double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_plan).count();
   auto L = std::make_unique<Layout>();
   L->cfg = cfg;
   L->npos = H.N;
@@ -483,6 +681,8 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   P.spin_limit = cfg.spin_limit;
   P.watchdog_ticks = (uint64_t)cfg.watchdog_ms * 100000ull;
   if ((s = null_stream_fence()) != TG_OK) return s;
+  L->plan_ms = plan_ms;
+  L->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_build).count();
   out = std::move(L);
   return TG_OK;
 }
@@ -566,8 +766,98 @@ tg_status emulate_layout(const HostLayout& H, uint32_t window, uint64_t seed, ui
   return ex == N ? TG_OK : fail(TG_EINVAL, "executed %llu of %u tasks", (unsigned long long)ex, N);
 }
 
+// Timed model of a layout: every worker runs the kernels' ready-window rule
+// (first ready entry of its window, window slid past the finished prefix)
+// with each task taking its estimated cost; an idle worker wakes when one of
+// its tasks becomes ready.  Returns the simulated makespan in cost units and
+// the lower bound max(longest path, total cost / workers).
+void timed_makespan(const std::vector<tg_graph>& gs, const HostLayout& H, uint32_t window, uint64_t* makespan,
+                    uint64_t* bound) {
+  const uint32_t N = H.N, nw = H.nw;
+  std::vector<uint64_t> cost(N);
+  std::vector<uint32_t> owner(N);
+  uint64_t total = 0;
+  for (uint32_t gi = 0; gi < gs.size(); ++gi)
+    for (uint32_t v = 0; v < gs[gi]->N(); ++v) {
+      const uint32_t pos = H.pos_of[gi][v];
+      cost[pos] = task_cost(gs[gi], v);
+      total += cost[pos];
+    }
+  for (uint32_t w = 0; w < nw; ++w)
+    for (uint32_t p = H.wbase[w]; p < H.wbase[w + 1]; ++p) owner[p] = w;
+  // longest path (positions' records hold the successors)
+  std::vector<uint64_t> est(N, 0);
+  uint64_t cp = 0;
+  {
+    std::vector<uint32_t> cnt(H.indeg), q;
+    for (uint32_t p = 0; p < N; ++p)
+      if (!cnt[p]) q.push_back(p);
+    for (size_t i = 0; i < q.size(); ++i) {
+      const uint32_t p = q[i];
+      const uint64_t f = est[p] + cost[p];
+      cp = std::max(cp, f);
+      const TaskRec& r = H.rec[p];
+      for (uint32_t j = 0; j < r.nsucc; ++j) {
+        const uint32_t d = H.succ_pos[r.succ_beg + j];
+        est[d] = std::max(est[d], f);
+        if (--cnt[d] == 0) q.push_back(d);
+      }
+    }
+  }
+  *bound = std::max(cp, (total + nw - 1) / nw);
+  struct W {
+    uint32_t h = 0;
+    uint64_t done = 0;
+    bool idle = false;
+  };
+  std::vector<W> ws(nw);
+  std::vector<uint32_t> cnt(H.indeg);
+  typedef std::pair<uint64_t, uint64_t> Ev;  // (time, kind << 32 | id): kind 0 = finish(pos), 1 = wake(worker)
+  std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> evq;
+  for (uint32_t w = 0; w < nw; ++w) evq.push(Ev(0, (1ull << 32) | w));
+  uint64_t t_end = 0;
+  while (!evq.empty()) {
+    const Ev e = evq.top();
+    evq.pop();
+    const uint64_t t = e.first;
+    const uint32_t id = (uint32_t)e.second;
+    if ((e.second >> 32) == 0) {
+      t_end = std::max(t_end, t);
+      const TaskRec& r = H.rec[id];
+      for (uint32_t j = 0; j < r.nsucc; ++j) {
+        const uint32_t d = H.succ_pos[r.succ_beg + j];
+        if (--cnt[d] == 0 && ws[owner[d]].idle) {
+          ws[owner[d]].idle = false;
+          evq.push(Ev(t, (1ull << 32) | owner[d]));
+        }
+      }
+      evq.push(Ev(t, (1ull << 32) | owner[id]));  // the worker is free again
+      continue;
+    }
+    W& x = ws[id];
+    const uint32_t wb = H.wbase[id], wcnt = H.wbase[id + 1] - wb;
+    const uint32_t adv = (~x.done == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~x.done);
+    x.h += adv;
+    x.done = adv >= 64u ? 0ull : (x.done >> adv);
+    if (x.h >= wcnt) continue;
+    bool ran = false;
+    for (uint32_t lane = 0; lane < window && x.h + lane < wcnt; ++lane) {
+      if ((x.done >> lane) & 1ull) continue;
+      const uint32_t p = wb + x.h + lane;
+      if (cnt[p] != 0) continue;
+      x.done |= 1ull << lane;
+      cnt[p] = 0xFFFFFFFFu;  // taken
+      evq.push(Ev(t + cost[p], (uint64_t)p));
+      ran = true;
+      break;
+    }
+    if (!ran) x.idle = true;
+  }
+  *makespan = t_end;
+}
+
 bool same_layout(const Config& a, const Config& b) {
-  return a.mapping == b.mapping && a.workers == b.workers && a.wg_waves == b.wg_waves;
+  return a.mapping == b.mapping && a.workers == b.workers && a.wg_waves == b.wg_waves && a.schedule == b.schedule;
 }
 
 // Launch reset + persistent executor for a layout.
@@ -1080,6 +1370,8 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
   cand.push_back(mk(TG_MAP_WORKGROUP, rg2, 2, 0));
   cand.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
   if (rg4 / 2) cand.push_back(mk(TG_MAP_WORKGROUP, rg4 / 2, 4, 0));
+  cand.push_back(mk(TG_MAP_WAVE, rw, 0, 0));
+  cand.back().schedule = TG_SCHED_LEVEL;
   double best_t = 1e300;
   tg_exec_config best_c = cand[0];
   for (const auto& c : cand) {
@@ -1214,8 +1506,10 @@ tg_status tg_batch_set_rounds(tg_batch b, uint32_t uniform_rounds) {
   return null_stream_fence();
 }
 
-tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks) {
+tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks, double* plan_ms, double* build_ms) {
   if (!b) return fail(TG_EINVAL, "batch is NULL");
+  if (plan_ms) *plan_ms = b->lay->plan_ms;
+  if (build_ms) *build_ms = b->lay->build_ms;
   if (cfg) {
     memset(cfg, 0, sizeof(*cfg));
     const Config& c = b->lay->cfg;
@@ -1226,6 +1520,7 @@ tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks) {
     cfg->watchdog_ms = c.watchdog_ms;
     cfg->notify = c.notify;
     cfg->idle_sleep = c.idle_sleep;
+    cfg->schedule = c.schedule;
   }
   if (tasks) *tasks = b->lay->npos;
   return TG_OK;
@@ -1242,6 +1537,10 @@ tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, dou
   if ((s = resident_workers(TG_MAP_WAVE, 4, &rw)) != TG_OK) return s;
   if ((s = resident_workers(TG_MAP_WORKGROUP, 2, &rg2)) != TG_OK) return s;
   if ((s = resident_workers(TG_MAP_WORKGROUP, 4, &rg4)) != TG_OK) return s;
+  // plans hold the graphs' device addresses: drop them if any moved
+  bool moved = false;
+  for (size_t i = 0; i < b->graphs.size(); ++i) moved |= b->graphs[i]->dev_gen != b->gens[i];
+  if (!b->plans || moved) b->plans = std::make_shared<PlanCache>();
   std::vector<Config> cand;
   auto mk = [](uint32_t m, uint32_t w, uint32_t ww, uint32_t nt) {
     Config c;
@@ -1256,11 +1555,13 @@ tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, dou
   cand.push_back(mk(TG_MAP_WAVE, rw, 0, 1));
   cand.push_back(mk(TG_MAP_WORKGROUP, rg2, 2, 0));
   cand.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
+  cand.push_back(mk(TG_MAP_WAVE, rw, 0, 0));
+  cand.back().schedule = TG_SCHED_LEVEL;
   double best_t = 1e300;
   Config best_c = cand[0];
   for (const auto& c : cand) {
     b->lay.reset();
-    if ((s = build_layout(b->graphs, c, b->lay)) != TG_OK) return s;
+    if ((s = build_layout(b->graphs, c, b->lay, b->plans.get())) != TG_OK) return s;
     double tot = 0;
     for (uint32_t r = 0; r <= reps; ++r) {
       if ((s = tg_batch_execute(b, nullptr)) != TG_OK) return s;
@@ -1276,10 +1577,10 @@ tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, dou
     }
   }
   b->lay.reset();
-  if ((s = build_layout(b->graphs, best_c, b->lay)) != TG_OK) return s;
+  if ((s = build_layout(b->graphs, best_c, b->lay, b->plans.get())) != TG_OK) return s;
   b->gens.clear();
   for (auto g : b->graphs) b->gens.push_back(g->dev_gen);
-  if ((s = tg_batch_info(b, best, nullptr)) != TG_OK) return s;
+  if ((s = tg_batch_info(b, best, nullptr, nullptr, nullptr)) != TG_OK) return s;
   if (best_ms) *best_ms = best_t;
   return TG_OK;
 }
@@ -1361,21 +1662,27 @@ tg_status tg_graph_debug_state(tg_graph g, uint32_t* pending, uint32_t* execs, u
   return TG_OK;
 }
 
-tg_status tg_graph_emulate_schedule(tg_graph g, uint32_t nworkers, uint32_t window, uint64_t seed, uint32_t* order,
-                                    uint64_t* executed) {
-  if (!g || !order || !executed) return fail(TG_EINVAL, "NULL argument");
-  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t nworkers, uint32_t window,
+                              uint32_t schedule, uint64_t seed, uint64_t* order, uint64_t* executed, uint64_t* makespan,
+                              uint64_t* bound) {
+  if (!graphs || !ngraphs || !order || !executed) return fail(TG_EINVAL, "NULL argument");
   if (window < 1 || window > 64 || nworkers == 0) return fail(TG_EINVAL, "window in [1,64], nworkers >= 1");
+  std::vector<tg_graph> gs(graphs, graphs + ngraphs);
+  for (auto g : gs) {
+    if (!g) return fail(TG_EINVAL, "NULL graph");
+    if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  }
   HostLayout H;
-  std::vector<tg_graph> gs{g};
-  tg_status s = plan_layout(gs, nworkers, H);
+  tg_status s = plan_layout(gs, nworkers, schedule ? schedule : (uint32_t)TG_SCHED_LIST, H);
   if (s != TG_OK) return s;
   std::vector<uint32_t> ord(H.N);
   s = emulate_layout(H, window, seed, ord.data(), executed);
-  // report task ids, not positions
-  std::vector<uint32_t> tid_of(H.N);
-  for (uint32_t v = 0; v < g->N(); ++v) tid_of[H.pos_of[0][v]] = v;
-  for (uint64_t i = 0; i < *executed; ++i) order[i] = tid_of[ord[i]];
+  // report (graph, id), not positions
+  std::vector<uint64_t> key_of(H.N);
+  for (uint32_t gi = 0; gi < gs.size(); ++gi)
+    for (uint32_t v = 0; v < gs[gi]->N(); ++v) key_of[H.pos_of[gi][v]] = ((uint64_t)gi << 32) | v;
+  for (uint64_t i = 0; i < *executed; ++i) order[i] = key_of[ord[i]];
+  if (s == TG_OK && makespan && bound) timed_makespan(gs, H, window, makespan, bound);
   return s;
 }
 

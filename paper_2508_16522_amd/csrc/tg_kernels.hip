@@ -159,6 +159,10 @@ __device__ __forceinline__ uint32_t elem(typename VecT<VEC>::T v, int i) {
 }
 
 // Explicit body over words k = k0, k0 + VEC*S, ... handled VEC at a time.
+// The chunk loop and the mix-round loop have wave-uniform trip counts (n,
+// the team size and R are uniform), so both run under scalar loop control;
+// lanes whose chunk lies past the payload (a team wider than n / VEC) only
+// skip the loads and the store.
 template <int VEC, class Team>
 __device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecParams& P, const TaskRec& r,
                                                    const GraphEnt& G) {
@@ -166,35 +170,42 @@ __device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecPar
   const uint32_t n = G.n, S = tm.size();
   const uint32_t nbytes = n * 4u;
   const cptr<uint64_t> pa = as_const(P.pred_addr) + r.pred_beg;
-  const uint32_t npred = r.npred;
+  const uint32_t npred = uni(r.npred), R = uni(r.rounds), tid = uni(r.tid);
   const __amdgpu_buffer_rsrc_t wr = make_rsrc((const void*)r.out, nbytes);
+  const uint32_t step = VEC * S;
+  const uint32_t chunks = uni((n + step - 1u) / step);
   uint32_t dsum = 0;
-  for (uint32_t k0 = tm.t * VEC; k0 < n; k0 += VEC * S) {
-    V acc;
-    if (npred == 0) {
-      // source: initial payload from the graph seed
-      if constexpr (VEC == 1) {
-        acc = h32k(G.key1, ((uint64_t)r.tid << 16) | k0);
+  for (uint32_t c = 0; c < chunks; ++c) {
+    const uint32_t k0 = c * step + tm.t * VEC;
+    const bool valid = k0 < n;
+    V acc = V(0);
+    if (valid) {
+      if (npred == 0) {
+        // source: initial payload from the graph seed
+        if constexpr (VEC == 1) {
+          acc = h32k(G.key1, ((uint64_t)tid << 16) | k0);
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) acc[i] = h32k(G.key1, ((uint64_t)tid << 16) | (k0 + i));
+        }
       } else {
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc[i] = h32k(G.key1, ((uint64_t)r.tid << 16) | (k0 + i));
+        uint32_t j = 0;
+        for (; j + 4 <= npred; j += 4) {
+          V a0 = buf_load<VEC>(make_rsrc((const void*)pa[j + 0], nbytes), k0 * 4);
+          V a1 = buf_load<VEC>(make_rsrc((const void*)pa[j + 1], nbytes), k0 * 4);
+          V a2 = buf_load<VEC>(make_rsrc((const void*)pa[j + 2], nbytes), k0 * 4);
+          V a3 = buf_load<VEC>(make_rsrc((const void*)pa[j + 3], nbytes), k0 * 4);
+          acc += (a0 + a1) + (a2 + a3);
+        }
+        for (; j < npred; ++j) acc += buf_load<VEC>(make_rsrc((const void*)pa[j], nbytes), k0 * 4);
       }
-    } else {
-      acc = V(0);
-      uint32_t j = 0;
-      for (; j + 4 <= npred; j += 4) {
-        V a0 = buf_load<VEC>(make_rsrc((const void*)pa[j + 0], nbytes), k0 * 4);
-        V a1 = buf_load<VEC>(make_rsrc((const void*)pa[j + 1], nbytes), k0 * 4);
-        V a2 = buf_load<VEC>(make_rsrc((const void*)pa[j + 2], nbytes), k0 * 4);
-        V a3 = buf_load<VEC>(make_rsrc((const void*)pa[j + 3], nbytes), k0 * 4);
-        acc += (a0 + a1) + (a2 + a3);
-      }
-      for (; j < npred; ++j) acc += buf_load<VEC>(make_rsrc((const void*)pa[j], nbytes), k0 * 4);
     }
-    V x = mix_rounds<V>(acc ^ r.tid, r.rounds);
-    buf_store<VEC>(x, wr, k0 * 4);
+    V x = mix_rounds<V>(acc ^ tid, R);
+    if (valid) {
+      buf_store<VEC>(x, wr, k0 * 4);
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) dsum += elem<VEC>(x, i) * (2u * (k0 + i) + 1u);
+      for (int i = 0; i < VEC; ++i) dsum += elem<VEC>(x, i) * (2u * (k0 + i) + 1u);
+    }
   }
   return dsum;
 }
@@ -224,34 +235,34 @@ __device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& 
     if (q.priv != 1) continue;
     for (uint64_t e = q.lo + tm.t; e < q.hi; e += S) part += ld_coherent(A + e);
   }
-  const uint32_t key = tm.sum(part) ^ r.tid;
-  const uint32_t R = r.rounds;
+  const uint32_t key = uni(tm.sum(part) ^ r.tid);
+  const uint32_t R = uni(r.rounds);
   uint32_t dsum = 0;
   for (uint32_t i = 0; i < r.nreq; ++i) {
     const ReqDev q = rq[i];
     if (q.priv != 2) continue;
     const uint64_t len = q.hi - q.lo;
-    uint64_t o = tm.t;
-    // four independent elements per lane per step
-    for (; o + 3 * (uint64_t)S < len; o += 4 * (uint64_t)S) {
+    uint32_t* const a = A + q.lo;
+    // four elements per lane per chunk; the chunk loop and the mix-round
+    // loop are wave-uniform, lanes past the end skip loads and stores
+    for (uint64_t base = 0; base < len; base += 4 * (uint64_t)S) {
       u32x4 x;
-      x[0] = ld_coherent(A + q.lo + o);
-      x[1] = ld_coherent(A + q.lo + o + S);
-      x[2] = ld_coherent(A + q.lo + o + 2 * S);
-      x[3] = ld_coherent(A + q.lo + o + 3 * S);
+      bool v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t o = base + tm.t + (uint64_t)k * S;
+        v[k] = o < len;
+        x[k] = v[k] ? ld_coherent(a + o) : 0u;
+      }
       x = mix_rounds<u32x4>(x ^ key, R);
-      st_coherent(A + q.lo + o, x[0]);
-      st_coherent(A + q.lo + o + S, x[1]);
-      st_coherent(A + q.lo + o + 2 * S, x[2]);
-      st_coherent(A + q.lo + o + 3 * S, x[3]);
-      const uint32_t j = q.rw_base + (uint32_t)o;
-      dsum += x[0] * (2u * j + 1u) + x[1] * (2u * (j + S) + 1u) + x[2] * (2u * (j + 2 * S) + 1u) +
-              x[3] * (2u * (j + 3 * S) + 1u);
-    }
-    for (; o < len; o += S) {
-      uint32_t x = mix_rounds<uint32_t>(ld_coherent(A + q.lo + o) ^ key, R);
-      st_coherent(A + q.lo + o, x);
-      dsum += x * (2u * (q.rw_base + (uint32_t)o) + 1u);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t o = base + tm.t + (uint64_t)k * S;
+        if (v[k]) {
+          st_coherent(a + o, x[k]);
+          dsum += x[k] * (2u * (q.rw_base + (uint32_t)o) + 1u);
+        }
+      }
     }
   }
   const uint32_t d = tm.sum(dsum);
@@ -421,7 +432,7 @@ __device__ __forceinline__ void worker_init(WorkerState& w, const ExecParams& P,
   w.rescan = true;
 }
 
-__global__ __launch_bounds__(256) void k_exec_wave(ExecParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exec_wave(ExecParams P) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t worker = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (worker >= P.nworkers) return;

@@ -22,6 +22,7 @@ TG_OK, TG_EINVAL, TG_ENOMEM, TG_EBUSY, TG_EDEVICE, TG_ETIMEOUT, TG_ESTATE = 0, -
 TG_EXPLICIT, TG_IMPLICIT = 1, 2
 TG_RO, TG_RW = 1, 2
 TG_MAP_WAVE, TG_MAP_WORKGROUP = 1, 2
+TG_SCHED_LIST, TG_SCHED_LEVEL = 1, 2
 TG_CMP_PER_TASK, TG_CMP_HIPGRAPH = 1, 2
 
 # Every symbol the header declares; the CPU test-suite checks the library
@@ -33,7 +34,7 @@ EXPORTS = (
     "tg_graph_read_digests", "tg_graph_read_payload", "tg_graph_read_data", "tg_graph_checksum",
     "tg_graph_read_dag", "tg_graph_timings", "tg_graph_destroy",
     "tg_batch_create", "tg_batch_execute", "tg_batch_wait", "tg_batch_time_ms", "tg_batch_destroy",
-    "tg_graph_execute_comparator", "tg_exec_occupancy", "tg_graph_exec_info", "tg_graph_debug_state", "tg_graph_emulate_schedule", "tg_graph_debug_times",
+    "tg_graph_execute_comparator", "tg_exec_occupancy", "tg_graph_exec_info", "tg_graph_debug_state", "tg_emulate_schedule", "tg_graph_debug_times",
     "tg_graph_kernel_ms", "tg_graph_autotune", "tg_probe", "tg_graph_kernel_times", "tg_graph_set_rounds",
     "tg_server_create", "tg_server_submit", "tg_server_wait", "tg_server_stats", "tg_server_destroy",
     "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
@@ -55,7 +56,8 @@ class tg_region_req(ctypes.Structure):
 class tg_exec_config(ctypes.Structure):
     _fields_ = [("mapping", ctypes.c_uint32), ("workers", ctypes.c_uint32), ("window", ctypes.c_uint32),
                 ("wg_waves", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32), ("spin_limit", ctypes.c_uint32),
-                ("diag", ctypes.c_uint32), ("notify", ctypes.c_uint32), ("idle_sleep", ctypes.c_uint32)]
+                ("diag", ctypes.c_uint32), ("notify", ctypes.c_uint32), ("idle_sleep", ctypes.c_uint32),
+                ("schedule", ctypes.c_uint32)]
 
 
 REQ_DTYPE = np.dtype([("lo", np.uint64), ("hi", np.uint64), ("priv", np.uint32), ("_pad", np.uint32)])
@@ -104,7 +106,7 @@ def load() -> ctypes.CDLL:
         "tg_exec_occupancy": (i32, [u32, u32, P, P, P]),
         "tg_graph_exec_info": (i32, [G, P, P]),
         "tg_graph_debug_state": (i32, [G, P, P, P, P, P, u32]),
-        "tg_graph_emulate_schedule": (i32, [G, u32, u32, u64, P, P]),
+        "tg_emulate_schedule": (i32, [P, u32, u32, u32, u32, u64, P, P, P, P]),
         "tg_graph_debug_times": (i32, [G, P, P, u32]),
         "tg_graph_kernel_ms": (i32, [G, P]),
         "tg_graph_autotune": (i32, [G, u32, P, P]),
@@ -118,7 +120,7 @@ def load() -> ctypes.CDLL:
         "tg_server_destroy": (i32, [G]),
         "tg_batch_kernel_times": (i32, [G, P, u32, P]),
         "tg_batch_set_rounds": (i32, [G, u32]),
-        "tg_batch_info": (i32, [G, P, P]),
+        "tg_batch_info": (i32, [G, P, P, P, P]),
         "tg_batch_autotune": (i32, [G, u32, P, P]),
         "tg_graph_execute_after": (i32, [G, P, P, P, u32, P]),
     }
@@ -253,8 +255,9 @@ def tg_graph_finalize(g):
 
 
 def make_config(mapping=0, workers=0, window=0, wg_waves=0, watchdog_ms=0, spin_limit=0, diag=0, notify=0,
-                idle_sleep=0) -> tg_exec_config:
-    return tg_exec_config(mapping, workers, window, wg_waves, watchdog_ms, spin_limit, diag, notify, idle_sleep)
+                idle_sleep=0, schedule=0) -> tg_exec_config:
+    return tg_exec_config(mapping, workers, window, wg_waves, watchdog_ms, spin_limit, diag, notify, idle_sleep,
+                          schedule)
 
 
 def tg_graph_execute(g, cfg: tg_exec_config | None = None, stream=None):
@@ -406,12 +409,26 @@ def tg_graph_debug_times(g):
     return t[:2 * N].reshape(N, 2), ws[:4 * w].reshape(w, 4)
 
 
-def tg_graph_emulate_schedule(g, nworkers: int, window: int = 64, seed: int = 0):
-    N = tg_graph_num_tasks(g)
-    order = np.zeros(max(N, 1), np.uint32)
-    ex = ctypes.c_uint64()
-    st = load().tg_graph_emulate_schedule(g, nworkers, window, seed, _ptr(order), ctypes.byref(ex))
-    return st, order[:ex.value]
+def tg_emulate_schedule(graphs, nworkers: int, window: int = 64, seed: int = 0, schedule: int = 0):
+    """Host-only model of one launch over `graphs` (a graph handle or a list
+    of them).  Returns (status, order, makespan, bound): order is an
+    (executed, 2) array of (graph index, event) in execution order."""
+    hs = list(graphs) if isinstance(graphs, (list, tuple)) else [graphs]
+    total = sum(tg_graph_num_tasks(h) for h in hs)
+    arr = (ctypes.c_void_p * len(hs))(*[ctypes.cast(h, ctypes.c_void_p) for h in hs])
+    order = np.zeros(max(total, 1), np.uint64)
+    ex, mk, bd = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    st = load().tg_emulate_schedule(arr, len(hs), nworkers, window, schedule, seed, _ptr(order), ctypes.byref(ex),
+                                    ctypes.byref(mk), ctypes.byref(bd))
+    o = order[:ex.value]
+    pairs = np.stack([(o >> np.uint64(32)).astype(np.int64), (o & np.uint64(0xFFFFFFFF)).astype(np.int64)], axis=1)
+    return st, pairs, mk.value, bd.value
+
+
+def tg_graph_emulate_schedule(g, nworkers: int, window: int = 64, seed: int = 0, schedule: int = 0):
+    """One graph: (status, execution order by event)."""
+    st, pairs, _, _ = tg_emulate_schedule(g, nworkers, window, seed, schedule)
+    return st, pairs[:, 1].astype(np.uint32)
 
 
 def tg_graph_execute_comparator(g, mode: int, stream=None):
@@ -454,11 +471,16 @@ def tg_batch_set_rounds(b, rounds: int):
     _check(load().tg_batch_set_rounds(b, rounds), "tg_batch_set_rounds")
 
 
-def tg_batch_info(b):
+def tg_batch_info(b, with_times: bool = False):
     c = tg_exec_config()
     n = ctypes.c_uint64()
-    _check(load().tg_batch_info(b, ctypes.byref(c), ctypes.byref(n)), "tg_batch_info")
-    return {f: getattr(c, f) for f, _ in tg_exec_config._fields_}, n.value
+    pm, bm = ctypes.c_double(), ctypes.c_double()
+    _check(load().tg_batch_info(b, ctypes.byref(c), ctypes.byref(n), ctypes.byref(pm), ctypes.byref(bm)),
+           "tg_batch_info")
+    cfg = {f: getattr(c, f) for f, _ in tg_exec_config._fields_}
+    if with_times:
+        return cfg, n.value, {"plan_ms": pm.value, "build_ms": bm.value}
+    return cfg, n.value
 
 
 def tg_batch_autotune(b, reps: int = 2):

@@ -11,14 +11,15 @@ from tests.gpu_util import check_explicit, oracle_explicit, run
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("schedule", [tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL])
 @pytest.mark.parametrize("mapping", [1, 2])
-def test_mixed_batch(gpu, mapping):
+def test_mixed_batch(gpu, mapping, schedule):
     specs = wl.batch_manifest(24, seed=3, wmax=64, tmax=32)
     egs = [wl.pattern_graph(s.pattern, s.W, s.T, seed=s.seed, n=s.n, rounds=min(s.rounds, 300)) for s in specs]
     ig = wl.halo_graph(16, 128, 6, seed=5, rounds=3)
     gs = [tg.graph_from_explicit(eg) for eg in egs]
     gi = tg.graph_from_implicit(ig)
-    b = tg.tg_batch_create([g.handle for g in gs] + [gi.handle], tg.make_config(mapping=mapping))
+    b = tg.tg_batch_create([g.handle for g in gs] + [gi.handle], tg.make_config(mapping=mapping, schedule=schedule))
     try:
         for _ in range(2):
             tg.tg_batch_execute(b)
@@ -60,3 +61,27 @@ def test_manifest_slice_256_graphs(gpu):
         ref = oracle_explicit(eg, want_payload=False)
         assert np.array_equal(tg.tg_graph_read_digests(gs[i].handle), ref["digest"]), f"graph {i}"
         assert tg.tg_graph_checksum(gs[i].handle) == ref["checksum"]
+
+
+def test_batch_autotune_keeps_results(gpu):
+    """The autotuner re-plans the batch for several launch shapes and
+    schedules (reusing plans with equal worker counts); the layout it keeps
+    still gives the oracle's digests, also after a change of mix rounds."""
+    specs = wl.batch_manifest(12, seed=9, wmax=48, tmax=24)
+    egs = [wl.pattern_graph(s.pattern, s.W, s.T, seed=s.seed, n=s.n, rounds=0) for s in specs]
+    gs = [tg.graph_from_explicit(eg) for eg in egs]
+    b = tg.tg_batch_create([g.handle for g in gs])
+    try:
+        for R in (0, 40):
+            tg.tg_batch_set_rounds(b, R)
+            cfg, ms = tg.tg_batch_autotune(b, reps=1)
+            assert ms > 0 and cfg["schedule"] in (tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL)
+            _, _, times = tg.tg_batch_info(b, with_times=True)
+            assert times["build_ms"] >= times["plan_ms"] >= 0
+            tg.tg_batch_execute(b)
+            tg.tg_batch_wait(b)
+            for g, eg in zip(gs, egs):
+                eg.rounds = R
+                check_explicit(g, eg, oracle_explicit(eg, want_payload=False))
+    finally:
+        tg.tg_batch_destroy(b)

@@ -29,13 +29,14 @@ def test_patterns_ragged(gpu, pattern, n, mapping):
     check_explicit(g, eg, ref, payload_sample=64)
 
 
+@pytest.mark.parametrize("schedule", [tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL])
 @pytest.mark.parametrize("workers,window", [(1, 64), (1, 1), (7, 3), (64, 64), (0, 1), (0, 64)])
 @pytest.mark.parametrize("mapping", [1, 2])
-def test_worker_and_window_variants(gpu, mapping, workers, window):
+def test_worker_and_window_variants(gpu, mapping, workers, window, schedule):
     eg = wl.pattern_graph("random", 50, 20, seed=2, n=128, rounds=2)
     ref = oracle_explicit(eg)
     g = tg.graph_from_explicit(eg)
-    run(g, tg.make_config(mapping=mapping, workers=workers, window=window, wg_waves=4))
+    run(g, tg.make_config(mapping=mapping, workers=workers, window=window, wg_waves=4, schedule=schedule))
     check_explicit(g, eg, ref)
 
 
