@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-alone", action="store_true", help="skip timing each graph alone")
     ap.add_argument("--comparator-steps", type=int, default=50, help="timesteps of the comparator sub-graph")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2 (default): the bench line; c3 implicit, c4 4096-graph batch, c5 serving")
@@ -142,6 +143,8 @@ def main():
     tuned = {}
     solo_ms = {}
     for p, g in zip(wl.PATTERNS, gs):
+        if args.no_alone:
+            break
         if args.no_tune:
             tuned[p] = None
             tg.tg_graph_execute(g.handle, None, stream)
@@ -291,7 +294,7 @@ def main():
             "launch": bcfg,
         },
         "alone_ms": solo_ms,
-        "alone_launch": {p: tuned[p] for p in wl.PATTERNS},
+        "alone_launch": tuned,
         "per_task_overhead_ns": 1e9 / value,
         "metg50_us": sweep["metg50_us"] if sweep else None,
         "parity": parity,

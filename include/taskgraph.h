@@ -103,10 +103,13 @@ typedef struct {
  *   idle_sleep   : back-off of an idle worker, in units of 128 cycles
  *                  (1..64, default 2).
  *   schedule     : how tasks are partitioned over the workers' lists
- *                  (Algorithm 1, Compile): TG_SCHED_LIST (default) simulates
- *                  the workers with estimated task costs and starts ready
- *                  tasks longest-remaining-path first; TG_SCHED_LEVEL sorts
- *                  by dependence level and deals round-robin. */
+ *                  (Algorithm 1, Compile): TG_SCHED_LEVEL (default) sorts by
+ *                  dependence level and deals round-robin; TG_SCHED_SPREAD
+ *                  stretches every graph's levels over the same interval
+ *                  before sorting and dealing, so graphs of different depths
+ *                  advance side by side; TG_SCHED_LIST simulates the workers
+ *                  with estimated task costs and starts ready tasks
+ *                  longest-remaining-path first. */
 typedef struct {
   uint32_t mapping;
   uint32_t workers;
@@ -121,7 +124,7 @@ typedef struct {
 } tg_exec_config;
 
 enum { TG_MAP_WAVE = 1, TG_MAP_WORKGROUP = 2 };
-enum { TG_SCHED_LIST = 1, TG_SCHED_LEVEL = 2 };
+enum { TG_SCHED_LIST = 1, TG_SCHED_LEVEL = 2, TG_SCHED_SPREAD = 3 };
 
 /* ------------------------------------------------------------- status */
 const char* tg_status_str(tg_status s);

@@ -3,13 +3,14 @@
 //
 // Compilation follows Algorithm 1 (Compile): the graph's vertices are
 // partitioned over workers, every vertex gets a counter of pending in-edges
-// and an O(1) list of out-edges.  The partition is a static list schedule:
-// a simulation of the workers with estimated task costs assigns each ready
-// vertex, longest remaining path first, to the next free worker, and each
-// worker's list holds its vertices in simulated start order (a dependence-
-// level order dealt round-robin is kept as the alternative).  Either way
-// every list is topologically ordered, which is what makes the executor
-// deadlock-free for any ready-window length.
+// and an O(1) list of out-edges.  Three static partitions are offered: the
+// default sorts vertices by dependence level and deals them round-robin (a
+// graph as wide as the worker count keeps every column on one worker);
+// a spread order stretches every graph's levels over one common interval
+// first; a list schedule simulates the workers with estimated task costs
+// and starts ready vertices longest-remaining-path first.  Every list is
+// topologically ordered, which is what makes the executor deadlock-free for
+// any ready-window length.
 #include "taskgraph.h"
 #include "tg_internal.h"
 
@@ -151,7 +152,7 @@ tg_status device_info(DevInfo& di) {
 
 struct Config {
   uint32_t mapping = 1, workers = 0, window = 64, wg_waves = 4, watchdog_ms = 5000, spin_limit = 0, diag = 0;
-  uint32_t idle_sleep = 2, notify = 0, schedule = TG_SCHED_LIST;
+  uint32_t idle_sleep = 2, notify = 0, schedule = TG_SCHED_LEVEL;
 };
 
 Config resolve(const tg_exec_config* c) {
@@ -176,7 +177,7 @@ tg_status check_config(const Config& c) {
   if (c.window < 1 || c.window > 64) return fail(TG_EINVAL, "window must be in [1, 64]");
   if (c.idle_sleep < 1 || c.idle_sleep > 64) return fail(TG_EINVAL, "idle_sleep must be in [1, 64]");
   if (c.wg_waves < 1 || c.wg_waves > 16) return fail(TG_EINVAL, "wg_waves must be in [1, 16]");
-  if (c.schedule != TG_SCHED_LIST && c.schedule != TG_SCHED_LEVEL) return fail(TG_EINVAL, "schedule must be 1 or 2");
+  if (c.schedule < TG_SCHED_LIST || c.schedule > TG_SCHED_SPREAD) return fail(TG_EINVAL, "schedule must be 1, 2 or 3");
   return TG_OK;
 }
 
@@ -193,6 +194,10 @@ struct Layout {
   ExecParams params{};
   double plan_ms = 0, build_ms = 0;  // host time: schedule + records, whole layout incl. upload
 };
+
+namespace {
+struct PlanCache;
+}  // namespace
 
 struct tg_graph_s {
   uint32_t mode = 0, n = 0;
@@ -213,6 +218,7 @@ struct tg_graph_s {
   std::vector<uint32_t> rw_base;  // implicit: per requirement, ordinal of its first written element
   DevBuf payload, data, digest;
   std::unique_ptr<Layout> solo;
+  std::shared_ptr<PlanCache> plans;  // schedules of this graph alone, by (workers, schedule)
   // execution state
   bool inflight = false;
   Layout* last_layout = nullptr;
@@ -234,10 +240,6 @@ struct tg_graph_s {
   hipGraphExec_t hgx = nullptr;
   uint32_t N() const { return mode == TG_EXPLICIT ? (uint32_t)(pred_ptr.size() - 1) : (uint32_t)(req_ptr.size() - 1); }
 };
-
-namespace {
-struct PlanCache;
-}  // namespace
 
 struct tg_batch_s {
   std::vector<tg_graph> graphs;
@@ -362,6 +364,76 @@ void schedule_levels(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw, s
   wlen.assign(nw, 0);
   for (uint32_t w = 0; w < nw; ++w) wlen[w] = (N > w) ? (N - w + nw - 1) / nw : 0;
   // seq lists worker 0's tasks, then worker 1's, ...
+  std::vector<uint64_t> off(nw + 1, 0);
+  for (uint32_t w = 0; w < nw; ++w) off[w + 1] = off[w] + wlen[w];
+  seq.assign(N, 0);
+  for (uint64_t si = 0; si < N; ++si) seq[off[si % nw] + si / nw] = sorted[si];
+}
+
+// Spread order: every graph's dependence levels are stretched over the same
+// unit interval (task i of the m tasks at level l of an L-level graph gets
+// the key (l + (i + 1/2) / m) / L), all tasks are sorted by key and dealt
+// round-robin.  Graphs of different depths then advance side by side, and a
+// shallow graph's tasks (a dependence-free graph is one level) are spread
+// evenly through every worker's list, where the ready window finds them
+// whenever the next deep-graph task is not ready yet.  A predecessor's key
+// is below its successor's (its level is lower), and ties after
+// quantisation keep (graph, id) order, so the sequence is topological.
+void schedule_spread(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw, std::vector<uint32_t>& wlen,
+                     std::vector<uint64_t>& seq) {
+  const uint64_t Q = std::max<uint64_t>(1024, std::min<uint64_t>(1ull << 24, 2ull * N));
+  // key = (l + (i + 1/2) / m) / L = (2 (l m + i) + 1) / (2 m L), kept exact as
+  // num / den (both below 2^63 for fewer than 2^32 tasks); its double value
+  // only picks the bucket, which is monotone in the exact key
+  std::vector<uint64_t> num(N), den(N);
+  std::vector<uint32_t> bucket(N);
+  std::vector<uint64_t> start(Q + 1, 0);
+  uint32_t x = 0;
+  for (auto g : gs) {
+    const uint32_t n = g->N();
+    uint32_t L = 0;
+    for (uint32_t lv : g->level) L = std::max(L, lv + 1);
+    std::vector<uint32_t> width(L, 0), seen(L, 0);
+    for (uint32_t lv : g->level) width[lv]++;
+    for (uint32_t v = 0; v < n; ++v, ++x) {
+      const uint32_t lv = g->level[v];
+      const uint64_t i = seen[lv]++;
+      num[x] = 2 * ((uint64_t)lv * width[lv] + i) + 1;
+      den[x] = 2 * (uint64_t)width[lv] * L;
+      const double k = (lv + (i + 0.5) / width[lv]) / L;
+      bucket[x] = (uint32_t)std::min<uint64_t>((uint64_t)(k * (double)Q), Q - 1);
+      start[bucket[x] + 1]++;
+    }
+  }
+  for (uint64_t i = 1; i <= Q; ++i) start[i] += start[i - 1];
+  std::vector<uint64_t> sorted(N);
+  std::vector<uint32_t> idx(N);
+  {
+    std::vector<uint64_t> fill(start.begin(), start.end() - 1);
+    x = 0;
+    for (uint32_t gi = 0; gi < gs.size(); ++gi)
+      for (uint32_t v = 0; v < gs[gi]->N(); ++v, ++x) {
+        sorted[fill[bucket[x]]] = ((uint64_t)gi << 32) | v;
+        idx[fill[bucket[x]]++] = x;
+      }
+  }
+  // inside a bucket: by exact key, equal keys (only tasks of different
+  // graphs) by (graph, id)
+  for (uint64_t q = 0; q < Q; ++q) {
+    const uint64_t a = start[q], b = start[q + 1];
+    if (b - a < 2) continue;
+    std::vector<std::pair<uint32_t, uint64_t>> items;
+    for (uint64_t i = a; i < b; ++i) items.emplace_back(idx[i], sorted[i]);
+    std::sort(items.begin(), items.end(), [&](const std::pair<uint32_t, uint64_t>& u, const std::pair<uint32_t, uint64_t>& w) {
+      const unsigned __int128 l = (unsigned __int128)num[u.first] * den[w.first];
+      const unsigned __int128 r = (unsigned __int128)num[w.first] * den[u.first];
+      if (l != r) return l < r;
+      return u.second < w.second;
+    });
+    for (uint64_t i = a; i < b; ++i) sorted[i] = items[i - a].second;
+  }
+  wlen.assign(nw, 0);
+  for (uint32_t w = 0; w < nw; ++w) wlen[w] = (N > w) ? (N - w + nw - 1) / nw : 0;
   std::vector<uint64_t> off(nw + 1, 0);
   for (uint32_t w = 0; w < nw; ++w) off[w + 1] = off[w] + wlen[w];
   seq.assign(N, 0);
@@ -502,7 +574,15 @@ tg_status schedule_list(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw
 // Schedule a set of finalised graphs onto nw workers (list schedule or
 // dependence-level order) and store each worker's tasks contiguously in the
 // order it is to run them.
-tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t schedule, HostLayout& H) {
+// A schedule: per-worker list lengths and, worker by worker, the tasks of
+// each list in order as (graph << 32) | id.
+struct Plan {
+  std::vector<uint32_t> wlen;
+  std::vector<uint64_t> seq;
+};
+
+tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t schedule, HostLayout& H,
+                      const Plan* reuse = nullptr, Plan* keep = nullptr) {
   uint64_t ntot = 0, npred_tot = 0, nsucc_tot = 0, nreq_tot = 0;
   for (auto g : gs) {
     ntot += g->N();
@@ -513,7 +593,7 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
   if (ntot >= 0xFFFFFFFFull || npred_tot >= 0xFFFFFFFFull || nsucc_tot >= 0xFFFFFFFFull || nreq_tot >= 0xFFFFFFFFull)
     return fail(TG_EINVAL, "layout too large: %llu tasks, %llu edges", (unsigned long long)ntot,
                 (unsigned long long)nsucc_tot);
-  if (schedule != TG_SCHED_LIST && schedule != TG_SCHED_LEVEL) return fail(TG_EINVAL, "schedule must be 1 or 2");
+  if (schedule < TG_SCHED_LIST || schedule > TG_SCHED_SPREAD) return fail(TG_EINVAL, "schedule must be 1, 2 or 3");
   const uint32_t N = (uint32_t)ntot;
   uint64_t nw = nw_req;
   if (nw > N) nw = N ? N : 1;
@@ -522,11 +602,20 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
   H.nw = (uint32_t)nw;
   std::vector<uint32_t> wlen;
   std::vector<uint64_t> at_pos;  // (graph << 32) | id, by position
-  if (schedule == TG_SCHED_LIST) {
+  if (reuse && reuse->wlen.size() == nw && reuse->seq.size() == N) {
+    wlen = reuse->wlen;
+    at_pos = reuse->seq;
+  } else if (schedule == TG_SCHED_LIST) {
     tg_status st = schedule_list(gs, N, (uint32_t)nw, wlen, at_pos);
     if (st != TG_OK) return st;
-  } else {
+  } else if (schedule == TG_SCHED_LEVEL) {
     schedule_levels(gs, N, (uint32_t)nw, wlen, at_pos);
+  } else {
+    schedule_spread(gs, N, (uint32_t)nw, wlen, at_pos);
+  }
+  if (keep) {
+    keep->wlen = wlen;
+    keep->seq = at_pos;
   }
   H.wbase.assign((size_t)nw + 1, 0);
   for (uint64_t w = 0; w < nw; ++w) H.wbase[w + 1] = H.wbase[w] + wlen[w];
@@ -561,15 +650,22 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
     if (g->mode == TG_EXPLICIT) {
       const uint64_t base = (uint64_t)g->payload.p;
       r.out = base + (uint64_t)v * g->n * 4ull;
-      for (uint64_t j = g->dpred_ptr[v]; j < g->dpred_ptr[v + 1]; ++j)
-        H.pred_addr.push_back(base + (uint64_t)g->dpred[j] * g->n * 4ull);
+      for (uint64_t j = g->dpred_ptr[v]; j < g->dpred_ptr[v + 1]; ++j) {
+        const uint64_t a = base + (uint64_t)g->dpred[j] * g->n * 4ull;
+        if (j - g->dpred_ptr[v] < tg::kInPred) r.pred[j - g->dpred_ptr[v]] = a;
+        H.pred_addr.push_back(a);
+      }
     } else {
       r.out = req_base[gi] + g->req_ptr[v];
       r.nreq = (uint32_t)(g->req_ptr[v + 1] - g->req_ptr[v]);
     }
     r.succ_beg = (uint32_t)H.succ_pos.size();
     r.nsucc = (uint32_t)(g->succ_ptr[v + 1] - g->succ_ptr[v]);
-    for (uint64_t j = g->succ_ptr[v]; j < g->succ_ptr[v + 1]; ++j) H.succ_pos.push_back(H.pos_of[gi][g->succ[j]]);
+    for (uint64_t j = g->succ_ptr[v]; j < g->succ_ptr[v + 1]; ++j) {
+      const uint32_t sp = H.pos_of[gi][g->succ[j]];
+      if (j - g->succ_ptr[v] < tg::kInSucc) r.succ[j - g->succ_ptr[v]] = sp;
+      H.succ_pos.push_back(sp);
+    }
     H.indeg[pos] = r.npred;
   }
   H.gtab.assign(gs.size(), GraphEnt());
@@ -602,14 +698,14 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
 tg_status ensure_device(tg_graph g);
 
 // Schedule and upload the layout of a set of finalised graphs.
-// Host layouts already planned for a set of graphs, by (workers, schedule):
-// launch shapes with the same worker count share one plan, so an autotuner
-// pass re-plans only for new worker counts.  Records are refreshed from the
-// graphs' current mix rounds whenever a plan is reused.
+// Schedules already computed for a set of graphs, by (workers, schedule):
+// launch shapes with the same worker count share one, so an autotuner pass
+// schedules only new (worker count, schedule) pairs; task records are always
+// rebuilt, so they carry the graphs' current mix rounds.
 struct PlanCache {
-  static constexpr uint64_t kMaxTasks = 1ull << 24;  // larger layouts are not kept
-  static constexpr size_t kMaxEntries = 6;
-  std::map<std::pair<uint32_t, uint32_t>, std::shared_ptr<const HostLayout>> m;
+  static constexpr uint64_t kMaxTasks = 1ull << 25;  // larger schedules are not kept
+  static constexpr size_t kMaxEntries = 16;
+  std::map<std::pair<uint32_t, uint32_t>, std::shared_ptr<const Plan>> m;
 };
 
 tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::unique_ptr<Layout>& out,
@@ -627,15 +723,17 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   HostLayout H;
   const auto t_plan = std::chrono::steady_clock::now();
   const std::pair<uint32_t, uint32_t> key((uint32_t)nw, cfg.schedule);
-  auto hit = cache ? cache->m.find(key) : decltype(cache->m.end()){};
-  if (cache && hit != cache->m.end()) {
-    H = *hit->second;
-    for (auto& r : H.rec) r.rounds = gs[r.graph]->rounds[r.tid];
-  } else {
-    if ((s = plan_layout(gs, nw, cfg.schedule, H)) != TG_OK) return s;
-    if (cache && H.N <= PlanCache::kMaxTasks && cache->m.size() < PlanCache::kMaxEntries)
-      cache->m[key] = std::make_shared<const HostLayout>(H);
+  const Plan* reuse = nullptr;
+  if (cache) {
+    auto hit = cache->m.find(key);
+    if (hit != cache->m.end()) reuse = hit->second.get();
   }
+  uint64_t ntasks = 0;
+  for (auto g : gs) ntasks += g->N();
+  const bool keep = cache && !reuse && ntasks <= PlanCache::kMaxTasks && cache->m.size() < PlanCache::kMaxEntries;
+  auto kept = keep ? std::make_shared<Plan>() : nullptr;
+  if ((s = plan_layout(gs, nw, cfg.schedule, H, reuse, kept.get())) != TG_OK) return s;
+  if (keep) cache->m[key] = kept;
   const double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_plan).count();
   auto L = std::make_unique<Layout>();
   L->cfg = cfg;
@@ -1186,7 +1284,8 @@ tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfgp, void* stream)
     if (g->inflight && (s = graph_wait(g)) != TG_OK) return s;
     g->solo.reset();
     std::vector<tg_graph> gs{g};
-    if ((s = build_layout(gs, cfg, g->solo)) != TG_OK) return s;
+    if (!g->plans) g->plans = std::make_shared<PlanCache>();
+    if ((s = build_layout(gs, cfg, g->solo, g->plans.get())) != TG_OK) return s;
   }
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipEventRecord(g->ev0, st));
@@ -1364,14 +1463,18 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
     c.notify = nt;
     return c;
   };
-  for (uint32_t w : {rw, rw / 2, rw / 4, rw / 6})
-    if (w) cand.push_back(mk(TG_MAP_WAVE, w, 0, 0));
+  for (uint32_t sch : {TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD}) {
+    std::vector<tg_exec_config> shapes;
+    for (uint32_t w : {rw, rw / 4, rw / 8})
+      if (w) shapes.push_back(mk(TG_MAP_WAVE, w, 0, 0));
+    shapes.push_back(mk(TG_MAP_WORKGROUP, rg2, 2, 0));
+    shapes.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
+    for (auto c : shapes) {
+      c.schedule = sch;
+      cand.push_back(c);
+    }
+  }
   cand.push_back(mk(TG_MAP_WAVE, rw, 0, 1));
-  cand.push_back(mk(TG_MAP_WORKGROUP, rg2, 2, 0));
-  cand.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
-  if (rg4 / 2) cand.push_back(mk(TG_MAP_WORKGROUP, rg4 / 2, 4, 0));
-  cand.push_back(mk(TG_MAP_WAVE, rw, 0, 0));
-  cand.back().schedule = TG_SCHED_LEVEL;
   double best_t = 1e300;
   tg_exec_config best_c = cand[0];
   for (const auto& c : cand) {
@@ -1423,7 +1526,8 @@ tg_status tg_batch_create(tg_batch* out, const tg_graph* graphs, uint32_t n, con
   Config cfg = resolve(cfgp);
   auto b = std::make_unique<tg_batch_s>();
   b->graphs = gs;
-  tg_status s = build_layout(gs, cfg, b->lay);
+  b->plans = std::make_shared<PlanCache>();
+  tg_status s = build_layout(gs, cfg, b->lay, b->plans.get());
   if (s != TG_OK) return s;
   for (auto g : gs) b->gens.push_back(g->dev_gen);
   HIPCHK(hipEventCreate(&b->ev0));
@@ -1537,10 +1641,7 @@ tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, dou
   if ((s = resident_workers(TG_MAP_WAVE, 4, &rw)) != TG_OK) return s;
   if ((s = resident_workers(TG_MAP_WORKGROUP, 2, &rg2)) != TG_OK) return s;
   if ((s = resident_workers(TG_MAP_WORKGROUP, 4, &rg4)) != TG_OK) return s;
-  // plans hold the graphs' device addresses: drop them if any moved
-  bool moved = false;
-  for (size_t i = 0; i < b->graphs.size(); ++i) moved |= b->graphs[i]->dev_gen != b->gens[i];
-  if (!b->plans || moved) b->plans = std::make_shared<PlanCache>();
+  if (!b->plans) b->plans = std::make_shared<PlanCache>();
   std::vector<Config> cand;
   auto mk = [](uint32_t m, uint32_t w, uint32_t ww, uint32_t nt) {
     Config c;
@@ -1550,13 +1651,18 @@ tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, dou
     c.notify = nt;
     return c;
   };
-  for (uint32_t w : {rw, rw / 2, rw / 4})
-    if (w) cand.push_back(mk(TG_MAP_WAVE, w, 0, 0));
+  for (uint32_t sch : {TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD}) {
+    std::vector<Config> shapes;
+    for (uint32_t w : {rw, rw / 4})
+      if (w) shapes.push_back(mk(TG_MAP_WAVE, w, 0, 0));
+    shapes.push_back(mk(TG_MAP_WORKGROUP, rg2, 2, 0));
+    shapes.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
+    for (auto c : shapes) {
+      c.schedule = sch;
+      cand.push_back(c);
+    }
+  }
   cand.push_back(mk(TG_MAP_WAVE, rw, 0, 1));
-  cand.push_back(mk(TG_MAP_WORKGROUP, rg2, 2, 0));
-  cand.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
-  cand.push_back(mk(TG_MAP_WAVE, rw, 0, 0));
-  cand.back().schedule = TG_SCHED_LEVEL;
   double best_t = 1e300;
   Config best_c = cand[0];
   for (const auto& c : cand) {
@@ -1673,7 +1779,7 @@ tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t
     if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
   }
   HostLayout H;
-  tg_status s = plan_layout(gs, nworkers, schedule ? schedule : (uint32_t)TG_SCHED_LIST, H);
+  tg_status s = plan_layout(gs, nworkers, schedule ? schedule : (uint32_t)TG_SCHED_LEVEL, H);
   if (s != TG_OK) return s;
   std::vector<uint32_t> ord(H.N);
   s = emulate_layout(H, window, seed, ord.data(), executed);

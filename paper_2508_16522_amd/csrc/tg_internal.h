@@ -4,11 +4,12 @@
 // graphs for one launch configuration.  Every task of every graph gets a
 // position; positions are grouped per worker (a wavefront or a workgroup, the
 // GPU counterpart of the paper's per-resource worker actor), and within a
-// worker they are ordered by dependence level.  Each position owns one u32
+// worker they are in the order the schedule runs them (topological).  Each position owns one u32
 // counter of pending in-edges (Algorithm 1's per-vertex counter) and an O(1)
 // out-edge list of successor positions.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace tg {
@@ -24,20 +25,40 @@ struct GraphEnt {
   uint32_t pad[2];
 };
 
-// Per-position task record (48 bytes, read with scalar loads).
-struct alignas(16) TaskRec {
-  uint64_t out;       // explicit: device address of this task's payload
-                      // implicit: index of its first region requirement
-  uint32_t tid;       // task id inside its graph (creation index)
-  uint32_t graph;     // index into the graph table
-  uint32_t pred_beg;  // explicit: first entry in pred_addr[]
-  uint32_t npred;     // number of distinct predecessors (= in-degree)
-  uint32_t succ_beg;  // first entry in succ_pos[]
-  uint32_t nsucc;     // number of successors
-  uint32_t rounds;    // mix rounds
-  uint32_t nreq;      // implicit: number of region requirements
-  uint32_t pad[2];
+constexpr uint32_t kInPred = 6;  // predecessor payload addresses held in the record
+constexpr uint32_t kInSucc = 8;  // successor positions held in the record
+
+// Per-position task record: 128 bytes (32 dwords), read by one coalesced
+// vector load per wavefront (lane i holds dword i % 32) and unpacked with
+// readlane.  The first kInPred predecessor addresses and kInSucc successor
+// positions are inline, so a task's payload loads depend on one load (the
+// record) and its edge signals on none after the payload store.
+struct alignas(128) TaskRec {
+  uint64_t out;            // dw 0-1  explicit: device address of this task's payload
+                           //         implicit: index of its first region requirement
+  uint32_t tid;            // dw 2    task id inside its graph (creation index)
+  uint32_t graph;          // dw 3    index into the graph table
+  uint32_t pred_beg;       // dw 4    explicit: all predecessors at pred_addr[pred_beg ..]
+  uint32_t npred;          // dw 5    number of distinct predecessors (= in-degree)
+  uint32_t succ_beg;       // dw 6    all successors at succ_pos[succ_beg ..]
+  uint32_t nsucc;          // dw 7    number of successors
+  uint32_t rounds;         // dw 8    mix rounds
+  uint32_t nreq;           // dw 9    implicit: number of region requirements
+  uint64_t pred[kInPred];  // dw 10-21 first predecessors' payload addresses
+  uint32_t succ[kInSucc];  // dw 22-29 first successor positions
+  uint32_t pad[2];         // dw 30-31
 };
+static_assert(sizeof(TaskRec) == 128, "task record is 32 dwords");
+enum : uint32_t {
+  kDwOut = 0, kDwTid = 2, kDwGraph = 3, kDwPredBeg = 4, kDwNpred = 5, kDwSuccBeg = 6, kDwNsucc = 7,
+  kDwRounds = 8, kDwNreq = 9, kDwPred = 10, kDwSucc = 22
+};
+static_assert(offsetof(TaskRec, tid) == 4 * kDwTid && offsetof(TaskRec, graph) == 4 * kDwGraph &&
+                  offsetof(TaskRec, pred_beg) == 4 * kDwPredBeg && offsetof(TaskRec, npred) == 4 * kDwNpred &&
+                  offsetof(TaskRec, succ_beg) == 4 * kDwSuccBeg && offsetof(TaskRec, nsucc) == 4 * kDwNsucc &&
+                  offsetof(TaskRec, rounds) == 4 * kDwRounds && offsetof(TaskRec, nreq) == 4 * kDwNreq &&
+                  offsetof(TaskRec, pred) == 4 * kDwPred && offsetof(TaskRec, succ) == 4 * kDwSucc,
+              "record dword map");
 
 // Region requirement on the device (implicit mode).
 struct alignas(16) ReqDev {

@@ -128,6 +128,53 @@ struct BlockTeam {
   }
 };
 
+// ----------------------------------------------------------------- record
+
+__device__ __forceinline__ uint32_t rl(uint32_t v, uint32_t k) { return __builtin_amdgcn_readlane(v, k); }
+
+// A task record as one team holds it: every wavefront loads the 128-byte
+// record with one coalesced load (lane i: dword i % 32) and reads the scalar
+// fields out with readlane.  succ0 is the successor this team index signals
+// first (index t), fetched together with the record so that no load stands
+// between the payload store and the edge signals.
+struct Rec {
+  uint32_t v;
+  uint64_t out;
+  uint32_t tid, graph, pred_beg, npred, succ_beg, nsucc, rounds, nreq;
+  uint32_t succ0;
+};
+
+// This lane's dword of the record at `pos`.  Records are read-only while a
+// launch runs, so a plain (cached) load is enough.
+__device__ __forceinline__ uint32_t rec_dword(const ExecParams& P, uint32_t pos, uint32_t lane) {
+  return reinterpret_cast<const uint32_t*>(P.rec + pos)[lane & 31u];
+}
+
+template <class Team>
+__device__ __forceinline__ void unpack_rec(const Team& tm, const ExecParams& P, uint32_t v, Rec& r) {
+  const uint32_t lane = tm.t & 63u;
+  r.v = v;
+  r.out = (uint64_t)rl(r.v, kDwOut) | ((uint64_t)rl(r.v, kDwOut + 1) << 32);
+  r.tid = rl(r.v, kDwTid);
+  r.graph = rl(r.v, kDwGraph);
+  r.pred_beg = rl(r.v, kDwPredBeg);
+  r.npred = rl(r.v, kDwNpred);
+  r.succ_beg = rl(r.v, kDwSuccBeg);
+  r.nsucc = rl(r.v, kDwNsucc);
+  r.rounds = rl(r.v, kDwRounds);
+  r.nreq = rl(r.v, kDwNreq);
+  const uint32_t inl = __shfl(r.v, (int)(kDwSucc + (lane & (kInSucc - 1))), 64);
+  const uint32_t j = tm.t;
+  r.succ0 = 0;
+  if (j < r.nsucc) r.succ0 = j < kInSucc ? inl : P.succ_pos[r.succ_beg + j];
+}
+
+// Payload address of predecessor j (j wave-uniform).
+__device__ __forceinline__ uint64_t pred_at(const ExecParams& P, const Rec& r, uint32_t j) {
+  if (j < kInPred) return (uint64_t)rl(r.v, kDwPred + 2 * j) | ((uint64_t)rl(r.v, kDwPred + 2 * j + 1) << 32);
+  return as_const(P.pred_addr)[r.pred_beg + j];
+}
+
 // ------------------------------------------------------------------ bodies
 
 template <int VEC>
@@ -164,13 +211,12 @@ __device__ __forceinline__ uint32_t elem(typename VecT<VEC>::T v, int i) {
 // lanes whose chunk lies past the payload (a team wider than n / VEC) only
 // skip the loads and the store.
 template <int VEC, class Team>
-__device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecParams& P, const TaskRec& r,
+__device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecParams& P, const Rec& r,
                                                    const GraphEnt& G) {
   typedef typename VecT<VEC>::T V;
   const uint32_t n = G.n, S = tm.size();
   const uint32_t nbytes = n * 4u;
-  const cptr<uint64_t> pa = as_const(P.pred_addr) + r.pred_beg;
-  const uint32_t npred = uni(r.npred), R = uni(r.rounds), tid = uni(r.tid);
+  const uint32_t npred = r.npred, R = r.rounds, tid = r.tid;
   const __amdgpu_buffer_rsrc_t wr = make_rsrc((const void*)r.out, nbytes);
   const uint32_t step = VEC * S;
   const uint32_t chunks = uni((n + step - 1u) / step);
@@ -191,13 +237,13 @@ __device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecPar
       } else {
         uint32_t j = 0;
         for (; j + 4 <= npred; j += 4) {
-          V a0 = buf_load<VEC>(make_rsrc((const void*)pa[j + 0], nbytes), k0 * 4);
-          V a1 = buf_load<VEC>(make_rsrc((const void*)pa[j + 1], nbytes), k0 * 4);
-          V a2 = buf_load<VEC>(make_rsrc((const void*)pa[j + 2], nbytes), k0 * 4);
-          V a3 = buf_load<VEC>(make_rsrc((const void*)pa[j + 3], nbytes), k0 * 4);
+          V a0 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 0), nbytes), k0 * 4);
+          V a1 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 1), nbytes), k0 * 4);
+          V a2 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 2), nbytes), k0 * 4);
+          V a3 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 3), nbytes), k0 * 4);
           acc += (a0 + a1) + (a2 + a3);
         }
-        for (; j < npred; ++j) acc += buf_load<VEC>(make_rsrc((const void*)pa[j], nbytes), k0 * 4);
+        for (; j < npred; ++j) acc += buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j), nbytes), k0 * 4);
       }
     }
     V x = mix_rounds<V>(acc ^ tid, R);
@@ -211,7 +257,7 @@ __device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecPar
 }
 
 template <class Team>
-__device__ __forceinline__ void body_explicit(const Team& tm, const ExecParams& P, const TaskRec& r,
+__device__ __forceinline__ void body_explicit(const Team& tm, const ExecParams& P, const Rec& r,
                                               const GraphEnt& G) {
   const uint32_t n = G.n, S = tm.size();
   uint32_t dsum;
@@ -223,7 +269,7 @@ __device__ __forceinline__ void body_explicit(const Team& tm, const ExecParams& 
 }
 
 template <class Team>
-__device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& P, const TaskRec& r,
+__device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& P, const Rec& r,
                                               const GraphEnt& G) {
   const cptr<ReqDev> rq = as_const(P.reqs) + r.out;
   uint32_t* A = G.data;
@@ -236,7 +282,7 @@ __device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& 
     for (uint64_t e = q.lo + tm.t; e < q.hi; e += S) part += ld_coherent(A + e);
   }
   const uint32_t key = uni(tm.sum(part) ^ r.tid);
-  const uint32_t R = uni(r.rounds);
+  const uint32_t R = r.rounds;
   uint32_t dsum = 0;
   for (uint32_t i = 0; i < r.nreq; ++i) {
     const ReqDev q = rq[i];
@@ -269,9 +315,10 @@ __device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& 
   if (tm.leader()) G.digest[r.tid] = d;
 }
 
+// Run the task at `pos`; v is this lane's dword of its record.
 template <class Team>
-__device__ __forceinline__ void run_body(const Team& tm, const ExecParams& P, uint32_t pos, TaskRec& r) {
-  r = as_const(P.rec)[pos];
+__device__ __forceinline__ void run_body(const Team& tm, const ExecParams& P, uint32_t pos, uint32_t v, Rec& r) {
+  unpack_rec(tm, P, v, r);
   const GraphEnt G = as_const(P.gtab)[r.graph];
   if (P.tstamp && tm.leader()) P.tstamp[2 * pos] = __builtin_amdgcn_s_memrealtime();
   if (G.mode == 1) body_explicit(tm, P, r, G);
@@ -281,24 +328,25 @@ __device__ __forceinline__ void run_body(const Team& tm, const ExecParams& P, ui
 
 // Signal every out-edge of a finished task (COMPLETED_EDGE).
 template <class Team>
-__device__ __forceinline__ void complete_edges(const Team& tm, const ExecParams& P, const TaskRec& r) {
-  vm_drain();  // this lane's payload stores are complete
-  tm.sync();   // ... and so are every other lane's of the team
-  const uint32_t* sp = P.succ_pos + r.succ_beg;
+__device__ __forceinline__ void signal_edge(const ExecParams& P, uint32_t dst) {
   if (P.notify) {
     // COMPLETED_EDGE plus, for the edge that empties a counter, the message
     // that starts the task at its owner: the owner's doorbell is rung only
     // after the decrement has been performed (its old value has returned).
-    for (uint32_t j = tm.t; j < r.nsucc; j += tm.size()) {
-      const uint32_t dst = sp[j];
-      const uint32_t old = __hip_atomic_fetch_sub(P.cnt + dst, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (old == 1u)
-        __hip_atomic_fetch_add(P.bell + P.owner[dst] * kBellStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const uint32_t old = __hip_atomic_fetch_sub(P.cnt + dst, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 1u)
+      __hip_atomic_fetch_add(P.bell + P.owner[dst] * kBellStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   } else {
-    for (uint32_t j = tm.t; j < r.nsucc; j += tm.size())
-      __hip_atomic_fetch_sub(P.cnt + sp[j], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_sub(P.cnt + dst, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+template <class Team>
+__device__ __forceinline__ void complete_edges(const Team& tm, const ExecParams& P, const Rec& r) {
+  vm_drain();  // this lane's payload stores are complete
+  tm.sync();   // ... and so are every other lane's of the team
+  if (tm.t < r.nsucc) signal_edge<Team>(P, r.succ0);
+  for (uint32_t j = tm.t + tm.size(); j < r.nsucc; j += tm.size()) signal_edge<Team>(P, P.succ_pos[r.succ_beg + j]);
 }
 
 // ------------------------------------------------------------ worker loop
@@ -316,13 +364,25 @@ struct WorkerState {
   uint32_t spins;             // consecutive empty polls
   uint64_t last;              // time of the last task taken (realtime counter)
   bool rescan;                // the window must be scanned before waiting
+  uint32_t pf_pos;            // position whose record dword is held in pf_v
+  uint32_t pf_v;              // per lane: dword lane % 32 of that record
 };
 
 __device__ __forceinline__ uint64_t uni64(uint64_t x) {
   return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
 }
 
-__device__ __forceinline__ uint64_t ready_scan(uint32_t lane, const ExecParams& P, const WorkerState& w) {
+// One poll of the ready window: every lane reads one counter and a ballot
+// collects the ready entries.  The record of the oldest unfinished entry,
+// the likeliest next task, is fetched in the same round trip (once per
+// entry), so a task that becomes ready while its worker waits for it starts
+// without another dependent load.
+__device__ __forceinline__ uint64_t ready_scan(uint32_t lane, const ExecParams& P, WorkerState& w) {
+  const uint32_t head = w.wb + w.h;
+  if (head != w.pf_pos) {
+    w.pf_v = rec_dword(P, head, lane);
+    w.pf_pos = head;
+  }
   const uint32_t idx = w.h + lane;
   const bool valid = lane < P.window && idx < w.wcnt && !((w.done >> lane) & 1ull);
   uint32_t c = 1u;
@@ -430,6 +490,8 @@ __device__ __forceinline__ void worker_init(WorkerState& w, const ExecParams& P,
   w.spins = 0;
   w.last = __builtin_amdgcn_s_memrealtime();
   w.rescan = true;
+  w.pf_pos = kExit;
+  w.pf_v = 0;
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exec_wave(ExecParams P) {
@@ -437,18 +499,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   const uint32_t worker = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (worker >= P.nworkers) return;
   const WaveTeam tm{lane};
-  if (P.residency_probe) {
-    residency_probe(P, lane == 0);
-    return;
-  }
   if (P.diag && lane == 0) __hip_atomic_fetch_add(&P.ctrl->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   WorkerState w;
   worker_init(w, P, worker);
   for (;;) {
     const uint32_t pos = next_task(P, w, lane);
     if (pos == kExit) break;
-    TaskRec r;
-    run_body(tm, P, pos, r);
+    const uint32_t v = pos == w.pf_pos ? w.pf_v : rec_dword(P, pos, lane);
+    Rec r;
+    run_body(tm, P, pos, v, r);
     complete_edges(tm, P, r);
     if (P.tstamp && lane == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
   }
@@ -456,22 +515,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 }
 
 // One workgroup per task: wave 0 runs the scheduling state machine and
-// stages the chosen position in LDS; every wave then executes the same
-// sequence of barriers for each task.
-__global__ __launch_bounds__(1024) void k_exec_block(ExecParams P) {
+// stages the chosen position and its record in LDS; every wave then executes
+// the same sequence of barriers for each task.
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exec_block(ExecParams P) {
   __shared__ uint32_t lds[32];
   __shared__ uint32_t cmd;
+  __shared__ uint32_t recl[32];
   const uint32_t worker = blockIdx.x;
   if (worker >= P.nworkers) return;
   const BlockTeam tm{threadIdx.x, blockDim.x, lds};
   const uint32_t lane = threadIdx.x & 63u;
-  if (P.residency_probe) {
-    // every wave stays until the probe is over, so the probe occupies
-    // exactly what a real launch occupies
-    if (threadIdx.x < 64) residency_probe(P, lane == 0);
-    __syncthreads();
-    return;
-  }
   if (P.diag && threadIdx.x == 0)
     __hip_atomic_fetch_add(&P.ctrl->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   WorkerState w;
@@ -479,19 +532,41 @@ __global__ __launch_bounds__(1024) void k_exec_block(ExecParams P) {
   for (;;) {
     if (threadIdx.x < 64) {
       const uint32_t pos = next_task(P, w, lane);
+      if (pos != kExit) {
+        const uint32_t v = pos == w.pf_pos ? w.pf_v : rec_dword(P, pos, lane);
+        if (lane < 32) recl[lane] = v;
+      }
       if (lane == 0) cmd = pos;
     }
     __syncthreads();
     const uint32_t pos = uni(cmd);
+    const uint32_t v = recl[lane & 31u];
     __syncthreads();
     if (pos == kExit) break;
-    TaskRec r;
-    run_body(tm, P, pos, r);
+    Rec r;
+    run_body(tm, P, pos, v, r);
     complete_edges(tm, P, r);
     if (P.tstamp && threadIdx.x == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
     __syncthreads();
   }
   if (P.wprog && threadIdx.x == 0) P.wprog[worker] = w.h;
+}
+
+// Residency probes: the executors' launch bounds and occupancy attributes
+// (so the same number of blocks fits per CU), kept as kernels of their own so
+// that kernel traces of real launches are not mixed with probe launches.
+// Every wave of a block stays until the probe is over, so a probe block
+// occupies what an executor block occupies.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe_wave(ExecParams P) {
+  const uint32_t worker = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (worker >= P.nworkers) return;
+  residency_probe(P, (threadIdx.x & 63u) == 0);
+}
+
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_probe_block(ExecParams P) {
+  if (blockIdx.x >= P.nworkers) return;
+  if (threadIdx.x < 64) residency_probe(P, threadIdx.x == 0);
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void k_reset(ExecParams P) {
@@ -518,8 +593,8 @@ __global__ __launch_bounds__(256) void k_reset(ExecParams P) {
 // from the hipGraph's dependency edges, so no counter is touched.
 __global__ __launch_bounds__(64) void k_one_task(ExecParams P, uint32_t pos) {
   const WaveTeam tm{threadIdx.x};
-  TaskRec r;
-  run_body(tm, P, pos, r);
+  Rec r;
+  run_body(tm, P, pos, rec_dword(P, pos, threadIdx.x), r);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -534,8 +609,14 @@ hipError_t launch_reset(const ExecParams& p, hipStream_t s) {
 
 hipError_t launch_exec(const ExecParams& p, uint32_t mapping, uint32_t wg_waves, uint32_t grid_blocks,
                        hipStream_t s) {
-  if (mapping == 1) hipLaunchKernelGGL(k_exec_wave, dim3(grid_blocks), dim3(256), 0, s, p);
-  else hipLaunchKernelGGL(k_exec_block, dim3(grid_blocks), dim3(wg_waves * 64u), 0, s, p);
+  if (p.residency_probe) {
+    if (mapping == 1) hipLaunchKernelGGL(k_probe_wave, dim3(grid_blocks), dim3(256), 0, s, p);
+    else hipLaunchKernelGGL(k_probe_block, dim3(grid_blocks), dim3(wg_waves * 64u), 0, s, p);
+  } else if (mapping == 1) {
+    hipLaunchKernelGGL(k_exec_wave, dim3(grid_blocks), dim3(256), 0, s, p);
+  } else {
+    hipLaunchKernelGGL(k_exec_block, dim3(grid_blocks), dim3(wg_waves * 64u), 0, s, p);
+  }
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ def test_patterns_ragged(gpu, pattern, n, mapping):
     check_explicit(g, eg, ref, payload_sample=64)
 
 
-@pytest.mark.parametrize("schedule", [tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL])
+@pytest.mark.parametrize("schedule", [tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL, tg.TG_SCHED_SPREAD])
 @pytest.mark.parametrize("workers,window", [(1, 64), (1, 1), (7, 3), (64, 64), (0, 1), (0, 64)])
 @pytest.mark.parametrize("mapping", [1, 2])
 def test_worker_and_window_variants(gpu, mapping, workers, window, schedule):
@@ -91,6 +91,42 @@ def test_random_dags_with_duplicates(gpu, seed):
     g = tg.graph_from_explicit(eg)
     run(g)
     check_explicit(g, eg, ref, payload_sample=50)
+
+
+def _hub_graph(fan: int, n: int = 128, rounds: int = 2) -> wl.ExplicitGraph:
+    """fan sources -> one hub (fan predecessors) -> fan tasks -> one sink
+    (fan predecessors): in- and out-degrees far beyond the edges a task
+    record holds inline, and beyond one wavefront of signalling lanes."""
+    lists = [[] for _ in range(fan)]
+    hub = len(lists)
+    lists.append(list(range(fan)))
+    mid = [len(lists) + i for i in range(fan)]
+    lists += [[hub, i % fan] for i in range(fan)]
+    lists.append(mid)
+    ptr = np.zeros(len(lists) + 1, np.uint64)
+    ptr[1:] = np.cumsum([len(x) for x in lists])
+    flat = np.array([p for x in lists for p in x], np.uint32)
+    return wl.ExplicitGraph(N=len(lists), pred_ptr=ptr, preds=flat, n=n, rounds=rounds, seed=7)
+
+
+@pytest.mark.parametrize("mapping,wg_waves", [(1, 4), (2, 1), (2, 4)])
+@pytest.mark.parametrize("fan", [7, 9, 65, 150])
+def test_high_degree_tasks(gpu, fan, mapping, wg_waves):
+    eg = _hub_graph(fan)
+    ref = oracle_explicit(eg)
+    g = tg.graph_from_explicit(eg)
+    run(g, tg.make_config(mapping=mapping, wg_waves=wg_waves))
+    check_explicit(g, eg, ref, payload_sample=16)
+
+
+def test_random_dags_many_predecessors(gpu):
+    rng = np.random.default_rng(21)
+    eg = wl.random_dag(500, 40, rng, n=64, rounds=3, seed=21, dup=True)
+    ref = oracle_explicit(eg)
+    g = tg.graph_from_explicit(eg)
+    for m in (1, 2):
+        run(g, tg.make_config(mapping=m))
+        check_explicit(g, eg, ref, payload_sample=20)
 
 
 def test_reexecution_is_identical(gpu):
