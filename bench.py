@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-alone", action="store_true", help="skip timing each graph alone")
+    ap.add_argument("--copy-probe-only", action="store_true",
+                    help="run only the copy-bandwidth probe (short runs under a counter profiler)")
     ap.add_argument("--comparator-steps", type=int, default=50, help="timesteps of the comparator sub-graph")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2 (default): the bench line; c3 implicit, c4 4096-graph batch, c5 serving")
@@ -121,13 +123,16 @@ def main():
         return
 
     # ---------------------------------------------------------- probes
-    probes = {
-        "mix_word_rounds_per_s": tg.tg_probe(tg.TG_PROBE_MIX_RATE),
-        "copy_bytes_per_s": tg.tg_probe(tg.TG_PROBE_COPY_BW),
-        "atomics_distinct_per_s": tg.tg_probe(tg.TG_PROBE_ATOMIC_DISTINCT),
-        "atomics_contended_per_s": tg.tg_probe(tg.TG_PROBE_ATOMIC_CONTENDED),
-        "launches_per_s": tg.tg_probe(tg.TG_PROBE_LAUNCH_RATE),
-    }
+    if args.copy_probe_only:
+        probes = {"copy_bytes_per_s": tg.tg_probe(tg.TG_PROBE_COPY_BW)}
+    else:
+        probes = {
+            "mix_word_rounds_per_s": tg.tg_probe(tg.TG_PROBE_MIX_RATE),
+            "copy_bytes_per_s": tg.tg_probe(tg.TG_PROBE_COPY_BW),
+            "atomics_distinct_per_s": tg.tg_probe(tg.TG_PROBE_ATOMIC_DISTINCT),
+            "atomics_contended_per_s": tg.tg_probe(tg.TG_PROBE_ATOMIC_CONTENDED),
+            "launches_per_s": tg.tg_probe(tg.TG_PROBE_LAUNCH_RATE),
+        }
     log(f"probes: {probes}")
 
     # --------------------------------------------------------- workload
