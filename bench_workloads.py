@@ -68,11 +68,24 @@ def run_c4(args, stream):
     N = sum(eg.N for eg in egs)
     U = sum(eg.N * eg.n * eg.rounds for eg in egs)
     log(f"c4: {len(gs)} graphs, {N} tasks, {U:.3e} word-rounds; host build {time.perf_counter() - t0:.0f} s")
+    # launch shape and schedule: autotuned on a seeded sample of 256 graphs
+    # (re-planning the full batch for every candidate would take minutes)
+    tune = None
+    if not args.no_tune:
+        rng = np.random.default_rng(7)
+        sub = rng.choice(len(gs), size=min(256, len(gs)), replace=False)
+        bs = tg.tg_batch_create([gs[i].handle for i in sub])
+        tune, tms = tg.tg_batch_autotune(bs, reps=1)
+        tg.tg_batch_destroy(bs)
+        log(f"c4: autotuned on {len(sub)} graphs: {tune} ({tms:.1f} ms)")
+    cfg = None if tune is None else tg.make_config(
+        mapping=tune["mapping"], workers=tune["workers"], wg_waves=tune["wg_waves"], notify=tune["notify"],
+        schedule=tune["schedule"])
     t1 = time.perf_counter()
-    b = tg.tg_batch_create([g.handle for g in gs])
+    b = tg.tg_batch_create([g.handle for g in gs], cfg)
     layout_s = time.perf_counter() - t1
-    bcfg, _ = tg.tg_batch_info(b)
-    log(f"c4: layout {layout_s:.1f} s, launch {bcfg}")
+    bcfg, _, btimes = tg.tg_batch_info(b, with_times=True)
+    log(f"c4: layout {layout_s:.1f} s ({btimes}), launch {bcfg}")
     for _ in range(args.warmup):
         tg.tg_batch_execute(b, stream)
     tg.tg_batch_wait(b)
@@ -103,6 +116,7 @@ def run_c4(args, stream):
                  {"workload": f"{len(gs)} independent graphs: W~U[8,512], T~U[8,256], five patterns, "
                               "n~U{64..1024}, R~LogNormal(ln 64, 1); one persistent launch", "launch": bcfg},
                  tasks=N, word_rounds=U, word_rounds_per_s=U / (ms * 1e-3), layout_s=layout_s,
+                 layout_ms=btimes, tuned_on_sample=tune,
                  parity_16_graphs=parity,
                  one_launch_per_graph={"sample_graphs": len(sample), "tasks": seq_tasks,
                                        "tasks_per_s": seq_tasks / (seq_ms * 1e-3)})

@@ -332,7 +332,15 @@ tg_status tg_server_submit(tg_server srv, tg_graph g, uint64_t* ticket);
  * times (ns) of submission, admission and completion.  Each ticket is waited
  * for once. */
 tg_status tg_server_wait(tg_server srv, uint64_t ticket, uint64_t* submit_ns, uint64_t* admit_ns, uint64_t* done_ns);
-tg_status tg_server_stats(tg_server srv, uint64_t* tasks_done, uint64_t* launches, uint64_t* peak_bytes);
+/* Totals so far: tasks finished, launches, peak admitted bytes; phase_ms (7
+ * doubles, may be NULL): host time of the serving thread building layouts
+ * (device buffers, schedule, upload), issuing launches and retiring finished
+ * launches (results copied back, buffers released); the device time of all
+ * launches (HIP events around each); and, inside the host time, the time
+ * spent planning schedules and records, in the device-memory allocator
+ * (hooks or hipMalloc/hipFree) and in host-device copies. */
+tg_status tg_server_stats(tg_server srv, uint64_t* tasks_done, uint64_t* launches, uint64_t* peak_bytes,
+                          double* phase_ms);
 /* Finishes all submitted work, then stops the server thread. */
 tg_status tg_server_destroy(tg_server srv);
 

@@ -63,6 +63,14 @@ void* (*g_alloc)(size_t, void*) = nullptr;
 void (*g_free)(void*, void*) = nullptr;
 void* g_ctx = nullptr;
 std::atomic<long> g_live{0};
+// host time this thread spent in allocator hooks and in host-device copies
+thread_local uint64_t t_hook_ns = 0, t_copy_ns = 0;
+
+uint64_t steady_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -76,8 +84,10 @@ struct DevBuf {
   ~DevBuf() { release(); }
   void release() {
     if (p) {
+      const uint64_t t0 = steady_ns();
       if (ff) ff(p, ctx);
       else (void)hipFree(p);
+      t_hook_ns += steady_ns() - t0;
       g_live--;
     }
     p = nullptr;
@@ -89,11 +99,14 @@ struct DevBuf {
     fa = g_alloc;
     ff = g_free;
     ctx = g_ctx;
+    const uint64_t t0 = steady_ns();
     if (fa) {
       p = fa(b, ctx);
+      t_hook_ns += steady_ns() - t0;
       if (!p) return fail(TG_ENOMEM, "device allocation of %zu bytes failed (allocator hook)", b);
     } else {
       hipError_t e = hipMalloc(&p, b);
+      t_hook_ns += steady_ns() - t0;
       if (e != hipSuccess) {
         p = nullptr;
         (void)hipGetLastError();
@@ -122,7 +135,9 @@ template <class T>
 tg_status upload(DevBuf& d, const std::vector<T>& h) {
   tg_status s = d.alloc(h.size() * sizeof(T));
   if (s != TG_OK) return s;
+  const uint64_t t0 = steady_ns();
   if (!h.empty()) HIPCHK(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  t_copy_ns += steady_ns() - t0;
   return TG_OK;
 }
 
@@ -622,13 +637,11 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
   H.pos_of.assign(gs.size(), {});
   for (uint32_t gi = 0; gi < gs.size(); ++gi) H.pos_of[gi].assign(gs[gi]->N(), 0);
   for (uint32_t pos = 0; pos < N; ++pos) H.pos_of[at_pos[pos] >> 32][(uint32_t)at_pos[pos]] = pos;
-  // records and edge arrays in position order
-  H.rec.assign(N, TaskRec());
-  H.pred_addr.clear();
-  H.pred_addr.reserve(npred_tot);
-  H.succ_pos.clear();
-  H.succ_pos.reserve(nsucc_tot);
-  H.indeg.assign(N, 0);
+  // records by position, edge arrays (every element is written below)
+  H.rec.resize(N);
+  H.pred_addr.resize(npred_tot);
+  H.succ_pos.resize(nsucc_tot);
+  H.indeg.resize(N);
   std::vector<uint64_t> req_base(gs.size(), 0);
   {
     uint64_t rb = 0;
@@ -637,36 +650,71 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
       if (gs[gi]->mode == TG_IMPLICIT) rb += gs[gi]->reqs.size();
     }
   }
-  for (uint32_t pos = 0; pos < N; ++pos) {
-    const uint32_t gi = (uint32_t)(at_pos[pos] >> 32), v = (uint32_t)at_pos[pos];
-    const tg_graph g = gs[gi];
-    TaskRec& r = H.rec[pos];
-    memset(&r, 0, sizeof(r));
-    r.tid = v;
-    r.graph = gi;
-    r.rounds = g->rounds[v];
-    r.npred = (uint32_t)(g->dpred_ptr[v + 1] - g->dpred_ptr[v]);
-    r.pred_beg = (uint32_t)H.pred_addr.size();
-    if (g->mode == TG_EXPLICIT) {
-      const uint64_t base = (uint64_t)g->payload.p;
-      r.out = base + (uint64_t)v * g->n * 4ull;
-      for (uint64_t j = g->dpred_ptr[v]; j < g->dpred_ptr[v + 1]; ++j) {
-        const uint64_t a = base + (uint64_t)g->dpred[j] * g->n * 4ull;
-        if (j - g->dpred_ptr[v] < tg::kInPred) r.pred[j - g->dpred_ptr[v]] = a;
-        H.pred_addr.push_back(a);
+  // records in graph order (each graph's arrays are read sequentially); a
+  // record is stored at its task's position, and its predecessor and
+  // successor lists are slices of pred_addr / succ_pos in graph order.
+  // Large layouts split the tasks over a few threads.
+  std::vector<uint64_t> gfirst(gs.size() + 1, 0), pbase(gs.size(), 0), sbase(gs.size(), 0);
+  {
+    uint64_t pb = 0, sb = 0;
+    for (uint32_t gi = 0; gi < gs.size(); ++gi) {
+      gfirst[gi + 1] = gfirst[gi] + gs[gi]->N();
+      pbase[gi] = pb;
+      sbase[gi] = sb;
+      if (gs[gi]->mode == TG_EXPLICIT) pb += gs[gi]->dpred.size();
+      sb += gs[gi]->succ.size();
+    }
+  }
+  auto build_range = [&](uint64_t lo, uint64_t hi) {  // global task indices [lo, hi)
+    uint32_t gi = (uint32_t)(std::upper_bound(gfirst.begin(), gfirst.end(), lo) - gfirst.begin()) - 1;
+    for (uint64_t x = lo; x < hi; ++gi) {
+      const tg_graph g = gs[gi];
+      const std::vector<uint32_t>& pos = H.pos_of[gi];
+      const bool expl = g->mode == TG_EXPLICIT;
+      const uint64_t base = expl ? (uint64_t)g->payload.p : 0, wbytes = (uint64_t)g->n * 4ull;
+      const uint64_t pb = pbase[gi], sb = sbase[gi];
+      const uint32_t vend = (uint32_t)(std::min(hi, gfirst[gi + 1]) - gfirst[gi]);
+      for (uint32_t v = (uint32_t)(x - gfirst[gi]); v < vend; ++v, ++x) {
+        TaskRec r;
+        memset(&r, 0, sizeof(r));
+        r.tid = v;
+        r.graph = gi;
+        r.rounds = g->rounds[v];
+        const uint64_t d0 = g->dpred_ptr[v], d1 = g->dpred_ptr[v + 1];
+        r.npred = (uint32_t)(d1 - d0);
+        if (expl) {
+          r.out = base + (uint64_t)v * wbytes;
+          r.pred_beg = (uint32_t)(pb + d0);
+          for (uint64_t j = d0; j < d1; ++j) {
+            const uint64_t addr = base + (uint64_t)g->dpred[j] * wbytes;
+            if (j - d0 < tg::kInPred) r.pred[j - d0] = addr;
+            H.pred_addr[pb + j] = addr;
+          }
+        } else {
+          r.out = req_base[gi] + g->req_ptr[v];
+          r.nreq = (uint32_t)(g->req_ptr[v + 1] - g->req_ptr[v]);
+        }
+        const uint64_t s0 = g->succ_ptr[v], s1 = g->succ_ptr[v + 1];
+        r.succ_beg = (uint32_t)(sb + s0);
+        r.nsucc = (uint32_t)(s1 - s0);
+        for (uint64_t j = s0; j < s1; ++j) {
+          const uint32_t sp = pos[g->succ[j]];
+          if (j - s0 < tg::kInSucc) r.succ[j - s0] = sp;
+          H.succ_pos[sb + j] = sp;
+        }
+        H.rec[pos[v]] = r;
+        H.indeg[pos[v]] = r.npred;
       }
-    } else {
-      r.out = req_base[gi] + g->req_ptr[v];
-      r.nreq = (uint32_t)(g->req_ptr[v + 1] - g->req_ptr[v]);
     }
-    r.succ_beg = (uint32_t)H.succ_pos.size();
-    r.nsucc = (uint32_t)(g->succ_ptr[v + 1] - g->succ_ptr[v]);
-    for (uint64_t j = g->succ_ptr[v]; j < g->succ_ptr[v + 1]; ++j) {
-      const uint32_t sp = H.pos_of[gi][g->succ[j]];
-      if (j - g->succ_ptr[v] < tg::kInSucc) r.succ[j - g->succ_ptr[v]] = sp;
-      H.succ_pos.push_back(sp);
-    }
-    H.indeg[pos] = r.npred;
+  };
+  const uint32_t nthreads = N >= (1u << 17) ? std::max(1u, std::min(8u, std::thread::hardware_concurrency())) : 1u;
+  if (nthreads <= 1) {
+    build_range(0, N);
+  } else {
+    std::vector<std::thread> pool;
+    for (uint32_t t = 0; t < nthreads; ++t)
+      pool.emplace_back(build_range, (uint64_t)N * t / nthreads, (uint64_t)N * (t + 1) / nthreads);
+    for (auto& th : pool) th.join();
   }
   H.gtab.assign(gs.size(), GraphEnt());
   H.reqs.clear();
@@ -696,6 +744,7 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
 }
 
 tg_status ensure_device(tg_graph g);
+tg_status ensure_events(tg_graph g);
 
 // Schedule and upload the layout of a set of finalised graphs.
 // Schedules already computed for a set of graphs, by (workers, schedule):
@@ -708,8 +757,11 @@ struct PlanCache {
   std::map<std::pair<uint32_t, uint32_t>, std::shared_ptr<const Plan>> m;
 };
 
+// keep_host: keep the host copy of the task records in the layout (needed
+// to re-set mix rounds later).  Without it the records are built in a
+// per-thread host layout whose buffers are reused from call to call.
 tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::unique_ptr<Layout>& out,
-                       PlanCache* cache = nullptr) {
+                       PlanCache* cache = nullptr, bool keep_host = true) {
   const auto t_build = std::chrono::steady_clock::now();
   tg_status s = check_config(cfg);
   if (s != TG_OK) return s;
@@ -720,7 +772,9 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   const uint64_t cap_workers = cap32;
   uint64_t nw = cfg.workers ? cfg.workers : cap_workers;
   if (nw > cap_workers) nw = cap_workers;  // every worker must be co-resident
-  HostLayout H;
+  static thread_local HostLayout tl_host;
+  HostLayout local;
+  HostLayout& H = keep_host ? local : tl_host;
   const auto t_plan = std::chrono::steady_clock::now();
   const std::pair<uint32_t, uint32_t> key((uint32_t)nw, cfg.schedule);
   const Plan* reuse = nullptr;
@@ -743,7 +797,7 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   L->pos_of = std::move(H.pos_of);
   const uint32_t N = H.N;
   if ((s = upload(L->rec, H.rec)) != TG_OK) return s;
-  L->rec_host = std::move(H.rec);
+  if (keep_host) L->rec_host = std::move(H.rec);
   if ((s = upload(L->pred_addr, H.pred_addr)) != TG_OK) return s;
   if ((s = upload(L->succ_pos, H.succ_pos)) != TG_OK) return s;
   if ((s = upload(L->indeg, H.indeg)) != TG_OK) return s;
@@ -1079,8 +1133,14 @@ tg_status ensure_device(tg_graph g) {
   }
   if (!g->digest.p) {
     if ((s = g->digest.alloc((size_t)N * 4)) != TG_OK) return s;
-    HIPCHK(hipMemset(g->digest.p, 0, (size_t)N * 4));
+    HIPCHK(hipMemsetAsync(g->digest.p, 0, (size_t)N * 4, nullptr));
   }
+  return TG_OK;  // the caller fences the null stream once for all its graphs
+}
+
+// Timing events of a graph's own launches, created at its first one (graphs
+// that only ever run inside batches or the server never need them).
+tg_status ensure_events(tg_graph g) {
   if (!g->ev0) HIPCHK(hipEventCreate(&g->ev0));
   if (!g->ev1) HIPCHK(hipEventCreate(&g->ev1));
   if (!g->evk) HIPCHK(hipEventCreate(&g->evk));
@@ -1089,7 +1149,7 @@ tg_status ensure_device(tg_graph g) {
       HIPCHK(hipEventCreate(&g->rk0[i]));
       HIPCHK(hipEventCreate(&g->rk1[i]));
     }
-  return null_stream_fence();
+  return TG_OK;
 }
 
 }  // namespace
@@ -1288,6 +1348,7 @@ tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfgp, void* stream)
     if ((s = build_layout(gs, cfg, g->solo, g->plans.get())) != TG_OK) return s;
   }
   hipStream_t st = (hipStream_t)stream;
+  if ((s = ensure_events(g)) != TG_OK) return s;
   HIPCHK(hipEventRecord(g->ev0, st));
   std::vector<tg_graph> gs{g};
   const uint32_t slot = (uint32_t)(g->launches % tg_graph_s::kRing);
@@ -1450,6 +1511,9 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
   if (s != TG_OK) return s;
   // candidate launch configurations
   std::vector<tg_exec_config> cand;
+  DevInfo di;
+  if ((s = device_info(di)) != TG_OK) return s;
+  const uint32_t cus = (uint32_t)di.cus;
   uint32_t rw = 0, rg2 = 0, rg4 = 0;
   if ((s = resident_workers(TG_MAP_WAVE, 4, &rw)) != TG_OK) return s;
   if ((s = resident_workers(TG_MAP_WORKGROUP, 2, &rg2)) != TG_OK) return s;
@@ -1469,6 +1533,8 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
       if (w) shapes.push_back(mk(TG_MAP_WAVE, w, 0, 0));
     shapes.push_back(mk(TG_MAP_WORKGROUP, rg2, 2, 0));
     shapes.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
+    // one large workgroup per CU: for graphs with few, large tasks
+    for (uint32_t ww : {8u, 16u}) shapes.push_back(mk(TG_MAP_WORKGROUP, cus, ww, 0));
     for (auto c : shapes) {
       c.schedule = sch;
       cand.push_back(c);
@@ -1814,6 +1880,7 @@ tg_status tg_graph_execute_comparator(tg_graph g, uint32_t mode, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const uint32_t N = g->N();
   ExecParams P = L.params;
+  if ((s = ensure_events(g)) != TG_OK) return s;
   HIPCHK(hipEventRecord(g->ev0, st));
   if (g->mode == TG_IMPLICIT) {
     HIPCHK(tg_launch_init_data(g->data.as<uint32_t>(), g->space, sm64_host(g->seed ^ (2ull << 32)), st));
@@ -1870,16 +1937,23 @@ struct tg_server_s {
     tg_status status = TG_OK;
     bool done = false;
   };
+  // A launch slot: one stream, one layout at a time, and a builder thread
+  // that compiles and launches the batch assigned to it, so that up to one
+  // batch per slot is planned on the host at once.
   struct Slot {
+    enum State { kIdle, kBuilding, kRunning };
     std::unique_ptr<Layout> lay;
     std::vector<Req*> reqs;
     hipStream_t st = nullptr;
-    hipEvent_t ev = nullptr;
-    bool busy = false;
+    hipEvent_t ev = nullptr, ev0 = nullptr;  // end of the launch; its start (timing)
+    State state = kIdle;
+    bool assigned = false;  // a batch waits for the builder
+    std::condition_variable cv;
+    std::thread th;
   };
   uint64_t budget = 0, in_use = 0, next_ticket = 1;
   uint32_t workers = 0, max_batch = 64;
-  std::vector<Slot> slots;
+  std::vector<std::unique_ptr<Slot>> slots;
   std::deque<Req*> pending;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
   std::mutex mu;
@@ -1887,6 +1961,10 @@ struct tg_server_s {
   std::thread th;
   bool stop = false;
   uint64_t tasks_done = 0, launches = 0, peak_in_use = 0;
+  // host time of the serving thread by phase, and executor time on the device
+  double build_ms = 0, launch_ms = 0, retire_ms = 0, gpu_ms = 0;
+  // parts of it: schedules and records, allocator hooks, host-device copies
+  double plan_ms = 0, hook_ms = 0, copy_ms = 0;
 };
 
 namespace {
@@ -1920,34 +1998,95 @@ void release_graph_device(tg_graph g) {
   g->released = true;
 }
 
+// Builder thread of one slot: compile the assigned batch into a layout and
+// launch it on the slot's stream.
+void slot_builder(tg_server srv, tg_server_s::Slot* sl) {
+  std::unique_lock<std::mutex> lk(srv->mu);
+  for (;;) {
+    sl->cv.wait(lk, [&] { return sl->assigned || srv->stop; });
+    if (!sl->assigned) return;  // stopping
+    sl->assigned = false;
+    const std::vector<tg_server_s::Req*> batch = sl->reqs;
+    lk.unlock();
+    std::vector<tg_graph> gs;
+    for (auto* r : batch) gs.push_back(r->g);
+    Config cfg;
+    cfg.workers = srv->workers;
+    const uint64_t h0 = t_hook_ns, c0 = t_copy_ns;
+    const uint64_t t0 = now_ns();
+    tg_status st = build_layout(gs, cfg, sl->lay, nullptr, false);
+    const uint64_t t1 = now_ns();
+    if (st == TG_OK && hipEventRecord(sl->ev0, sl->st) != hipSuccess) st = TG_EDEVICE;
+    if (st == TG_OK) st = launch_layout(*sl->lay, cfg, gs, sl->st);
+    if (st == TG_OK && hipEventRecord(sl->ev, sl->st) != hipSuccess) st = TG_EDEVICE;
+    const uint64_t t2 = now_ns();
+    if (st != TG_OK)
+      for (auto* r : batch) release_graph_device(r->g);
+    lk.lock();
+    srv->build_ms += (t1 - t0) * 1e-6;
+    srv->launch_ms += (t2 - t1) * 1e-6;
+    if (sl->lay) srv->plan_ms += sl->lay->plan_ms;
+    srv->hook_ms += (t_hook_ns - h0) * 1e-6;
+    srv->copy_ms += (t_copy_ns - c0) * 1e-6;
+    if (st != TG_OK) {
+      for (auto* r : batch) {
+        srv->in_use -= r->bytes;
+        r->status = st;
+        r->t_done = now_ns();
+        r->done = true;
+      }
+      sl->lay.reset();
+      sl->reqs.clear();
+      sl->state = tg_server_s::Slot::kIdle;
+      srv->cv_done.notify_all();
+    } else {
+      sl->state = tg_server_s::Slot::kRunning;
+      srv->launches++;
+    }
+    srv->cv_work.notify_all();
+  }
+}
+
+// Serving thread: retires finished launches and admits waiting requests,
+// by memory budget, into idle slots (their builders do the rest).
 void server_loop(tg_server srv) {
   std::unique_lock<std::mutex> lk(srv->mu);
   while (!srv->stop) {
-    bool progressed = false, busy = false;
+    bool progressed = false, running = false;
     // retire finished launches
-    for (auto& sl : srv->slots) {
-      if (!sl.busy) continue;
-      busy = true;
+    for (auto& slp : srv->slots) {
+      tg_server_s::Slot& sl = *slp;
+      if (sl.state != tg_server_s::Slot::kRunning) continue;
+      running = true;
       if (hipEventQuery(sl.ev) != hipSuccess) continue;
+      const uint64_t t = now_ns(), h0 = t_hook_ns, c0 = t_copy_ns;
+      float gms = 0;
+      if (hipEventElapsedTime(&gms, sl.ev0, sl.ev) == hipSuccess) srv->gpu_ms += gms;
       tg_status st = check_abort(sl.lay.get());
-      const uint64_t t = now_ns();
-      for (auto* r : sl.reqs) {
-        release_graph_device(r->g);
+      std::vector<tg_server_s::Req*> done;
+      done.swap(sl.reqs);
+      lk.unlock();
+      for (auto* r : done) release_graph_device(r->g);
+      sl.lay.reset();
+      lk.lock();
+      for (auto* r : done) {
         srv->in_use -= r->bytes;
         srv->tasks_done += r->g->N();
         r->status = st;
         r->t_done = t;
         r->done = true;
       }
-      sl.lay.reset();
-      sl.reqs.clear();
-      sl.busy = false;
+      sl.state = tg_server_s::Slot::kIdle;
+      srv->retire_ms += (now_ns() - t) * 1e-6;
+      srv->hook_ms += (t_hook_ns - h0) * 1e-6;
+      srv->copy_ms += (t_copy_ns - c0) * 1e-6;
       progressed = true;
       srv->cv_done.notify_all();
     }
-    // admit waiting requests into free slots
-    for (auto& sl : srv->slots) {
-      if (sl.busy || srv->pending.empty()) continue;
+    // admit waiting requests into idle slots
+    for (auto& slp : srv->slots) {
+      tg_server_s::Slot& sl = *slp;
+      if (sl.state != tg_server_s::Slot::kIdle || srv->pending.empty()) continue;
       std::vector<tg_server_s::Req*> batch;
       uint64_t add = 0;
       while (!srv->pending.empty() && batch.size() < srv->max_batch) {
@@ -1970,39 +2109,19 @@ void server_loop(tg_server srv) {
       if (srv->in_use > srv->peak_in_use) srv->peak_in_use = srv->in_use;
       const uint64_t t = now_ns();
       for (auto* r : batch) r->t_admit = t;
-      lk.unlock();
-      std::vector<tg_graph> gs;
-      for (auto* r : batch) gs.push_back(r->g);
-      Config cfg;
-      cfg.workers = srv->workers;
-      tg_status st = build_layout(gs, cfg, sl.lay);
-      if (st == TG_OK) st = launch_layout(*sl.lay, cfg, gs, sl.st);
-      if (st == TG_OK && hipEventRecord(sl.ev, sl.st) != hipSuccess) st = TG_EDEVICE;
-      lk.lock();
-      if (st != TG_OK) {
-        for (auto* r : batch) {
-          release_graph_device(r->g);
-          srv->in_use -= r->bytes;
-          r->status = st;
-          r->t_done = now_ns();
-          r->done = true;
-        }
-        sl.lay.reset();
-        srv->cv_done.notify_all();
-      } else {
-        sl.reqs = batch;
-        sl.busy = true;
-        srv->launches++;
-        busy = true;
-      }
+      sl.reqs = batch;
+      sl.state = tg_server_s::Slot::kBuilding;
+      sl.assigned = true;
+      sl.cv.notify_one();
       progressed = true;
     }
-    if (!busy && srv->pending.empty()) {
-      srv->cv_work.wait(lk);
-    } else if (!progressed) {
+    if (progressed) continue;
+    if (running) {
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(20));
       lk.lock();
+    } else {
+      srv->cv_work.wait(lk);  // woken by submissions, builders and destroy
     }
   }
 }
@@ -2024,12 +2143,15 @@ tg_status tg_server_create(tg_server* out, uint64_t budget_bytes, uint32_t slots
   srv->budget = budget_bytes;
   srv->workers = resident / slots;  // concurrent launches stay co-resident together
   srv->max_batch = max_batch ? max_batch : 64;
-  srv->slots.resize(slots);
-  for (auto& sl : srv->slots) {
-    HIPCHK(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+  for (uint32_t i = 0; i < slots; ++i) {
+    auto sl = std::make_unique<tg_server_s::Slot>();
+    HIPCHK(hipStreamCreateWithFlags(&sl->st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreate(&sl->ev));
+    HIPCHK(hipEventCreate(&sl->ev0));
+    srv->slots.push_back(std::move(sl));
   }
   tg_server srvp = srv.release();
+  for (auto& sl : srvp->slots) sl->th = std::thread(slot_builder, srvp, sl.get());
   srvp->th = std::thread(server_loop, srvp);
   *out = srvp;
   return TG_OK;
@@ -2068,12 +2190,22 @@ tg_status tg_server_wait(tg_server srv, uint64_t ticket, uint64_t* submit_ns, ui
   return TG_OK;
 }
 
-tg_status tg_server_stats(tg_server srv, uint64_t* tasks_done, uint64_t* launches, uint64_t* peak_bytes) {
+tg_status tg_server_stats(tg_server srv, uint64_t* tasks_done, uint64_t* launches, uint64_t* peak_bytes,
+                          double* phase_ms) {
   if (!srv) return fail(TG_EINVAL, "server is NULL");
   std::lock_guard<std::mutex> lk(srv->mu);
   if (tasks_done) *tasks_done = srv->tasks_done;
   if (launches) *launches = srv->launches;
   if (peak_bytes) *peak_bytes = srv->peak_in_use;
+  if (phase_ms) {
+    phase_ms[0] = srv->build_ms;
+    phase_ms[1] = srv->launch_ms;
+    phase_ms[2] = srv->retire_ms;
+    phase_ms[3] = srv->gpu_ms;
+    phase_ms[4] = srv->plan_ms;
+    phase_ms[5] = srv->hook_ms;
+    phase_ms[6] = srv->copy_ms;
+  }
   return TG_OK;
 }
 
@@ -2085,16 +2217,19 @@ tg_status tg_server_destroy(tg_server srv) {
     srv->cv_done.wait(lk, [&] {
       if (!srv->pending.empty()) return false;
       for (auto& sl : srv->slots)
-        if (sl.busy) return false;
+        if (sl->state != tg_server_s::Slot::kIdle) return false;
       return true;
     });
     srv->stop = true;
     srv->cv_work.notify_all();
+    for (auto& sl : srv->slots) sl->cv.notify_all();
   }
   srv->th.join();
   for (auto& sl : srv->slots) {
-    if (sl.ev) (void)hipEventDestroy(sl.ev);
-    if (sl.st) (void)hipStreamDestroy(sl.st);
+    sl->th.join();
+    if (sl->ev) (void)hipEventDestroy(sl->ev);
+    if (sl->ev0) (void)hipEventDestroy(sl->ev0);
+    if (sl->st) (void)hipStreamDestroy(sl->st);
   }
   delete srv;
   return TG_OK;

@@ -268,6 +268,17 @@ __device__ __forceinline__ void body_explicit(const Team& tm, const ExecParams& 
   if (tm.leader()) G.digest[r.tid] = d;
 }
 
+// Elements t, t + S, t + 2S, t + 3S of p[0, len) (0 past the end).
+__device__ __forceinline__ u32x4 load4(const uint32_t* p, uint32_t t, uint32_t S, uint64_t len) {
+  u32x4 x;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t o = t + (uint64_t)k * S;
+    x[k] = o < len ? ld_coherent(p + o) : 0u;
+  }
+  return x;
+}
+
 template <class Team>
 __device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& P, const Rec& r,
                                               const GraphEnt& G) {
@@ -290,25 +301,22 @@ __device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& 
     const uint64_t len = q.hi - q.lo;
     uint32_t* const a = A + q.lo;
     // four elements per lane per chunk; the chunk loop and the mix-round
-    // loop are wave-uniform, lanes past the end skip loads and stores
-    for (uint64_t base = 0; base < len; base += 4 * (uint64_t)S) {
-      u32x4 x;
-      bool v[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint64_t o = base + tm.t + (uint64_t)k * S;
-        v[k] = o < len;
-        x[k] = v[k] ? ld_coherent(a + o) : 0u;
-      }
+    // loop are wave-uniform, lanes past the end skip loads and stores; the
+    // next chunk's loads are issued before this chunk's mix
+    const uint64_t step = 4 * (uint64_t)S;
+    u32x4 x = load4(a, tm.t, S, len);
+    for (uint64_t base = 0; base < len; base += step) {
+      const u32x4 y = base + step < len ? load4(a + base + step, tm.t, S, len - base - step) : u32x4{0, 0, 0, 0};
       x = mix_rounds<u32x4>(x ^ key, R);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const uint64_t o = base + tm.t + (uint64_t)k * S;
-        if (v[k]) {
+        if (o < len) {
           st_coherent(a + o, x[k]);
           dsum += x[k] * (2u * (q.rw_base + (uint32_t)o) + 1u);
         }
       }
+      x = y;
     }
   }
   const uint32_t d = tm.sum(dsum);

@@ -116,7 +116,7 @@ def load() -> ctypes.CDLL:
         "tg_server_create": (i32, [ctypes.POINTER(G), u64, u32, u32]),
         "tg_server_submit": (i32, [G, G, P]),
         "tg_server_wait": (i32, [G, u64, P, P, P]),
-        "tg_server_stats": (i32, [G, P, P, P]),
+        "tg_server_stats": (i32, [G, P, P, P, P]),
         "tg_server_destroy": (i32, [G]),
         "tg_batch_kernel_times": (i32, [G, P, u32, P]),
         "tg_batch_set_rounds": (i32, [G, u32]),
@@ -519,8 +519,11 @@ def tg_server_wait(srv, ticket: int):
 
 def tg_server_stats(srv):
     a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
-    _check(load().tg_server_stats(srv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "tg_server_stats")
-    return {"tasks_done": a.value, "launches": b.value, "peak_bytes": c.value}
+    ph = (ctypes.c_double * 7)()
+    _check(load().tg_server_stats(srv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ph), "tg_server_stats")
+    return {"tasks_done": a.value, "launches": b.value, "peak_bytes": c.value,
+            "host_build_ms": ph[0], "host_launch_ms": ph[1], "host_retire_ms": ph[2], "device_ms": ph[3],
+            "host_plan_ms": ph[4], "host_alloc_ms": ph[5], "host_copy_ms": ph[6]}
 
 
 def tg_server_destroy(srv):

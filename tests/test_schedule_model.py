@@ -113,3 +113,15 @@ def test_emulator_rejects_bad_arguments(tglib):
     assert st == tg.TG_EINVAL
     st, _ = tg.tg_graph_emulate_schedule(g.handle, 4, 8, schedule=4)
     assert st == tg.TG_EINVAL
+
+
+def test_large_layout_built_in_parallel(tglib):
+    """Layouts of at least 2^17 tasks build their records on several host
+    threads; two graphs of that size together still run exactly once and in
+    dependence order in the worker-loop model."""
+    egs = [wl.pattern_graph("stencil", 512, 200, seed=1, n=64), wl.pattern_graph("random", 300, 200, seed=2, n=64)]
+    gs = [tg.graph_from_explicit(eg) for eg in egs]
+    st, pairs, _, _ = tg.tg_emulate_schedule([g.handle for g in gs], 2048, 64, seed=3)
+    assert st == tg.TG_OK
+    assert sum(eg.N for eg in egs) >= 1 << 17
+    _check_batch_order(egs, pairs)
