@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 W, T, NWORDS = 1024, 1000, 256
-SWEEP_ROUNDS = (0, 16, 64, 256, 1024, 4096)
+SWEEP_ROUNDS = (0, 4, 8, 16, 64, 256, 1024, 4096)
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 
 

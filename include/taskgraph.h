@@ -109,7 +109,11 @@ typedef struct {
  *                  before sorting and dealing, so graphs of different depths
  *                  advance side by side; TG_SCHED_LIST simulates the workers
  *                  with estimated task costs and starts ready tasks
- *                  longest-remaining-path first. */
+ *                  longest-remaining-path first; TG_SCHED_COLUMN gives task i
+ *                  of every level of a graph to the same worker (graphs packed
+ *                  side by side by width) and orders each worker's list by the
+ *                  stretched level, so columns stay on one worker and shallow
+ *                  graphs fill the gaps of deep ones. */
 typedef struct {
   uint32_t mapping;
   uint32_t workers;
@@ -124,7 +128,7 @@ typedef struct {
 } tg_exec_config;
 
 enum { TG_MAP_WAVE = 1, TG_MAP_WORKGROUP = 2 };
-enum { TG_SCHED_LIST = 1, TG_SCHED_LEVEL = 2, TG_SCHED_SPREAD = 3 };
+enum { TG_SCHED_LIST = 1, TG_SCHED_LEVEL = 2, TG_SCHED_SPREAD = 3, TG_SCHED_COLUMN = 4 };
 
 /* ------------------------------------------------------------- status */
 const char* tg_status_str(tg_status s);

@@ -192,7 +192,7 @@ tg_status check_config(const Config& c) {
   if (c.window < 1 || c.window > 64) return fail(TG_EINVAL, "window must be in [1, 64]");
   if (c.idle_sleep < 1 || c.idle_sleep > 64) return fail(TG_EINVAL, "idle_sleep must be in [1, 64]");
   if (c.wg_waves < 1 || c.wg_waves > 16) return fail(TG_EINVAL, "wg_waves must be in [1, 16]");
-  if (c.schedule < TG_SCHED_LIST || c.schedule > TG_SCHED_SPREAD) return fail(TG_EINVAL, "schedule must be 1, 2 or 3");
+  if (c.schedule < TG_SCHED_LIST || c.schedule > TG_SCHED_COLUMN) return fail(TG_EINVAL, "schedule must be 1..4");
   return TG_OK;
 }
 
@@ -455,6 +455,63 @@ void schedule_spread(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw, s
   for (uint64_t si = 0; si < N; ++si) seq[off[si % nw] + si / nw] = sorted[si];
 }
 
+// Column order: task i of level l of a graph goes to worker (o_g + i) mod nw,
+// where o_g packs the graphs side by side by their widest level, and every
+// worker's list is sorted by the spread key (l + (i + 1/2) / m) / L (exact;
+// ties by graph, id).  A graph as wide as its share of the workers keeps each
+// column on one worker at every level, and a shallow graph's tasks (a
+// dependence-free graph is one level) are spread through every worker's list
+// between the deep graphs' tasks.  Keys grow along every edge, so each list
+// is topological and the task with the smallest unfinished key is always
+// ready at the head of its list.
+void schedule_columns(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw, std::vector<uint32_t>& wlen,
+                      std::vector<uint64_t>& seq) {
+  std::vector<uint64_t> num(N), den(N);
+  std::vector<uint32_t> worker(N);
+  uint64_t off = 0;
+  uint32_t x = 0;
+  for (auto g : gs) {
+    uint32_t L = 0;
+    for (uint32_t lv : g->level) L = std::max(L, lv + 1);
+    std::vector<uint32_t> width(L, 0), seen(L, 0);
+    for (uint32_t lv : g->level) width[lv]++;
+    uint32_t wmax = 0;
+    for (uint32_t w : width) wmax = std::max(wmax, w);
+    for (uint32_t v = 0; v < g->N(); ++v, ++x) {
+      const uint32_t lv = g->level[v];
+      const uint64_t i = seen[lv]++;
+      num[x] = 2 * ((uint64_t)lv * width[lv] + i) + 1;
+      den[x] = 2 * (uint64_t)width[lv] * L;
+      worker[x] = (uint32_t)((off + i) % nw);
+    }
+    off += wmax;
+  }
+  wlen.assign(nw, 0);
+  for (uint32_t k = 0; k < N; ++k) wlen[worker[k]]++;
+  std::vector<uint64_t> start(nw + 1, 0);
+  for (uint32_t w = 0; w < nw; ++w) start[w + 1] = start[w] + wlen[w];
+  std::vector<uint32_t> idx(N);
+  {
+    std::vector<uint64_t> fill(start.begin(), start.end() - 1);
+    for (uint32_t k = 0; k < N; ++k) idx[fill[worker[k]]++] = k;
+  }
+  // graph and id of global index k
+  std::vector<uint64_t> key_of(N);
+  x = 0;
+  for (uint32_t gi = 0; gi < gs.size(); ++gi)
+    for (uint32_t v = 0; v < gs[gi]->N(); ++v, ++x) key_of[x] = ((uint64_t)gi << 32) | v;
+  seq.assign(N, 0);
+  for (uint32_t w = 0; w < nw; ++w) {
+    auto b = idx.begin() + start[w], e = idx.begin() + start[w + 1];
+    std::sort(b, e, [&](uint32_t u, uint32_t v) {
+      const unsigned __int128 l = (unsigned __int128)num[u] * den[v];
+      const unsigned __int128 r = (unsigned __int128)num[v] * den[u];
+      return l != r ? l < r : u < v;
+    });
+    for (uint64_t k = start[w]; k < start[w + 1]; ++k) seq[k] = key_of[idx[k]];
+  }
+}
+
 // List schedule: simulate nw identical workers.  Whenever workers are free,
 // the ready tasks with the longest remaining path (sum of estimated costs to
 // a sink) start on them, in the order the workers became free; a task's
@@ -608,7 +665,7 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
   if (ntot >= 0xFFFFFFFFull || npred_tot >= 0xFFFFFFFFull || nsucc_tot >= 0xFFFFFFFFull || nreq_tot >= 0xFFFFFFFFull)
     return fail(TG_EINVAL, "layout too large: %llu tasks, %llu edges", (unsigned long long)ntot,
                 (unsigned long long)nsucc_tot);
-  if (schedule < TG_SCHED_LIST || schedule > TG_SCHED_SPREAD) return fail(TG_EINVAL, "schedule must be 1, 2 or 3");
+  if (schedule < TG_SCHED_LIST || schedule > TG_SCHED_COLUMN) return fail(TG_EINVAL, "schedule must be 1..4");
   const uint32_t N = (uint32_t)ntot;
   uint64_t nw = nw_req;
   if (nw > N) nw = N ? N : 1;
@@ -625,8 +682,10 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
     if (st != TG_OK) return st;
   } else if (schedule == TG_SCHED_LEVEL) {
     schedule_levels(gs, N, (uint32_t)nw, wlen, at_pos);
-  } else {
+  } else if (schedule == TG_SCHED_SPREAD) {
     schedule_spread(gs, N, (uint32_t)nw, wlen, at_pos);
+  } else {
+    schedule_columns(gs, N, (uint32_t)nw, wlen, at_pos);
   }
   if (keep) {
     keep->wlen = wlen;
@@ -1503,6 +1562,23 @@ tg_status tg_graph_set_rounds(tg_graph g, uint32_t uniform_rounds) {
   return null_stream_fence();
 }
 
+// Median number of tasks per dependence level over levels 1.. of a set of
+// graphs (levels of different graphs with the same index counted together).
+// A level-ordered layout with this many workers gives every worker one task
+// per level, mostly of the same column, so it waits on its own last task.
+static uint32_t typical_level_width(const std::vector<tg_graph>& gs) {
+  std::vector<uint32_t> width;
+  for (auto g : gs)
+    for (uint32_t lv : g->level) {
+      if (lv >= width.size()) width.resize(lv + 1, 0);
+      width[lv]++;
+    }
+  if (width.size() < 2) return width.empty() ? 0 : width[0];
+  std::vector<uint32_t> w(width.begin() + 1, width.end());
+  std::nth_element(w.begin(), w.begin() + w.size() / 2, w.end());
+  return w[w.size() / 2];
+}
+
 tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, double* best_ms) {
   if (!g || !best) return fail(TG_EINVAL, "NULL argument");
   if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
@@ -1527,7 +1603,7 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
     c.notify = nt;
     return c;
   };
-  for (uint32_t sch : {TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD}) {
+  for (uint32_t sch : {TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD, TG_SCHED_COLUMN}) {
     std::vector<tg_exec_config> shapes;
     for (uint32_t w : {rw, rw / 4, rw / 8})
       if (w) shapes.push_back(mk(TG_MAP_WAVE, w, 0, 0));
@@ -1535,6 +1611,9 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
     shapes.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
     // one large workgroup per CU: for graphs with few, large tasks
     for (uint32_t ww : {8u, 16u}) shapes.push_back(mk(TG_MAP_WORKGROUP, cus, ww, 0));
+    // one worker per task of a typical level
+    const uint32_t lw = typical_level_width(std::vector<tg_graph>{g});
+    if (lw >= 64 && lw <= rw && lw != rw && lw != rw / 4 && lw != rw / 8) shapes.push_back(mk(TG_MAP_WAVE, lw, 0, 0));
     for (auto c : shapes) {
       c.schedule = sch;
       cand.push_back(c);
@@ -1717,10 +1796,13 @@ tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, dou
     c.notify = nt;
     return c;
   };
-  for (uint32_t sch : {TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD}) {
+  for (uint32_t sch : {TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD, TG_SCHED_COLUMN}) {
     std::vector<Config> shapes;
     for (uint32_t w : {rw, rw / 4})
       if (w) shapes.push_back(mk(TG_MAP_WAVE, w, 0, 0));
+    // one worker per task of a typical level
+    const uint32_t lw = typical_level_width(b->graphs);
+    if (lw >= 64 && lw <= rw && lw != rw && lw != rw / 4) shapes.push_back(mk(TG_MAP_WAVE, lw, 0, 0));
     shapes.push_back(mk(TG_MAP_WORKGROUP, rg2, 2, 0));
     shapes.push_back(mk(TG_MAP_WORKGROUP, rg4, 4, 0));
     for (auto c : shapes) {
