@@ -80,6 +80,7 @@ def run_c4(args, stream):
         log(f"c4: autotuned on {len(sub)} graphs: {tune} ({tms:.1f} ms)")
     cfg = None if tune is None else tg.make_config(
         mapping=tune["mapping"], workers=tune["workers"], wg_waves=tune["wg_waves"], notify=tune["notify"],
+        gang=tune.get("gang", 0),
         schedule=tune["schedule"])
     t1 = time.perf_counter()
     b = tg.tg_batch_create([g.handle for g in gs], cfg)

@@ -86,12 +86,13 @@ typedef struct {
 
 /* Launch configuration of the persistent executor.  Zero fields mean "let the
  * library choose" (built-in defaults).
- *   mapping      : 1 = one wavefront per task, 2 = one workgroup per task.
- *   workers      : number of workers (wavefronts or workgroups); 0 = as many
+ *   mapping      : 1 = one wavefront per task, 2 = one workgroup per task,
+ *                  3 = a gang of `gang` workgroups (on different CUs) per task.
+ *   workers      : number of workers (wavefronts, workgroups or gangs); 0 = as many
  *                  as are co-resident (calibrated, see tg_exec_occupancy);
  *                  larger values are clamped to that.
  *   window       : ready-window length scanned per poll (1..64).
- *   wg_waves     : wavefronts per workgroup for mapping 2 (1..16).
+ *   wg_waves     : wavefronts per workgroup for mappings 2 and 3 (1..16).
  *   watchdog_ms  : abort a launch after this long without progress.
  *   spin_limit   : if non-zero, abort after this many consecutive empty polls
  *                  (lets a host test force the timeout path).
@@ -113,7 +114,10 @@ typedef struct {
  *                  of every level of a graph to the same worker (graphs packed
  *                  side by side by width) and orders each worker's list by the
  *                  stretched level, so columns stay on one worker and shallow
- *                  graphs fill the gaps of deep ones. */
+ *                  graphs fill the gaps of deep ones.
+ *   gang         : mapping 3: workgroups per gang (2..32).  Member 0 runs the
+ *                  scheduling loop and publishes each task to the others; the
+ *                  task's work items are split over all members. */
 typedef struct {
   uint32_t mapping;
   uint32_t workers;
@@ -125,9 +129,10 @@ typedef struct {
   uint32_t notify;
   uint32_t idle_sleep;
   uint32_t schedule;
+  uint32_t gang;
 } tg_exec_config;
 
-enum { TG_MAP_WAVE = 1, TG_MAP_WORKGROUP = 2 };
+enum { TG_MAP_WAVE = 1, TG_MAP_WORKGROUP = 2, TG_MAP_GANG = 3 };
 enum { TG_SCHED_LIST = 1, TG_SCHED_LEVEL = 2, TG_SCHED_SPREAD = 3, TG_SCHED_COLUMN = 4 };
 
 /* ------------------------------------------------------------- status */

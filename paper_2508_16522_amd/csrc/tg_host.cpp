@@ -167,7 +167,7 @@ tg_status device_info(DevInfo& di) {
 
 struct Config {
   uint32_t mapping = 1, workers = 0, window = 64, wg_waves = 4, watchdog_ms = 5000, spin_limit = 0, diag = 0;
-  uint32_t idle_sleep = 2, notify = 0, schedule = TG_SCHED_LEVEL;
+  uint32_t idle_sleep = 2, notify = 0, schedule = TG_SCHED_LEVEL, gang = 1;
 };
 
 Config resolve(const tg_exec_config* c) {
@@ -183,12 +183,17 @@ Config resolve(const tg_exec_config* c) {
     r.notify = c->notify & 1u;
     if (c->idle_sleep) r.idle_sleep = c->idle_sleep;
     if (c->schedule) r.schedule = c->schedule;
+    if (c->gang) r.gang = c->gang;
   }
+  if (r.mapping != TG_MAP_GANG) r.gang = 1;
   return r;
 }
 
 tg_status check_config(const Config& c) {
-  if (c.mapping != TG_MAP_WAVE && c.mapping != TG_MAP_WORKGROUP) return fail(TG_EINVAL, "mapping must be 1 or 2");
+  if (c.mapping != TG_MAP_WAVE && c.mapping != TG_MAP_WORKGROUP && c.mapping != TG_MAP_GANG)
+    return fail(TG_EINVAL, "mapping must be 1, 2 or 3");
+  if (c.mapping == TG_MAP_GANG && (c.gang < 2 || c.gang > tg::kMaxGang))
+    return fail(TG_EINVAL, "gang must be in [2, %u]", tg::kMaxGang);
   if (c.window < 1 || c.window > 64) return fail(TG_EINVAL, "window must be in [1, 64]");
   if (c.idle_sleep < 1 || c.idle_sleep > 64) return fail(TG_EINVAL, "idle_sleep must be in [1, 64]");
   if (c.wg_waves < 1 || c.wg_waves > 16) return fail(TG_EINVAL, "wg_waves must be in [1, 16]");
@@ -203,7 +208,7 @@ tg_status check_config(const Config& c) {
 struct Layout {
   Config cfg;
   uint32_t nworkers = 0, grid_blocks = 0, npos = 0, last_started = 0;
-  DevBuf rec, pred_addr, succ_pos, indeg, cnt, wbase, gtab, reqs, ctrl, execs, wprog, owner, bell, tstamp, wstamp;
+  DevBuf rec, pred_addr, succ_pos, indeg, cnt, wbase, gtab, reqs, ctrl, execs, wprog, owner, bell, tstamp, wstamp, mbox;
   std::vector<std::vector<uint32_t>> pos_of;  // per graph: task id -> position
   std::vector<TaskRec> rec_host;               // host copy (rounds can be re-set)
   ExecParams params{};
@@ -827,8 +832,12 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   for (auto g : gs)
     if ((s = ensure_device(g)) != TG_OK) return s;
   uint32_t cap32 = 0;
-  if ((s = resident_workers(cfg.mapping, cfg.wg_waves, &cap32)) != TG_OK) return s;
-  const uint64_t cap_workers = cap32;
+  // a gang's workgroups are the workgroup executor's (same bounds and
+  // occupancy attributes), so its residency is that count over the gang size
+  const uint32_t res_mapping = cfg.mapping == TG_MAP_GANG ? (uint32_t)TG_MAP_WORKGROUP : cfg.mapping;
+  if ((s = resident_workers(res_mapping, cfg.wg_waves, &cap32)) != TG_OK) return s;
+  const uint64_t cap_workers = cap32 / cfg.gang;
+  if (cap_workers == 0) return fail(TG_EINVAL, "gang of %u workgroups of %u waves does not fit", cfg.gang, cfg.wg_waves);
   uint64_t nw = cfg.workers ? cfg.workers : cap_workers;
   if (nw > cap_workers) nw = cap_workers;  // every worker must be co-resident
   static thread_local HostLayout tl_host;
@@ -852,7 +861,7 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   L->cfg = cfg;
   L->npos = H.N;
   L->nworkers = H.nw;
-  L->grid_blocks = cfg.mapping == TG_MAP_WAVE ? (H.nw + 3) / 4 : H.nw;
+  L->grid_blocks = cfg.mapping == TG_MAP_WAVE ? (H.nw + 3) / 4 : H.nw * cfg.gang;
   L->pos_of = std::move(H.pos_of);
   const uint32_t N = H.N;
   if ((s = upload(L->rec, H.rec)) != TG_OK) return s;
@@ -886,6 +895,11 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   P.ctrl = L->ctrl.as<tg::Ctrl>();
   P.owner = L->owner.as<uint32_t>();
   P.bell = L->bell.as<uint32_t>();
+  P.gang = cfg.gang;
+  if (cfg.mapping == TG_MAP_GANG) {
+    if ((s = L->mbox.alloc((size_t)H.nw * tg::kMboxStride * 4)) != TG_OK) return s;
+    P.mbox = L->mbox.as<uint32_t>();
+  }
   P.npos = N;
   P.nworkers = L->nworkers;
   P.window = cfg.window;
@@ -1068,7 +1082,8 @@ void timed_makespan(const std::vector<tg_graph>& gs, const HostLayout& H, uint32
 }
 
 bool same_layout(const Config& a, const Config& b) {
-  return a.mapping == b.mapping && a.workers == b.workers && a.wg_waves == b.wg_waves && a.schedule == b.schedule;
+  return a.mapping == b.mapping && a.workers == b.workers && a.wg_waves == b.wg_waves && a.schedule == b.schedule &&
+         a.gang == b.gang;
 }
 
 // Launch reset + persistent executor for a layout.
@@ -1590,7 +1605,9 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
   DevInfo di;
   if ((s = device_info(di)) != TG_OK) return s;
   const uint32_t cus = (uint32_t)di.cus;
-  uint32_t rw = 0, rg2 = 0, rg4 = 0;
+  uint32_t rw = 0, rg2 = 0, rg4 = 0, rg8 = 0, rg16 = 0;
+  if ((s = resident_workers(TG_MAP_WORKGROUP, 16, &rg16)) != TG_OK) return s;
+  if ((s = resident_workers(TG_MAP_WORKGROUP, 8, &rg8)) != TG_OK) return s;
   if ((s = resident_workers(TG_MAP_WAVE, 4, &rw)) != TG_OK) return s;
   if ((s = resident_workers(TG_MAP_WORKGROUP, 2, &rg2)) != TG_OK) return s;
   if ((s = resident_workers(TG_MAP_WORKGROUP, 4, &rg4)) != TG_OK) return s;
@@ -1614,6 +1631,13 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
     // one worker per task of a typical level
     const uint32_t lw = typical_level_width(std::vector<tg_graph>{g});
     if (lw >= 64 && lw <= rw && lw != rw && lw != rw / 4 && lw != rw / 8) shapes.push_back(mk(TG_MAP_WAVE, lw, 0, 0));
+    // gangs of workgroups on several CUs per task, for large tasks
+    const uint32_t gshape[][3] = {{16, 4, rg16}, {8, 4, rg8}, {8, 8, rg8}, {4, 16, rg4}};
+    for (const auto& gsh : gshape)
+      if (gsh[2] / gsh[1]) {
+        shapes.push_back(mk(TG_MAP_GANG, gsh[2] / gsh[1], gsh[0], 0));
+        shapes.back().gang = gsh[1];
+      }
     for (auto c : shapes) {
       c.schedule = sch;
       cand.push_back(c);
@@ -1770,6 +1794,7 @@ tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks, double
     cfg->notify = c.notify;
     cfg->idle_sleep = c.idle_sleep;
     cfg->schedule = c.schedule;
+    cfg->gang = c.mapping == TG_MAP_GANG ? c.gang : 0;
   }
   if (tasks) *tasks = b->lay->npos;
   return TG_OK;

@@ -98,13 +98,18 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 
 // ------------------------------------------------------------------ teams
 
-// A team is the set of lanes that executes one task: one wavefront or one
-// workgroup.  sum() returns the wrap-around sum of v over the team to every
-// lane; sync() is a team-wide barrier.
+// A team is the set of lanes that executes one task: one wavefront, one
+// workgroup, or (gang) the same lane slot of several workgroups on different
+// CUs.  t / size() index the lanes of this wavefront or workgroup: sum()
+// returns the wrap-around sum of v over them to every lane and sync() is
+// their barrier.  wt() / ws() index the task's work items over the whole
+// team (equal to t / size() except in a gang).
 struct WaveTeam {
   uint32_t t;
   static constexpr uint32_t S = 64;
   __device__ __forceinline__ uint32_t size() const { return 64; }
+  __device__ __forceinline__ uint32_t wt() const { return t; }
+  __device__ __forceinline__ uint32_t ws() const { return 64; }
   __device__ __forceinline__ uint32_t sum(uint32_t v) const { return wave_sum(v); }
   __device__ __forceinline__ void sync() const {}
   __device__ __forceinline__ bool leader() const { return t == 0; }
@@ -114,6 +119,8 @@ struct BlockTeam {
   uint32_t t, n;
   uint32_t* lds;  // >= 17 words
   __device__ __forceinline__ uint32_t size() const { return n; }
+  __device__ __forceinline__ uint32_t wt() const { return t; }
+  __device__ __forceinline__ uint32_t ws() const { return n; }
   __device__ __forceinline__ void sync() const { __syncthreads(); }
   __device__ __forceinline__ bool leader() const { return t == 0; }
   __device__ uint32_t sum(uint32_t v) const {
@@ -126,6 +133,15 @@ struct BlockTeam {
     for (uint32_t i = 0; i < (n >> 6); ++i) s += lds[i];
     return s;
   }
+};
+
+// One workgroup (member m of G) of a gang: reductions and barriers stay
+// inside the workgroup, work items are split over all G workgroups.
+struct GangTeam : BlockTeam {
+  uint32_t m, G;
+  __device__ __forceinline__ uint32_t wt() const { return m * n + t; }
+  __device__ __forceinline__ uint32_t ws() const { return G * n; }
+  __device__ __forceinline__ bool leader() const { return m == 0 && t == 0; }
 };
 
 // ----------------------------------------------------------------- record
@@ -142,6 +158,7 @@ struct Rec {
   uint64_t out;
   uint32_t tid, graph, pred_beg, npred, succ_beg, nsucc, rounds, nreq;
   uint32_t succ0;
+  uint32_t* digest;  // the graph's digest array
 };
 
 // This lane's dword of the record at `pos`.  Records are read-only while a
@@ -214,7 +231,7 @@ template <int VEC, class Team>
 __device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecParams& P, const Rec& r,
                                                    const GraphEnt& G) {
   typedef typename VecT<VEC>::T V;
-  const uint32_t n = G.n, S = tm.size();
+  const uint32_t n = G.n, S = tm.ws();
   const uint32_t nbytes = n * 4u;
   const uint32_t npred = r.npred, R = r.rounds, tid = r.tid;
   const __amdgpu_buffer_rsrc_t wr = make_rsrc((const void*)r.out, nbytes);
@@ -222,7 +239,7 @@ __device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecPar
   const uint32_t chunks = uni((n + step - 1u) / step);
   uint32_t dsum = 0;
   for (uint32_t c = 0; c < chunks; ++c) {
-    const uint32_t k0 = c * step + tm.t * VEC;
+    const uint32_t k0 = c * step + tm.wt() * VEC;
     const bool valid = k0 < n;
     V acc = V(0);
     if (valid) {
@@ -256,16 +273,17 @@ __device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecPar
   return dsum;
 }
 
+// Returns the digest part of this wavefront / workgroup (the whole digest
+// unless the team is a gang).
 template <class Team>
-__device__ __forceinline__ void body_explicit(const Team& tm, const ExecParams& P, const Rec& r,
-                                              const GraphEnt& G) {
-  const uint32_t n = G.n, S = tm.size();
+__device__ __forceinline__ uint32_t body_explicit(const Team& tm, const ExecParams& P, const Rec& r,
+                                                  const GraphEnt& G) {
+  const uint32_t n = G.n, S = tm.ws();
   uint32_t dsum;
   if (n >= 4 * S) dsum = explicit_words<4>(tm, P, r, G);
   else if (n >= 2 * S) dsum = explicit_words<2>(tm, P, r, G);
   else dsum = explicit_words<1>(tm, P, r, G);
-  const uint32_t d = tm.sum(dsum);
-  if (tm.leader()) G.digest[r.tid] = d;
+  return tm.sum(dsum);
 }
 
 // Elements t, t + S, t + 2S, t + 3S of p[0, len) (0 past the end).
@@ -279,21 +297,24 @@ __device__ __forceinline__ u32x4 load4(const uint32_t* p, uint32_t t, uint32_t S
   return x;
 }
 
+// Returns the digest part of this wavefront / workgroup (the whole digest
+// unless the team is a gang).  Every workgroup of a gang sums all read-only
+// elements itself; the read-write elements are split over the gang.
 template <class Team>
-__device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& P, const Rec& r,
-                                              const GraphEnt& G) {
+__device__ __forceinline__ uint32_t body_implicit(const Team& tm, const ExecParams& P, const Rec& r,
+                                                  const GraphEnt& G) {
   const cptr<ReqDev> rq = as_const(P.reqs) + r.out;
   uint32_t* A = G.data;
-  const uint32_t S = tm.size();
   // read-only elements: their wrap sum c
   uint32_t part = 0;
   for (uint32_t i = 0; i < r.nreq; ++i) {
     const ReqDev q = rq[i];
     if (q.priv != 1) continue;
-    for (uint64_t e = q.lo + tm.t; e < q.hi; e += S) part += ld_coherent(A + e);
+    for (uint64_t e = q.lo + tm.t; e < q.hi; e += tm.size()) part += ld_coherent(A + e);
   }
   const uint32_t key = uni(tm.sum(part) ^ r.tid);
   const uint32_t R = r.rounds;
+  const uint32_t S = tm.ws(), wt = tm.wt();
   uint32_t dsum = 0;
   for (uint32_t i = 0; i < r.nreq; ++i) {
     const ReqDev q = rq[i];
@@ -304,13 +325,13 @@ __device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& 
     // loop are wave-uniform, lanes past the end skip loads and stores; the
     // next chunk's loads are issued before this chunk's mix
     const uint64_t step = 4 * (uint64_t)S;
-    u32x4 x = load4(a, tm.t, S, len);
+    u32x4 x = load4(a, wt, S, len);
     for (uint64_t base = 0; base < len; base += step) {
-      const u32x4 y = base + step < len ? load4(a + base + step, tm.t, S, len - base - step) : u32x4{0, 0, 0, 0};
+      const u32x4 y = base + step < len ? load4(a + base + step, wt, S, len - base - step) : u32x4{0, 0, 0, 0};
       x = mix_rounds<u32x4>(x ^ key, R);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const uint64_t o = base + tm.t + (uint64_t)k * S;
+        const uint64_t o = base + wt + (uint64_t)k * S;
         if (o < len) {
           st_coherent(a + o, x[k]);
           dsum += x[k] * (2u * (q.rw_base + (uint32_t)o) + 1u);
@@ -319,19 +340,26 @@ __device__ __forceinline__ void body_implicit(const Team& tm, const ExecParams& 
       x = y;
     }
   }
-  const uint32_t d = tm.sum(dsum);
-  if (tm.leader()) G.digest[r.tid] = d;
+  return tm.sum(dsum);
 }
 
-// Run the task at `pos`; v is this lane's dword of its record.
+// Run the task at `pos`; v is this lane's dword of its record.  Returns the
+// digest part of this wavefront / workgroup; run_task also stores it.
 template <class Team>
-__device__ __forceinline__ void run_body(const Team& tm, const ExecParams& P, uint32_t pos, uint32_t v, Rec& r) {
+__device__ __forceinline__ uint32_t run_body(const Team& tm, const ExecParams& P, uint32_t pos, uint32_t v, Rec& r) {
   unpack_rec(tm, P, v, r);
   const GraphEnt G = as_const(P.gtab)[r.graph];
+  r.digest = G.digest;
   if (P.tstamp && tm.leader()) P.tstamp[2 * pos] = __builtin_amdgcn_s_memrealtime();
-  if (G.mode == 1) body_explicit(tm, P, r, G);
-  else body_implicit(tm, P, r, G);
+  const uint32_t d = G.mode == 1 ? body_explicit(tm, P, r, G) : body_implicit(tm, P, r, G);
   if (P.execs && tm.leader()) __hip_atomic_fetch_add(P.execs + pos, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return d;
+}
+
+template <class Team>
+__device__ __forceinline__ void run_task(const Team& tm, const ExecParams& P, uint32_t pos, uint32_t v, Rec& r) {
+  const uint32_t d = run_body(tm, P, pos, v, r);
+  if (tm.leader()) r.digest[r.tid] = d;
 }
 
 // Signal every out-edge of a finished task (COMPLETED_EDGE).
@@ -515,7 +543,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     if (pos == kExit) break;
     const uint32_t v = pos == w.pf_pos ? w.pf_v : rec_dword(P, pos, lane);
     Rec r;
-    run_body(tm, P, pos, v, r);
+    run_task(tm, P, pos, v, r);
     complete_edges(tm, P, r);
     if (P.tstamp && lane == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
   }
@@ -552,12 +580,117 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     __syncthreads();
     if (pos == kExit) break;
     Rec r;
-    run_body(tm, P, pos, v, r);
+    run_task(tm, P, pos, v, r);
     complete_edges(tm, P, r);
     if (P.tstamp && threadIdx.x == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
     __syncthreads();
   }
   if (P.wprog && threadIdx.x == 0) P.wprog[worker] = w.h;
+}
+
+// Bounded wait on a gang mailbox word: returns true once *p >= target; false
+// when the launch is being aborted or nothing arrived for the watchdog
+// interval (the waiter then raises the abort flag itself).
+__device__ bool gang_wait(const ExecParams& P, const uint32_t* p, uint32_t target) {
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (uint32_t spins = 1;; ++spins) {
+    if (ld_coherent(p) >= target) return true;
+    if ((spins & 63u) == 0u) {
+      if (ld_coherent(&P.ctrl->abort) != 0u) return false;
+      const bool limit = P.spin_limit != 0u && spins >= P.spin_limit;
+      if (limit || __builtin_amdgcn_s_memrealtime() - t0 > P.watchdog_ticks) {
+        __hip_atomic_fetch_add(&P.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// A gang of P.gang workgroups per task (on different CUs): member 0 runs the
+// scheduling state machine of the gang's list and publishes each task in the
+// gang's mailbox (position, then sequence number); every member executes its
+// share of the task's work items and reports its digest part and arrival;
+// member 0 waits for all arrivals, stores the digest and signals the
+// out-edges.  Members' payload stores are drained before they report, so
+// the edge signals follow every store of the task.
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exec_gang(ExecParams P) {
+  __shared__ uint32_t lds[32];
+  __shared__ uint32_t cmd, ok;
+  __shared__ uint32_t recl[32];
+  const uint32_t G = P.gang;
+  const uint32_t gang = blockIdx.x / G, member = blockIdx.x % G;
+  if (gang >= P.nworkers) return;
+  GangTeam tm;
+  tm.t = threadIdx.x;
+  tm.n = blockDim.x;
+  tm.lds = lds;
+  tm.m = member;
+  tm.G = G;
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t* mb = P.mbox + (size_t)gang * kMboxStride;
+  WorkerState w;
+  worker_init(w, P, gang);
+  for (uint32_t it = 0;; ++it) {
+    if (member == 0) {
+      if (threadIdx.x < 64) {
+        const uint32_t pos = next_task(P, w, lane);
+        if (pos != kExit) {
+          const uint32_t v = pos == w.pf_pos ? w.pf_v : rec_dword(P, pos, lane);
+          if (lane < 32) recl[lane] = v;
+        }
+        if (lane == 0) {
+          cmd = pos;
+          st_coherent(mb + 1, pos);
+          vm_drain();  // the position is visible before its sequence number
+          __hip_atomic_store(mb + 0, it + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    } else if (threadIdx.x == 0) {
+      cmd = gang_wait(P, mb + 0, it + 1) ? ld_coherent(mb + 1) : kExit;
+    }
+    __syncthreads();
+    const uint32_t pos = uni(cmd);
+    uint32_t v = member == 0 ? recl[lane & 31u] : 0u;
+    __syncthreads();
+    if (pos == kExit) break;
+    if (member != 0) v = rec_dword(P, pos, lane);
+    Rec r;
+    const uint32_t d = run_body(tm, P, pos, v, r);
+    vm_drain();  // this lane's payload stores are complete
+    __syncthreads();
+    if (member != 0) {
+      if (threadIdx.x == 0) {
+        st_coherent(mb + 16 + member, d);
+        vm_drain();
+        __hip_atomic_fetch_add(mb + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      continue;
+    }
+    if (threadIdx.x == 0) {
+      ok = gang_wait(P, mb + 2, (it + 1) * (G - 1)) ? 1u : 0u;
+      if (ok) {
+        uint32_t total = d;
+        for (uint32_t m = 1; m < G; ++m) total += ld_coherent(mb + 16 + m);
+        r.digest[r.tid] = total;
+      }
+    }
+    __syncthreads();
+    if (ok == 0u) {
+      // a member did not arrive: the launch is being aborted; tell the
+      // members to stop and leave
+      if (threadIdx.x == 0) {
+        st_coherent(mb + 1, kExit);
+        vm_drain();
+        __hip_atomic_store(mb + 0, it + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      break;
+    }
+    complete_edges(tm, P, r);
+    if (P.tstamp && threadIdx.x == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
+    __syncthreads();
+  }
+  if (member == 0 && P.wprog && threadIdx.x == 0) P.wprog[gang] = w.h;
 }
 
 // Residency probes: the executors' launch bounds and occupancy attributes
@@ -583,6 +716,8 @@ __global__ __launch_bounds__(256) void k_reset(ExecParams P) {
     P.cnt[i] = P.indeg[i];
     if (P.execs) P.execs[i] = 0;
   }
+  if (P.mbox)
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P.nworkers * kMboxStride; i += stride) P.mbox[i] = 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P.nworkers; i += stride) {
     P.bell[i * kBellStride] = 0;
     if (P.wprog) P.wprog[i] = 0xFFFFFFFFu;
@@ -602,7 +737,7 @@ __global__ __launch_bounds__(256) void k_reset(ExecParams P) {
 __global__ __launch_bounds__(64) void k_one_task(ExecParams P, uint32_t pos) {
   const WaveTeam tm{threadIdx.x};
   Rec r;
-  run_body(tm, P, pos, rec_dword(P, pos, threadIdx.x), r);
+  run_task(tm, P, pos, rec_dword(P, pos, threadIdx.x), r);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -622,8 +757,10 @@ hipError_t launch_exec(const ExecParams& p, uint32_t mapping, uint32_t wg_waves,
     else hipLaunchKernelGGL(k_probe_block, dim3(grid_blocks), dim3(wg_waves * 64u), 0, s, p);
   } else if (mapping == 1) {
     hipLaunchKernelGGL(k_exec_wave, dim3(grid_blocks), dim3(256), 0, s, p);
-  } else {
+  } else if (mapping == 2) {
     hipLaunchKernelGGL(k_exec_block, dim3(grid_blocks), dim3(wg_waves * 64u), 0, s, p);
+  } else {
+    hipLaunchKernelGGL(k_exec_gang, dim3(grid_blocks), dim3(wg_waves * 64u), 0, s, p);
   }
   return hipGetLastError();
 }

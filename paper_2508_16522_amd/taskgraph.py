@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libtaskgraph.so")
 TG_OK, TG_EINVAL, TG_ENOMEM, TG_EBUSY, TG_EDEVICE, TG_ETIMEOUT, TG_ESTATE = 0, -1, -2, -3, -4, -5, -6
 TG_EXPLICIT, TG_IMPLICIT = 1, 2
 TG_RO, TG_RW = 1, 2
-TG_MAP_WAVE, TG_MAP_WORKGROUP = 1, 2
+TG_MAP_WAVE, TG_MAP_WORKGROUP, TG_MAP_GANG = 1, 2, 3
 TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD, TG_SCHED_COLUMN = 1, 2, 3, 4
 TG_CMP_PER_TASK, TG_CMP_HIPGRAPH = 1, 2
 
@@ -57,7 +57,7 @@ class tg_exec_config(ctypes.Structure):
     _fields_ = [("mapping", ctypes.c_uint32), ("workers", ctypes.c_uint32), ("window", ctypes.c_uint32),
                 ("wg_waves", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32), ("spin_limit", ctypes.c_uint32),
                 ("diag", ctypes.c_uint32), ("notify", ctypes.c_uint32), ("idle_sleep", ctypes.c_uint32),
-                ("schedule", ctypes.c_uint32)]
+                ("schedule", ctypes.c_uint32), ("gang", ctypes.c_uint32)]
 
 
 REQ_DTYPE = np.dtype([("lo", np.uint64), ("hi", np.uint64), ("priv", np.uint32), ("_pad", np.uint32)])
@@ -255,9 +255,9 @@ def tg_graph_finalize(g):
 
 
 def make_config(mapping=0, workers=0, window=0, wg_waves=0, watchdog_ms=0, spin_limit=0, diag=0, notify=0,
-                idle_sleep=0, schedule=0) -> tg_exec_config:
+                idle_sleep=0, schedule=0, gang=0) -> tg_exec_config:
     return tg_exec_config(mapping, workers, window, wg_waves, watchdog_ms, spin_limit, diag, notify, idle_sleep,
-                          schedule)
+                          schedule, gang)
 
 
 def tg_graph_execute(g, cfg: tg_exec_config | None = None, stream=None):

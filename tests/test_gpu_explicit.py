@@ -225,6 +225,34 @@ def test_watchdog_path_then_recovery(gpu):
     check_explicit(g, eg, oracle_explicit(eg))
 
 
+@pytest.mark.parametrize("gang,wg_waves", [(2, 1), (3, 4), (8, 16)])
+@pytest.mark.parametrize("n", [64, 1024, 65536])
+def test_patterns_gangs(gpu, n, gang, wg_waves):
+    """Explicit graphs with a gang of workgroups per task: payload words are
+    split over the whole gang (a gang wider than the payload leaves members
+    idle), digests combined by member 0."""
+    for pattern in ("stencil", "random"):
+        eg = wl.pattern_graph(pattern, 13 if n == 65536 else 37, 5 if n == 65536 else 11, seed=4, n=n, rounds=2)
+        ref = oracle_explicit(eg)
+        g = tg.graph_from_explicit(eg)
+        run(g, tg.make_config(mapping=3, gang=gang, wg_waves=wg_waves))
+        check_explicit(g, eg, ref, payload_sample=8)
+        run(g, tg.make_config(mapping=3, gang=gang, wg_waves=wg_waves, workers=1, window=3))
+        check_explicit(g, eg, ref)
+
+
+def test_gang_watchdog_path_then_recovery(gpu):
+    # as the single-team test: the abort reaches every member of every gang
+    eg = wl.pattern_graph("stencil", 1, 24, seed=0, n=64, rounds=4096)
+    g = tg.graph_from_explicit(eg)
+    tg.tg_graph_execute(g.handle, tg.make_config(mapping=3, gang=4, wg_waves=4, workers=8, spin_limit=1))
+    with pytest.raises(tg.TaskGraphError) as ei:
+        tg.tg_graph_wait(g.handle)
+    assert ei.value.status == tg.TG_ETIMEOUT
+    run(g, tg.make_config(mapping=3, gang=4, wg_waves=4))
+    check_explicit(g, eg, oracle_explicit(eg))
+
+
 def test_external_pre_and_post_conditions(gpu):
     # graph B may start only after graph A's post-condition event; B runs on
     # another stream; both results stay bit-exact

@@ -103,3 +103,36 @@ def test_comparators_implicit(gpu, mode):
     tg.tg_graph_execute_comparator(g.handle, mode)
     tg.tg_graph_wait(g.handle)
     _check_exec(g, ig, _ref(ig))
+
+
+GANGS = [dict(mapping=3, wg_waves=1, gang=2), dict(mapping=3, wg_waves=4, gang=3), dict(mapping=3, wg_waves=16, gang=8)]
+
+
+@pytest.mark.parametrize("kw", GANGS, ids=["g2w1", "g3w4", "g8w16"])
+@pytest.mark.parametrize("P,S,iters", [(8, 128, 4), (33, 256, 3)])
+def test_halo_small_gangs(gpu, P, S, iters, kw):
+    """A gang of workgroups on several CUs per task: the read-write elements
+    are split over the gang, the digest parts are combined by member 0."""
+    ig = wl.halo_graph(P, S, iters, seed=2, rounds=3)
+    g = tg.graph_from_implicit(ig)
+    run(g, tg.make_config(**kw))
+    _check_exec(g, ig, _ref(ig))
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_random_regions_gangs(gpu, seed):
+    rng = np.random.default_rng(seed)
+    ig = wl.random_regions(80, 300, 4, 40, rng, rounds=2, seed=seed)
+    g = tg.graph_from_implicit(ig)
+    for kw in GANGS:
+        run(g, tg.make_config(**kw))
+        _check_exec(g, ig, _ref(ig))
+
+
+def test_c3_execution_r64_gangs(gpu):
+    """The C3 program's first four sweeps at R = 64 with gangs of eight
+    16-wave workgroups: the whole array and every digest bit-exact."""
+    ig = wl.halo_graph(1024, 16384, 4, seed=0, rounds=64)
+    g = tg.graph_from_implicit(ig)
+    run(g, tg.make_config(mapping=3, wg_waves=16, gang=8))
+    _check_exec(g, ig, _ref(ig))
