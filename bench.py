@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-alone", action="store_true", help="skip timing each graph alone")
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="with --no-tune: the batch's schedule (1 list, 2 level, 3 spread, 4 column; 0 default)")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="run only the copy-bandwidth probe (short runs under a counter profiler)")
     ap.add_argument("--comparator-steps", type=int, default=50, help="timesteps of the comparator sub-graph")
@@ -163,7 +165,7 @@ def main():
         log(f"alone {p}: {solo_ms[p]:.3f} ms ({tuned[p]})")
 
     # the step: one batched launch over the five graphs
-    batch = tg.tg_batch_create([g.handle for g in gs])
+    batch = tg.tg_batch_create([g.handle for g in gs], tg.make_config(schedule=args.schedule))
     if not args.no_tune:
         bcfg, bms = tg.tg_batch_autotune(batch, reps=2)
         log(f"autotune batch: {bcfg} {bms:.3f} ms")
