@@ -220,7 +220,7 @@ tg_status tg_graph_wait(tg_graph g);
 
 /* Read results (each waits for an in-flight execution first). */
 tg_status tg_graph_num_tasks(tg_graph g, uint64_t* n);
-tg_status tg_graph_num_edges(tg_graph g, uint64_t* e);          /* distinct edges */
+tg_status tg_graph_num_edges(tg_graph g, uint64_t* e);  /* distinct edges executed (reduced ones if reduced) */
 tg_status tg_graph_read_digests(tg_graph g, uint32_t* host_out, uint64_t n);  /* n = #tasks */
 tg_status tg_graph_read_payload(tg_graph g, tg_event v, uint32_t* host_out, uint32_t n); /* n = payload words */
 tg_status tg_graph_read_data(tg_graph g, uint32_t* host_out, uint64_t lo, uint64_t hi);  /* implicit A[lo,hi) */
@@ -229,6 +229,26 @@ tg_status tg_graph_checksum(tg_graph g, uint64_t* out);
  * of task j in ascending order.  row_ptr has #tasks+1 entries; col holds up to
  * cap_e entries; *e receives the edge count (TG_ENOMEM if it exceeds cap_e). */
 tg_status tg_graph_read_dag(tg_graph g, uint64_t* row_ptr, uint32_t* col, uint64_t cap_e, uint64_t* e);
+/* Dependence reduction (Section 5 names transitive reduction as an
+ * optimisation of inferred dependences).  tg_reduce_dag: for a DAG given as
+ * an out-edge CSR over n vertices whose ids are a topological order (every
+ * edge j -> k has j < k; rows may be in any order inside), writes the CSR of
+ * the same DAG without every edge j -> k for which some i has edges j -> i
+ * and i -> k.  Each dropped edge is implied by a path, so reachability (the
+ * order the DAG imposes) is unchanged.  out_row_ptr: n + 1 entries;
+ * out_col: capacity row_ptr[n]; rows come out ascending; *out_e = edges kept.
+ * Host memory only; cost grows with the sum over edges i -> k of i's
+ * in-degree.  TG_EINVAL for an edge that does not go forward.
+ * tg_graph_reduce_edges: apply it to a finalised implicit graph's inferred
+ * DAG for execution (fewer counter decrements, identical results: an
+ * implicit task's inputs come from the shared array, not from its
+ * predecessors); tg_graph_read_dag keeps returning the full inferred DAG.
+ * *removed (may be NULL) = edges dropped.  TG_EINVAL for explicit graphs,
+ * whose predecessor sets are task inputs. */
+tg_status tg_reduce_dag(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, uint64_t* out_row_ptr,
+                        uint32_t* out_col, uint64_t* out_e);
+tg_status tg_graph_reduce_edges(tg_graph g, uint64_t* removed);
+
 /* Times of the last finalize (host compile, device inference) and of the last
  * execution measured with HIP events, in milliseconds (0 when not measured). */
 tg_status tg_graph_timings(tg_graph g, double* compile_ms, double* infer_ms, double* exec_ms);

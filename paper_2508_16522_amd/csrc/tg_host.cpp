@@ -235,6 +235,11 @@ struct tg_graph_s {
   std::vector<uint64_t> succ_ptr;
   std::vector<uint32_t> succ;
   std::vector<uint32_t> level;
+  // implicit graphs after tg_graph_reduce_edges: the full inferred DAG (what
+  // tg_graph_read_dag returns); succ / dpred then hold the reduced edges
+  bool reduced = false;
+  std::vector<uint64_t> full_succ_ptr;
+  std::vector<uint32_t> full_succ;
   std::vector<uint32_t> rw_base;  // implicit: per requirement, ordinal of its first written element
   DevBuf payload, data, digest;
   std::unique_ptr<Layout> solo;
@@ -1522,13 +1527,123 @@ tg_status tg_graph_checksum(tg_graph g, uint64_t* out) {
 tg_status tg_graph_read_dag(tg_graph g, uint64_t* row_ptr, uint32_t* col, uint64_t cap_e, uint64_t* e) {
   if (!g || !row_ptr || !e) return fail(TG_EINVAL, "NULL argument");
   if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
-  *e = g->succ.size();
-  memcpy(row_ptr, g->succ_ptr.data(), g->succ_ptr.size() * sizeof(uint64_t));
-  if (g->succ.size() > cap_e) return fail(TG_ENOMEM, "col capacity %llu < %zu edges", (unsigned long long)cap_e, g->succ.size());
-  if (!g->succ.empty()) {
+  const std::vector<uint64_t>& rp = g->reduced ? g->full_succ_ptr : g->succ_ptr;
+  const std::vector<uint32_t>& cl = g->reduced ? g->full_succ : g->succ;
+  *e = cl.size();
+  memcpy(row_ptr, rp.data(), rp.size() * sizeof(uint64_t));
+  if (cl.size() > cap_e) return fail(TG_ENOMEM, "col capacity %llu < %zu edges", (unsigned long long)cap_e, cl.size());
+  if (!cl.empty()) {
     if (!col) return fail(TG_EINVAL, "col is NULL");
-    memcpy(col, g->succ.data(), g->succ.size() * 4);
+    memcpy(col, cl.data(), cl.size() * 4);
   }
+  return TG_OK;
+}
+
+tg_status tg_graph_reduce_edges(tg_graph g, uint64_t* removed) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  if (g->mode != TG_IMPLICIT)
+    return fail(TG_EINVAL, "only implicit graphs: an explicit task's predecessors are its inputs");
+  tg_status s = graph_wait(g);
+  if (s != TG_OK) return s;
+  if (g->reduced) {
+    if (removed) *removed = g->full_succ.size() - g->succ.size();
+    return TG_OK;
+  }
+  const uint32_t N = g->N();
+  std::vector<uint64_t> rp(N + 1);
+  std::vector<uint32_t> cl(g->succ.size());
+  uint64_t e = 0;
+  if ((s = tg_reduce_dag(N, g->succ_ptr.data(), g->succ.data(), rp.data(), cl.data(), &e)) != TG_OK) return s;
+  cl.resize(e);
+  g->full_succ_ptr.swap(g->succ_ptr);
+  g->full_succ.swap(g->succ);
+  g->succ_ptr.swap(rp);
+  g->succ.swap(cl);
+  // predecessor lists of the reduced edges (ascending)
+  std::vector<uint64_t> pp(N + 1, 0);
+  for (uint32_t x : g->succ) pp[x + 1]++;
+  for (uint32_t k = 0; k < N; ++k) pp[k + 1] += pp[k];
+  std::vector<uint32_t> pr(g->succ.size());
+  {
+    std::vector<uint64_t> fill(pp.begin(), pp.end() - 1);
+    for (uint32_t j = 0; j < N; ++j)
+      for (uint64_t a = g->succ_ptr[j]; a < g->succ_ptr[j + 1]; ++a) pr[fill[g->succ[a]]++] = j;
+  }
+  g->dpred_ptr.swap(pp);
+  g->dpred.swap(pr);
+  g->reduced = true;
+  // layouts and schedules were built on the full edge set
+  g->solo.reset();
+  g->last_layout = nullptr;
+  g->plans.reset();
+  g->has_tuned = false;
+  if (removed) *removed = g->full_succ.size() - g->succ.size();
+  return TG_OK;
+}
+
+// Two-hop reduction of a DAG whose vertex ids are a topological order: the
+// edge j -> k is dropped when some i has edges j -> i and i -> k.  Every
+// dropped edge is implied by a path of the input, so reachability is
+// unchanged (all edges of the transitive reduction are kept).
+tg_status tg_reduce_dag(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, uint64_t* out_row_ptr,
+                        uint32_t* out_col, uint64_t* out_e) {
+  if (!row_ptr || !out_row_ptr || !out_e) return fail(TG_EINVAL, "NULL argument");
+  const uint64_t E = row_ptr[n];
+  if (E && (!col || !out_col)) return fail(TG_EINVAL, "NULL edge array");
+  for (uint32_t j = 0; j < n; ++j) {
+    if (row_ptr[j + 1] < row_ptr[j]) return fail(TG_EINVAL, "row_ptr not ascending at %u", j);
+    for (uint64_t a = row_ptr[j]; a < row_ptr[j + 1]; ++a)
+      if (col[a] <= j || col[a] >= n) return fail(TG_EINVAL, "edge %u -> %u does not go forward", j, col[a]);
+  }
+  // predecessor lists
+  std::vector<uint64_t> pp(n + 1, 0);
+  for (uint64_t a = 0; a < E; ++a) pp[col[a] + 1]++;
+  for (uint32_t k = 0; k < n; ++k) pp[k + 1] += pp[k];
+  std::vector<uint32_t> pr(E);
+  {
+    std::vector<uint64_t> fill(pp.begin(), pp.end() - 1);
+    for (uint32_t j = 0; j < n; ++j)
+      for (uint64_t a = row_ptr[j]; a < row_ptr[j + 1]; ++a) pr[fill[col[a]]++] = j;
+  }
+  // keep[x]: predecessor entry x (edge pr[x] -> k) survives
+  std::vector<uint8_t> keep(E, 1);
+  auto work = [&](uint32_t k0, uint32_t k1) {
+    std::vector<uint32_t> stamp(n, 0xFFFFFFFFu);
+    std::vector<uint64_t> where(n, 0);
+    for (uint32_t k = k0; k < k1; ++k) {
+      for (uint64_t x = pp[k]; x < pp[k + 1]; ++x) {
+        stamp[pr[x]] = k;
+        where[pr[x]] = x;
+      }
+      for (uint64_t x = pp[k]; x < pp[k + 1]; ++x) {
+        const uint32_t i = pr[x];
+        for (uint64_t y = pp[i]; y < pp[i + 1]; ++y)
+          if (stamp[pr[y]] == k) keep[where[pr[y]]] = 0;
+      }
+    }
+  };
+  const uint32_t nth = n >= 4096 ? std::max(1u, std::min(8u, std::thread::hardware_concurrency())) : 1u;
+  if (nth <= 1) {
+    work(0, n);
+  } else {
+    std::vector<std::thread> pool;
+    for (uint32_t t = 0; t < nth; ++t)
+      pool.emplace_back(work, (uint32_t)((uint64_t)n * t / nth), (uint32_t)((uint64_t)n * (t + 1) / nth));
+    for (auto& th : pool) th.join();
+  }
+  // reduced successor CSR (rows ascending because predecessors are visited
+  // in ascending k)
+  std::fill(out_row_ptr, out_row_ptr + n + 1, 0);
+  for (uint32_t k = 0; k < n; ++k)
+    for (uint64_t x = pp[k]; x < pp[k + 1]; ++x)
+      if (keep[x]) out_row_ptr[pr[x] + 1]++;
+  for (uint32_t j = 0; j < n; ++j) out_row_ptr[j + 1] += out_row_ptr[j];
+  std::vector<uint64_t> fill(out_row_ptr, out_row_ptr + n);
+  for (uint32_t k = 0; k < n; ++k)
+    for (uint64_t x = pp[k]; x < pp[k + 1]; ++x)
+      if (keep[x]) out_col[fill[pr[x]]++] = k;
+  *out_e = out_row_ptr[n];
   return TG_OK;
 }
 

@@ -38,7 +38,7 @@ EXPORTS = (
     "tg_graph_kernel_ms", "tg_graph_autotune", "tg_probe", "tg_graph_kernel_times", "tg_graph_set_rounds",
     "tg_server_create", "tg_server_submit", "tg_server_wait", "tg_server_stats", "tg_server_destroy",
     "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
-    "tg_graph_execute_after",
+    "tg_graph_execute_after", "tg_reduce_dag", "tg_graph_reduce_edges",
 )
 
 
@@ -123,6 +123,8 @@ def load() -> ctypes.CDLL:
         "tg_batch_info": (i32, [G, P, P, P, P]),
         "tg_batch_autotune": (i32, [G, u32, P, P]),
         "tg_graph_execute_after": (i32, [G, P, P, P, u32, P]),
+        "tg_reduce_dag": (i32, [u32, P, P, P, P, P]),
+        "tg_graph_reduce_edges": (i32, [G, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -325,12 +327,16 @@ def tg_graph_checksum(g) -> int:
 
 
 def tg_graph_read_dag(g):
+    """The full (inferred or explicit) DAG as an out-edge CSR."""
     N = tg_graph_num_tasks(g)
-    E = tg_graph_num_edges(g)
     row_ptr = np.zeros(N + 1, np.uint64)
-    col = np.zeros(max(E, 1), np.uint32)
     e = ctypes.c_uint64()
-    _check(load().tg_graph_read_dag(g, _ptr(row_ptr), _ptr(col), E, ctypes.byref(e)), "tg_graph_read_dag")
+    # the first call reports the edge count (its row pointers are complete)
+    st = load().tg_graph_read_dag(g, _ptr(row_ptr), None, 0, ctypes.byref(e))
+    if st not in (TG_OK, TG_ENOMEM):
+        _check(st, "tg_graph_read_dag")
+    col = np.zeros(max(e.value, 1), np.uint32)
+    _check(load().tg_graph_read_dag(g, _ptr(row_ptr), _ptr(col), e.value, ctypes.byref(e)), "tg_graph_read_dag")
     return row_ptr, col[:e.value]
 
 
@@ -429,6 +435,28 @@ def tg_graph_emulate_schedule(g, nworkers: int, window: int = 64, seed: int = 0,
     """One graph: (status, execution order by event)."""
     st, pairs, _, _ = tg_emulate_schedule(g, nworkers, window, seed, schedule)
     return st, pairs[:, 1].astype(np.uint32)
+
+
+def tg_reduce_dag(row_ptr, col):
+    """Two-hop reduction of an out-edge CSR whose ids are a topological order:
+    returns (row_ptr, col) without edges implied by a two-edge path."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.uint64)
+    cl = np.ascontiguousarray(col, dtype=np.uint32)
+    n = rp.size - 1
+    orp = np.zeros(n + 1, np.uint64)
+    ocl = np.zeros(max(cl.size, 1), np.uint32)
+    e = ctypes.c_uint64()
+    _check(load().tg_reduce_dag(n, _ptr(rp), _ptr(cl) if cl.size else None, _ptr(orp), _ptr(ocl), ctypes.byref(e)),
+           "tg_reduce_dag")
+    return orp, ocl[:e.value]
+
+
+def tg_graph_reduce_edges(g) -> int:
+    """Execute an implicit graph on its two-hop-reduced inferred DAG; returns
+    the number of edges dropped (tg_graph_read_dag still returns all)."""
+    removed = ctypes.c_uint64()
+    _check(load().tg_graph_reduce_edges(g, ctypes.byref(removed)), "tg_graph_reduce_edges")
+    return removed.value
 
 
 def tg_graph_execute_comparator(g, mode: int, stream=None):

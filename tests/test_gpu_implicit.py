@@ -136,3 +136,36 @@ def test_c3_execution_r64_gangs(gpu):
     g = tg.graph_from_implicit(ig)
     run(g, tg.make_config(mapping=3, wg_waves=16, gang=8))
     _check_exec(g, ig, _ref(ig))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_reduced_dag_execution(gpu, seed):
+    """Execution on the two-hop-reduced DAG gives the program-order result;
+    the inferred DAG read back is still the full conflict DAG."""
+    ig = wl.random_regions(80, 300, 4, 40, np.random.default_rng(seed), rounds=2, seed=seed)
+    g = tg.graph_from_implicit(ig)
+    full = tg.tg_graph_num_edges(g.handle)
+    removed = tg.tg_graph_reduce_edges(g.handle)
+    assert 0 < removed < full
+    _check_dag(g, ig)
+    for kw in [dict(mapping=1), dict(mapping=2), dict(mapping=3, gang=2, wg_waves=1)]:
+        run(g, tg.make_config(**kw))
+        _check_exec(g, ig, _ref(ig))
+
+
+def test_c3_reduced_r64_four_sweeps(gpu):
+    ig = wl.halo_graph(1024, 16384, 4, seed=0, rounds=64)
+    g = tg.graph_from_implicit(ig)
+    full = tg.tg_graph_num_edges(g.handle)
+    removed = tg.tg_graph_reduce_edges(g.handle)
+    assert full - removed == 1023 * (2 * 4 - 1)  # exact transitive reduction of the halo program
+    run(g, tg.make_config(mapping=3, wg_waves=8, gang=8))
+    _check_exec(g, ig, _ref(ig))
+
+
+def test_reduce_rejects_explicit(gpu):
+    eg = wl.pattern_graph("stencil", 8, 4, seed=0, n=64)
+    g = tg.graph_from_explicit(eg)
+    with pytest.raises(tg.TaskGraphError) as ei:
+        tg.tg_graph_reduce_edges(g.handle)
+    assert ei.value.status == tg.TG_EINVAL
