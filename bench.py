@@ -143,6 +143,7 @@ def main():
     gs = [tg.graph_from_explicit(eg) for eg in egs]
     tasks_per_step = sum(eg.N for eg in egs)
     bytes_per_step = sum(algorithmic_bytes(eg) for eg in egs)
+    edges_per_step = sum(eg.E for eg in egs)
     compile_ms = [tg.tg_graph_timings(g.handle)["compile_ms"] for g in gs]
     log(f"built {len(gs)} graphs ({tasks_per_step} tasks) in {time.time() - t0:.1f}s; compile ms {compile_ms}")
 
@@ -315,6 +316,14 @@ def main():
             "kernel": "k_exec_wave / k_exec_block (persistent executor)",
             "algorithmic_bytes_per_step": bytes_per_step,
             "kernel_ms_per_step": kernel_ms_per_step,
+            # the same bytes against the copy bandwidth this GPU measured
+            "frac_of_measured_copy": (achieved_gbs * 1e9 / probes["copy_bytes_per_s"]
+                                      if probes.get("copy_bytes_per_s") else None),
+            # one device atomic per edge: against the measured distinct-address rate
+            "atomics_per_step": edges_per_step,
+            "atomics_per_s": edges_per_step / (kernel_ms_per_step * 1e-3),
+            "atomics_frac": (edges_per_step / (kernel_ms_per_step * 1e-3) / probes["atomics_distinct_per_s"]
+                             if probes.get("atomics_distinct_per_s") else None),
         },
         "cpu_baseline": cpu,
         "rounds_sweep": sweep,
