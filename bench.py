@@ -247,6 +247,31 @@ def main():
         m = metg50([r["granularity_us"] for r in rows if r["rounds"]], [r["efficiency"] for r in rows if r["rounds"]])
         sweep = {"rows": rows, "metg50_us": m, "peak_word_rounds_per_s": pi}
 
+    # ------------------------------------------------------------- C1
+    # the small configuration: stencil 8x16, 64-word payloads, 16 rounds;
+    # launch + per-level latency, checked against the oracle
+    c1 = None
+    eg1 = wl.pattern_graph("stencil", 8, 16, seed=0, n=64, rounds=16)
+    g1 = tg.graph_from_explicit(eg1)
+    tg.tg_graph_execute(g1.handle, None, stream)
+    tg.tg_graph_wait(g1.handle)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        tg.tg_graph_execute(g1.handle, None, stream)
+    e1.record(stream)
+    tg.tg_graph_wait(g1.handle)
+    torch.cuda.synchronize()
+    c1 = {"graph": "stencil 8x16, n=64, R=16 (128 tasks, 16 levels)", "ms_per_execution": e0.elapsed_time(e1) / 20,
+          "kernel_ms": float(np.mean(tg.tg_graph_kernel_times(g1.handle, 20)))}
+    if not args.no_cpu:
+        import oracle
+        r1 = oracle.exec_explicit(eg1.N, eg1.n, eg1.pred_ptr, eg1.preds, eg1.rounds, seed=0, want_payload=False)
+        c1["parity"] = bool(tg.tg_graph_checksum(g1.handle) == r1["checksum"] and
+                            np.array_equal(tg.tg_graph_read_digests(g1.handle), r1["digest"]))
+    log(f"c1: {c1}")
+    del g1
+
     # ------------------------------------------------------- comparators
     comps = None
     if not args.no_comparators:
@@ -327,6 +352,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "rounds_sweep": sweep,
+        "c1": c1,
         "comparators": comps,
         "probes": probes,
         "compile_ms": dict(zip(wl.PATTERNS, compile_ms)),
