@@ -85,3 +85,23 @@ def test_batch_autotune_keeps_results(gpu):
                 check_explicit(g, eg, oracle_explicit(eg, want_payload=False))
     finally:
         tg.tg_batch_destroy(b)
+
+
+@pytest.mark.parametrize("schedule", [tg.TG_SCHED_COLUMN, tg.TG_SCHED_LEVEL])
+def test_benchmark_step_full_size(gpu, schedule):
+    """The benchmark step at its full size in the launch shapes it is timed
+    in: the five 1024 x 1000 graphs (5,120,000 tasks, 256-word payloads) in
+    one batch on every resident wavefront; every digest and checksum equals
+    the oracle's, on two executions in a row."""
+    egs = [wl.pattern_graph(p, 1024, 1000, seed=0, n=256, rounds=0) for p in wl.PATTERNS]
+    refs = [oracle_explicit(eg, want_payload=False) for eg in egs]
+    gs = [tg.graph_from_explicit(eg) for eg in egs]
+    b = tg.tg_batch_create([g.handle for g in gs], tg.make_config(schedule=schedule))
+    try:
+        for _ in range(2):
+            tg.tg_batch_execute(b)
+            tg.tg_batch_wait(b)
+            for g, eg, ref in zip(gs, egs, refs):
+                check_explicit(g, eg, ref)
+    finally:
+        tg.tg_batch_destroy(b)
