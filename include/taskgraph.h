@@ -114,7 +114,10 @@ typedef struct {
  *                  of every level of a graph to the same worker (graphs packed
  *                  side by side by width) and orders each worker's list by the
  *                  stretched level, so columns stay on one worker and shallow
- *                  graphs fill the gaps of deep ones.
+ *                  graphs fill the gaps of deep ones; TG_SCHED_BALANCED keeps
+ *                  the level order but gives each task to the worker with the
+ *                  least estimated work so far (tasks of very different
+ *                  costs).
  *   gang         : mapping 3: workgroups per gang (2..32).  Member 0 runs the
  *                  scheduling loop and publishes each task to the others; the
  *                  task's work items are split over all members. */
@@ -133,7 +136,7 @@ typedef struct {
 } tg_exec_config;
 
 enum { TG_MAP_WAVE = 1, TG_MAP_WORKGROUP = 2, TG_MAP_GANG = 3 };
-enum { TG_SCHED_LIST = 1, TG_SCHED_LEVEL = 2, TG_SCHED_SPREAD = 3, TG_SCHED_COLUMN = 4 };
+enum { TG_SCHED_LIST = 1, TG_SCHED_LEVEL = 2, TG_SCHED_SPREAD = 3, TG_SCHED_COLUMN = 4, TG_SCHED_BALANCED = 5 };
 
 /* ------------------------------------------------------------- status */
 const char* tg_status_str(tg_status s);

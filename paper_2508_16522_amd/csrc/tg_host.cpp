@@ -197,7 +197,7 @@ tg_status check_config(const Config& c) {
   if (c.window < 1 || c.window > 64) return fail(TG_EINVAL, "window must be in [1, 64]");
   if (c.idle_sleep < 1 || c.idle_sleep > 64) return fail(TG_EINVAL, "idle_sleep must be in [1, 64]");
   if (c.wg_waves < 1 || c.wg_waves > 16) return fail(TG_EINVAL, "wg_waves must be in [1, 16]");
-  if (c.schedule < TG_SCHED_LIST || c.schedule > TG_SCHED_COLUMN) return fail(TG_EINVAL, "schedule must be 1..4");
+  if (c.schedule < TG_SCHED_LIST || c.schedule > TG_SCHED_BALANCED) return fail(TG_EINVAL, "schedule must be 1..5");
   return TG_OK;
 }
 
@@ -522,6 +522,44 @@ void schedule_columns(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw, 
   }
 }
 
+// Balanced level order: tasks in (dependence level, graph, id) order, each
+// given to the worker with the least estimated work so far (costs as for the
+// list schedule).  Every list is a subsequence of the level order, so it is
+// topological; the workers' total work stays even when task costs differ by
+// orders of magnitude (graphs of very different payloads and mix rounds).
+void schedule_balanced(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw, std::vector<uint32_t>& wlen,
+                       std::vector<uint64_t>& seq) {
+  uint32_t maxlevel = 0;
+  for (auto g : gs)
+    for (uint32_t lv : g->level) maxlevel = std::max(maxlevel, lv);
+  std::vector<uint64_t> lstart((size_t)maxlevel + 2, 0);
+  for (auto g : gs)
+    for (uint32_t lv : g->level) lstart[lv + 1]++;
+  for (size_t i = 1; i < lstart.size(); ++i) lstart[i] += lstart[i - 1];
+  std::vector<uint64_t> sorted(N);
+  for (uint32_t gi = 0; gi < gs.size(); ++gi) {
+    const auto& lv = gs[gi]->level;
+    for (uint32_t v = 0; v < lv.size(); ++v) sorted[lstart[lv[v]]++] = ((uint64_t)gi << 32) | v;
+  }
+  typedef std::pair<uint64_t, uint32_t> Load;  // (work so far, worker)
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (uint32_t w = 0; w < nw; ++w) heap.push(Load(0, w));
+  std::vector<uint32_t> owner(N);
+  wlen.assign(nw, 0);
+  for (uint64_t si = 0; si < N; ++si) {
+    Load l = heap.top();
+    heap.pop();
+    owner[si] = l.second;
+    wlen[l.second]++;
+    l.first += task_cost(gs[sorted[si] >> 32], (uint32_t)sorted[si]);
+    heap.push(l);
+  }
+  std::vector<uint64_t> off(nw + 1, 0);
+  for (uint32_t w = 0; w < nw; ++w) off[w + 1] = off[w] + wlen[w];
+  seq.assign(N, 0);
+  for (uint64_t si = 0; si < N; ++si) seq[off[owner[si]]++] = sorted[si];
+}
+
 // List schedule: simulate nw identical workers.  Whenever workers are free,
 // the ready tasks with the longest remaining path (sum of estimated costs to
 // a sink) start on them, in the order the workers became free; a task's
@@ -675,7 +713,7 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
   if (ntot >= 0xFFFFFFFFull || npred_tot >= 0xFFFFFFFFull || nsucc_tot >= 0xFFFFFFFFull || nreq_tot >= 0xFFFFFFFFull)
     return fail(TG_EINVAL, "layout too large: %llu tasks, %llu edges", (unsigned long long)ntot,
                 (unsigned long long)nsucc_tot);
-  if (schedule < TG_SCHED_LIST || schedule > TG_SCHED_COLUMN) return fail(TG_EINVAL, "schedule must be 1..4");
+  if (schedule < TG_SCHED_LIST || schedule > TG_SCHED_BALANCED) return fail(TG_EINVAL, "schedule must be 1..5");
   const uint32_t N = (uint32_t)ntot;
   uint64_t nw = nw_req;
   if (nw > N) nw = N ? N : 1;
@@ -694,8 +732,10 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
     schedule_levels(gs, N, (uint32_t)nw, wlen, at_pos);
   } else if (schedule == TG_SCHED_SPREAD) {
     schedule_spread(gs, N, (uint32_t)nw, wlen, at_pos);
-  } else {
+  } else if (schedule == TG_SCHED_COLUMN) {
     schedule_columns(gs, N, (uint32_t)nw, wlen, at_pos);
+  } else {
+    schedule_balanced(gs, N, (uint32_t)nw, wlen, at_pos);
   }
   if (keep) {
     keep->wlen = wlen;
@@ -1735,7 +1775,7 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
     c.notify = nt;
     return c;
   };
-  for (uint32_t sch : {TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD, TG_SCHED_COLUMN}) {
+  for (uint32_t sch : {TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD, TG_SCHED_COLUMN, TG_SCHED_BALANCED}) {
     std::vector<tg_exec_config> shapes;
     for (uint32_t w : {rw, rw / 4, rw / 8})
       if (w) shapes.push_back(mk(TG_MAP_WAVE, w, 0, 0));
@@ -1936,7 +1976,7 @@ tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, dou
     c.notify = nt;
     return c;
   };
-  for (uint32_t sch : {TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD, TG_SCHED_COLUMN}) {
+  for (uint32_t sch : {TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD, TG_SCHED_COLUMN, TG_SCHED_BALANCED}) {
     std::vector<Config> shapes;
     for (uint32_t w : {rw, rw / 4})
       if (w) shapes.push_back(mk(TG_MAP_WAVE, w, 0, 0));

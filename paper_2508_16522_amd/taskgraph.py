@@ -22,7 +22,7 @@ TG_OK, TG_EINVAL, TG_ENOMEM, TG_EBUSY, TG_EDEVICE, TG_ETIMEOUT, TG_ESTATE = 0, -
 TG_EXPLICIT, TG_IMPLICIT = 1, 2
 TG_RO, TG_RW = 1, 2
 TG_MAP_WAVE, TG_MAP_WORKGROUP, TG_MAP_GANG = 1, 2, 3
-TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD, TG_SCHED_COLUMN = 1, 2, 3, 4
+TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD, TG_SCHED_COLUMN, TG_SCHED_BALANCED = 1, 2, 3, 4, 5
 TG_CMP_PER_TASK, TG_CMP_HIPGRAPH = 1, 2
 
 # Every symbol the header declares; the CPU test-suite checks the library

@@ -11,7 +11,7 @@ from tests.gpu_util import check_explicit, oracle_explicit, run
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("schedule", [tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL, tg.TG_SCHED_SPREAD, tg.TG_SCHED_COLUMN])
+@pytest.mark.parametrize("schedule", [tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL, tg.TG_SCHED_SPREAD, tg.TG_SCHED_COLUMN, tg.TG_SCHED_BALANCED])
 @pytest.mark.parametrize("mapping", [1, 2])
 def test_mixed_batch(gpu, mapping, schedule):
     specs = wl.batch_manifest(24, seed=3, wmax=64, tmax=32)
@@ -75,7 +75,7 @@ def test_batch_autotune_keeps_results(gpu):
         for R in (0, 40):
             tg.tg_batch_set_rounds(b, R)
             cfg, ms = tg.tg_batch_autotune(b, reps=1)
-            assert ms > 0 and cfg["schedule"] in (tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL, tg.TG_SCHED_SPREAD, tg.TG_SCHED_COLUMN)
+            assert ms > 0 and cfg["schedule"] in (tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL, tg.TG_SCHED_SPREAD, tg.TG_SCHED_COLUMN, tg.TG_SCHED_BALANCED)
             _, _, times = tg.tg_batch_info(b, with_times=True)
             assert times["build_ms"] >= times["plan_ms"] >= 0
             tg.tg_batch_execute(b)

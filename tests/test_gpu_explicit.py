@@ -29,7 +29,7 @@ def test_patterns_ragged(gpu, pattern, n, mapping):
     check_explicit(g, eg, ref, payload_sample=64)
 
 
-@pytest.mark.parametrize("schedule", [tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL, tg.TG_SCHED_SPREAD, tg.TG_SCHED_COLUMN])
+@pytest.mark.parametrize("schedule", [tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL, tg.TG_SCHED_SPREAD, tg.TG_SCHED_COLUMN, tg.TG_SCHED_BALANCED])
 @pytest.mark.parametrize("workers,window", [(1, 64), (1, 1), (7, 3), (64, 64), (0, 1), (0, 64)])
 @pytest.mark.parametrize("mapping", [1, 2])
 def test_worker_and_window_variants(gpu, mapping, workers, window, schedule):

@@ -22,7 +22,7 @@ def _check_order(eg, order):
         assert all(pos[p] < pos[v] for p in s), f"task {v} ran before a predecessor"
 
 
-SCHEDULES = [tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL, tg.TG_SCHED_SPREAD, tg.TG_SCHED_COLUMN]
+SCHEDULES = [tg.TG_SCHED_LIST, tg.TG_SCHED_LEVEL, tg.TG_SCHED_SPREAD, tg.TG_SCHED_COLUMN, tg.TG_SCHED_BALANCED]
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
@@ -111,7 +111,7 @@ def test_emulator_rejects_bad_arguments(tglib):
     assert st == tg.TG_EINVAL
     st, _ = tg.tg_graph_emulate_schedule(g.handle, 0, 8)
     assert st == tg.TG_EINVAL
-    st, _ = tg.tg_graph_emulate_schedule(g.handle, 4, 8, schedule=5)
+    st, _ = tg.tg_graph_emulate_schedule(g.handle, 4, 8, schedule=6)
     assert st == tg.TG_EINVAL
 
 
