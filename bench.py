@@ -96,11 +96,12 @@ def main():
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="run only the copy-bandwidth probe (short runs under a counter profiler)")
     ap.add_argument("--comparator-steps", type=int, default=50, help="timesteps of the comparator sub-graph")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
-                    help="c2 (default): the bench line; c3 implicit, c4 4096-graph batch, c5 serving")
-    ap.add_argument("--graphs", type=int, default=4096, help="c4: number of graphs")
-    ap.add_argument("--requests", type=int, default=10000, help="c5: measured requests")
-    ap.add_argument("--rate", type=float, default=2000.0, help="c5: arrivals per second")
+    ap.add_argument("--workload", default="step", choices=["step", "implicit", "batch", "serving"],
+                    help="step (default): the five-graph step; implicit: the 2^16-task halo program; "
+                         "batch: 4096 uneven graphs in one launch; serving: Poisson request replay")
+    ap.add_argument("--graphs", type=int, default=4096, help="batch: number of graphs")
+    ap.add_argument("--requests", type=int, default=10000, help="serving: measured requests")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serving: arrivals per second")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (its executor is single-device); use --gpus 1",
@@ -118,7 +119,7 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    if args.workload != "c2":
+    if args.workload != "step":
         import bench_workloads
         out = getattr(bench_workloads, "run_" + args.workload)(args, stream)
         print(json.dumps(out), flush=True)
@@ -247,10 +248,10 @@ def main():
         m = metg50([r["granularity_us"] for r in rows if r["rounds"]], [r["efficiency"] for r in rows if r["rounds"]])
         sweep = {"rows": rows, "metg50_us": m, "peak_word_rounds_per_s": pi}
 
-    # ------------------------------------------------------------- C1
+    # ----------------------------------------------------- small stencil
     # the small configuration: stencil 8x16, 64-word payloads, 16 rounds;
     # launch + per-level latency, checked against the oracle
-    c1 = None
+    small = None
     eg1 = wl.pattern_graph("stencil", 8, 16, seed=0, n=64, rounds=16)
     g1 = tg.graph_from_explicit(eg1)
     tg.tg_graph_execute(g1.handle, None, stream)
@@ -262,14 +263,14 @@ def main():
     e1.record(stream)
     tg.tg_graph_wait(g1.handle)
     torch.cuda.synchronize()
-    c1 = {"graph": "stencil 8x16, n=64, R=16 (128 tasks, 16 levels)", "ms_per_execution": e0.elapsed_time(e1) / 20,
+    small = {"graph": "stencil 8x16, n=64, R=16 (128 tasks, 16 levels)", "ms_per_execution": e0.elapsed_time(e1) / 20,
           "kernel_ms": float(np.mean(tg.tg_graph_kernel_times(g1.handle, 20)))}
     if not args.no_cpu:
         import oracle
         r1 = oracle.exec_explicit(eg1.N, eg1.n, eg1.pred_ptr, eg1.preds, eg1.rounds, seed=0, want_payload=False)
-        c1["parity"] = bool(tg.tg_graph_checksum(g1.handle) == r1["checksum"] and
+        small["parity"] = bool(tg.tg_graph_checksum(g1.handle) == r1["checksum"] and
                             np.array_equal(tg.tg_graph_read_digests(g1.handle), r1["digest"]))
-    log(f"c1: {c1}")
+    log(f"small stencil: {small}")
     del g1
 
     # ------------------------------------------------------- comparators
@@ -352,7 +353,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "rounds_sweep": sweep,
-        "c1": c1,
+        "small_stencil": small,
         "comparators": comps,
         "probes": probes,
         "compile_ms": dict(zip(wl.PATTERNS, compile_ms)),

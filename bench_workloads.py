@@ -1,6 +1,7 @@
 """The non-default measurements of bench.py: implicit inference and
-execution (--workload c3), 4096 independent graphs in one launch (c4) and
-the serving replay (c5).  Each returns one JSON-serialisable record."""
+execution (--workload implicit), 4096 independent graphs in one launch
+(batch) and the serving replay (serving).  Each returns one
+JSON-serialisable record."""
 from __future__ import annotations
 
 import sys
@@ -25,7 +26,7 @@ def _base(value, ms, steps, warmup, config, **extra):
             "data": "synthetic", "config": config, **extra}
 
 
-def run_c3(args, stream):
+def run_implicit(args, stream):
     """2^16 tasks over 2^24 elements in 1024 subregions, halos 1..64, R = 64:
     device inference (timed), then execution."""
     ig = wl.halo_graph(1024, 16384, 64, seed=0, rounds=64)
@@ -34,9 +35,9 @@ def run_c3(args, stream):
     host_s = time.perf_counter() - t0
     tm = tg.tg_graph_timings(g.handle)
     E = tg.tg_graph_num_edges(g.handle)
-    log(f"c3: inferred {E} edges, inference {tm['infer_ms']:.2f} ms, compile {tm['compile_ms']:.1f} ms")
+    log(f"implicit: inferred {E} edges, inference {tm['infer_ms']:.2f} ms, compile {tm['compile_ms']:.1f} ms")
     cfg, ms = tg.tg_graph_autotune(g.handle, reps=1)
-    log(f"c3: tuned {cfg} {ms:.2f} ms")
+    log(f"implicit: tuned {cfg} {ms:.2f} ms")
     for _ in range(args.warmup):
         tg.tg_graph_execute(g.handle, None, stream)
     tg.tg_graph_wait(g.handle)
@@ -57,7 +58,7 @@ def run_c3(args, stream):
     for _ in range(args.steps):
         tg.tg_graph_execute(g.handle, None, stream)
     rms = float(np.mean(tg.tg_graph_kernel_times(g.handle, args.steps)))
-    log(f"c3: reduced DAG {E - removed} edges ({reduce_ms:.0f} ms host), {rms:.2f} ms ({rcfg})")
+    log(f"implicit: reduced DAG {E - removed} edges ({reduce_ms:.0f} ms host), {rms:.2f} ms ({rcfg})")
     return _base(ig.N / (ms * 1e-3), ms, args.steps, args.warmup,
                  {"workload": "implicit halo program: 65536 tasks, 2^24 u32 in 1024 subregions, halos 1..64, R=64",
                   "launch": cfg},
@@ -66,7 +67,7 @@ def run_c3(args, stream):
                  reduced={"edges": E - removed, "reduce_ms": reduce_ms, "ms": rms, "launch": rcfg})
 
 
-def run_c4(args, stream):
+def run_batch(args, stream):
     """4096 independent graphs (frozen manifest) in one persistent launch, vs
     the same graphs launched one after another."""
     import oracle
@@ -78,10 +79,10 @@ def run_c4(args, stream):
         egs.append(eg)
         gs.append(tg.graph_from_explicit(eg))
         if i % 512 == 0:
-            log(f"c4: built {i} graphs, {time.perf_counter() - t0:.0f} s")
+            log(f"batch: built {i} graphs, {time.perf_counter() - t0:.0f} s")
     N = sum(eg.N for eg in egs)
     U = sum(eg.N * eg.n * eg.rounds for eg in egs)
-    log(f"c4: {len(gs)} graphs, {N} tasks, {U:.3e} word-rounds; host build {time.perf_counter() - t0:.0f} s")
+    log(f"batch: {len(gs)} graphs, {N} tasks, {U:.3e} word-rounds; host build {time.perf_counter() - t0:.0f} s")
     # launch shape and schedule: autotuned on a seeded sample of 256 graphs
     # (re-planning the full batch for every candidate would take minutes)
     tune = None
@@ -91,7 +92,7 @@ def run_c4(args, stream):
         bs = tg.tg_batch_create([gs[i].handle for i in sub])
         tune, tms = tg.tg_batch_autotune(bs, reps=1)
         tg.tg_batch_destroy(bs)
-        log(f"c4: autotuned on {len(sub)} graphs: {tune} ({tms:.1f} ms)")
+        log(f"batch: autotuned on {len(sub)} graphs: {tune} ({tms:.1f} ms)")
     cfg = None if tune is None else tg.make_config(
         mapping=tune["mapping"], workers=tune["workers"], wg_waves=tune["wg_waves"], notify=tune["notify"],
         gang=tune.get("gang", 0),
@@ -100,7 +101,7 @@ def run_c4(args, stream):
     b = tg.tg_batch_create([g.handle for g in gs], cfg)
     layout_s = time.perf_counter() - t1
     bcfg, _, btimes = tg.tg_batch_info(b, with_times=True)
-    log(f"c4: layout {layout_s:.1f} s ({btimes}), launch {bcfg}")
+    log(f"batch: layout {layout_s:.1f} s ({btimes}), launch {bcfg}")
     for _ in range(args.warmup):
         tg.tg_batch_execute(b, stream)
     tg.tg_batch_wait(b)
@@ -108,7 +109,7 @@ def run_c4(args, stream):
         tg.tg_batch_execute(b, stream)
     kt = tg.tg_batch_kernel_times(b, args.steps)
     ms = float(np.mean(kt))
-    log(f"c4: batched {ms:.1f} ms")
+    log(f"batch: batched {ms:.1f} ms")
     # parity on the 16 cheapest graphs (oracle, bit-exact digests)
     order = np.argsort([eg.N * eg.n * max(eg.rounds, 1) for eg in egs])[:16]
     parity = True
@@ -137,7 +138,7 @@ def run_c4(args, stream):
                                        "tasks_per_s": seq_tasks / (seq_ms * 1e-3)})
 
 
-def run_c5(args, stream):
+def run_serving(args, stream):
     """Poisson stream of graph submissions (frozen manifest) replayed in real
     time into the continuous-batching server; latency p50/p99 and sustained
     tasks/s."""
@@ -151,7 +152,7 @@ def run_c5(args, stream):
         graphs.append(x)
         handles.append(tg.graph_from_implicit(x) if isinstance(x, wl.ImplicitGraph) else tg.graph_from_explicit(x))
         if i % 1000 == 0:
-            log(f"c5: built {i} requests, {time.perf_counter() - t0:.0f} s")
+            log(f"serving: built {i} requests, {time.perf_counter() - t0:.0f} s")
     srv = tg.tg_server_create(64 << 30, slots=4, max_batch=64)
     tickets = [None] * len(reqs)
 

@@ -69,7 +69,7 @@ def test_long_rows_sorted(gpu):
     _check_exec(g, ig, _ref(ig))
 
 
-def test_c3_dag_full_size(gpu):
+def test_halo_program_dag_full_size(gpu):
     # 2^16 tasks over 2^24 elements in 1024 subregions, halos 1..64
     ig = wl.halo_graph(1024, 16384, 64, seed=0, rounds=64)
     g = tg.graph_from_implicit(ig)
@@ -82,14 +82,14 @@ def test_c3_dag_full_size(gpu):
         assert np.array_equal(col[int(row_ptr[j]):int(row_ptr[j + 1])], want), f"row {j}"
 
 
-def test_c3_full_size_execution_r0(gpu):
+def test_halo_program_execution_r0(gpu):
     ig = wl.halo_graph(1024, 16384, 64, seed=0, rounds=0)
     g = tg.graph_from_implicit(ig)
     run(g, tg.make_config(mapping=2))
     _check_exec(g, ig, _ref(ig))
 
 
-def test_c3_execution_r64_four_sweeps(gpu):
+def test_halo_program_r64_four_sweeps(gpu):
     ig = wl.halo_graph(1024, 16384, 4, seed=0, rounds=64)
     g = tg.graph_from_implicit(ig)
     run(g, tg.make_config(mapping=2))
@@ -129,8 +129,8 @@ def test_random_regions_gangs(gpu, seed):
         _check_exec(g, ig, _ref(ig))
 
 
-def test_c3_execution_r64_gangs(gpu):
-    """The C3 program's first four sweeps at R = 64 with gangs of eight
+def test_halo_program_r64_gangs(gpu):
+    """The halo program's (1024 subregions of 16,384 elements) first four sweeps at R = 64 with gangs of eight
     16-wave workgroups: the whole array and every digest bit-exact."""
     ig = wl.halo_graph(1024, 16384, 4, seed=0, rounds=64)
     g = tg.graph_from_implicit(ig)
@@ -153,7 +153,7 @@ def test_reduced_dag_execution(gpu, seed):
         _check_exec(g, ig, _ref(ig))
 
 
-def test_c3_reduced_r64_four_sweeps(gpu):
+def test_halo_program_reduced_r64(gpu):
     ig = wl.halo_graph(1024, 16384, 4, seed=0, rounds=64)
     g = tg.graph_from_implicit(ig)
     full = tg.tg_graph_num_edges(g.handle)

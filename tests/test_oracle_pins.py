@@ -250,7 +250,7 @@ def test_halo_dag_closed_form(P, iters, want):
     assert _dag_edges(ig.N, row_ptr, col) == C.element_conflict_dag(ig)
 
 
-def test_c3_closed_form_edge_count():
+def test_halo_program_closed_form_edge_count():
     assert C.halo_edge_count(1024, 64) == 6254592
 
 
