@@ -61,7 +61,7 @@ def metg50(gran_us, eff):
 def traffic_from_profile(kernel_hash):
     """HBM bytes per step from the committed counter profile, if it was taken
     on the current executor kernel source."""
-    path = os.path.join(ROOT, "profiles", "c2_r0_traffic.json")
+    path = os.path.join(ROOT, "profiles", "five_graph_step_r0_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
