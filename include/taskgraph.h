@@ -358,7 +358,8 @@ tg_status tg_probe(uint32_t kind, double* value);
  * A request larger than the whole budget fails with TG_ENOMEM. */
 tg_status tg_server_create(tg_server* out, uint64_t budget_bytes, uint32_t slots, uint32_t max_batch);
 /* Non-blocking.  g must be compiled (finalised) and not executing; the caller
- * keeps ownership and must not touch g until the ticket is waited for. */
+ * keeps ownership and must not touch g until the ticket is waited for.  A
+ * graph whose request has not finished cannot be submitted again: TG_EBUSY. */
 tg_status tg_server_submit(tg_server srv, tg_graph g, uint64_t* ticket);
 /* Blocks until the request finished; returns its status and the steady-clock
  * times (ns) of submission, admission and completion.  Each ticket is waited

@@ -23,6 +23,7 @@
 #include <thread>
 #include <tuple>
 #include <unordered_map>
+#include <unordered_set>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -2218,6 +2219,7 @@ struct tg_server_s {
   std::vector<std::unique_ptr<Slot>> slots;
   std::deque<Req*> pending;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
+  std::unordered_set<tg_graph> live;  // graphs of requests not yet finished
   std::mutex mu;
   std::condition_variable cv_done, cv_work;
   std::thread th;
@@ -2260,6 +2262,15 @@ void release_graph_device(tg_graph g) {
   g->released = true;
 }
 
+// Marks a request finished (the server's lock is held): its graph may be
+// submitted again.
+void finish_req(tg_server srv, tg_server_s::Req* r, tg_status st, uint64_t t) {
+  r->status = st;
+  r->t_done = t;
+  r->done = true;
+  srv->live.erase(r->g);
+}
+
 // Builder thread of one slot: compile the assigned batch into a layout and
 // launch it on the slot's stream.
 void slot_builder(tg_server srv, tg_server_s::Slot* sl) {
@@ -2293,9 +2304,7 @@ void slot_builder(tg_server srv, tg_server_s::Slot* sl) {
     if (st != TG_OK) {
       for (auto* r : batch) {
         srv->in_use -= r->bytes;
-        r->status = st;
-        r->t_done = now_ns();
-        r->done = true;
+        finish_req(srv, r, st, now_ns());
       }
       sl->lay.reset();
       sl->reqs.clear();
@@ -2334,9 +2343,7 @@ void server_loop(tg_server srv) {
       for (auto* r : done) {
         srv->in_use -= r->bytes;
         srv->tasks_done += r->g->N();
-        r->status = st;
-        r->t_done = t;
-        r->done = true;
+        finish_req(srv, r, st, t);
       }
       sl.state = tg_server_s::Slot::kIdle;
       srv->retire_ms += (now_ns() - t) * 1e-6;
@@ -2355,9 +2362,7 @@ void server_loop(tg_server srv) {
         auto* r = srv->pending.front();
         if (r->bytes > srv->budget) {  // can never fit
           srv->pending.pop_front();
-          r->status = TG_ENOMEM;
-          r->t_done = now_ns();
-          r->done = true;
+          finish_req(srv, r, TG_ENOMEM, now_ns());
           srv->cv_done.notify_all();
           continue;
         }
@@ -2428,6 +2433,7 @@ tg_status tg_server_submit(tg_server srv, tg_graph g, uint64_t* ticket) {
   r->bytes = graph_device_bytes(g);
   r->t_submit = now_ns();
   std::lock_guard<std::mutex> lk(srv->mu);
+  if (!srv->live.insert(g).second) return fail(TG_EBUSY, "graph already submitted and not finished");
   r->ticket = srv->next_ticket++;
   *ticket = r->ticket;
   srv->pending.push_back(r.get());

@@ -9,6 +9,7 @@ fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -164,6 +165,14 @@ def _stream(stream):
 
 _alloc_cb = None
 _free_cb = None
+_exiting = False
+
+
+def _mark_exiting():
+    # graphs still alive at interpreter exit are destroyed while modules are
+    # torn down; their device memory goes with the process, so frees stop here
+    global _exiting
+    _exiting = True
 
 
 def use_torch_allocator() -> bool:
@@ -188,9 +197,11 @@ def use_torch_allocator() -> bool:
             return None
 
     def _free(ptr, _ctx):
-        torch.cuda.caching_allocator_delete(int(ptr))
+        if not _exiting:
+            torch.cuda.caching_allocator_delete(int(ptr))
 
     a, f = ALLOC(_alloc), FREE(_free)
+    atexit.register(_mark_exiting)  # after torch's own handlers were registered: runs first
     _check(load().tg_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p), None),
            "tg_set_allocator")
     _alloc_cb, _free_cb = a, f

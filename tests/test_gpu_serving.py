@@ -95,3 +95,30 @@ def test_budget_admission(gpu):
         tg.tg_server_destroy(srv)
     for x, h in zip(graphs, handles):
         assert np.array_equal(tg.tg_graph_read_digests(h.handle), _ref(x)["digest"])
+
+
+def test_resubmit_while_pending_is_refused(gpu):
+    # a graph can be in one unfinished request at a time; once that request
+    # finished it can be served again, with the same result
+    reqs = _small_requests(2, seed=3)
+    graphs, handles = _build(reqs)
+    # one slot, batches of one: a slow graph first keeps handles[0] pending
+    slow = wl.pattern_graph("stencil", 64, 50, seed=4, n=256, rounds=1024)
+    hs = tg.graph_from_explicit(slow)
+    srv = tg.tg_server_create(8 << 30, slots=1, max_batch=1)
+    try:
+        ts = tg.tg_server_submit(srv, hs.handle)
+        t0 = tg.tg_server_submit(srv, handles[0].handle)
+        with pytest.raises(tg.TaskGraphError) as ei:
+            tg.tg_server_submit(srv, handles[0].handle)
+        assert ei.value.status == tg.TG_EBUSY
+        t1 = tg.tg_server_submit(srv, handles[1].handle)
+        for t in (ts, t0, t1):
+            tg.tg_server_wait(srv, t)
+        t2 = tg.tg_server_submit(srv, handles[0].handle)
+        tg.tg_server_wait(srv, t2)
+    finally:
+        tg.tg_server_destroy(srv)
+    for x, h in zip(graphs, handles):
+        assert np.array_equal(tg.tg_graph_read_digests(h.handle), _ref(x)["digest"])
+    assert np.array_equal(tg.tg_graph_read_digests(hs.handle), _ref(slow)["digest"])
