@@ -58,18 +58,19 @@ def metg50(gran_us, eff):
     return None
 
 
-def traffic_from_profile(kernel_hash):
-    """HBM bytes per step from the committed counter profile, if it was taken
-    on the current executor kernel source."""
+def counters_from_profile(kernel_hash):
+    """Counter figures per step (HBM bytes, L2 atomic requests, L2 hit
+    fraction) from the committed counter profiles, if they were taken on the
+    current executor kernel source; else an empty dict."""
     path = os.path.join(ROOT, "profiles", "five_graph_step_r0_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     if d.get("kernel_source_sha1") != kernel_hash:
-        return None
-    return d.get("hbm_bytes_per_step")
+        return {}
+    return d
 
 
 def kernel_source_hash():
@@ -313,7 +314,8 @@ def main():
         log(f"comparators: {comps}")
         del g
 
-    traffic = traffic_from_profile(kernel_source_hash())
+    counters = counters_from_profile(kernel_source_hash())
+    traffic = counters.get("hbm_bytes_per_step")
     out = {
         "metric": "tasks/sec + per-task overhead (ns) + min effective task granularity, 1 GPU",
         "value": value,
@@ -356,6 +358,10 @@ def main():
             "atomics_per_s": edges_per_step / (kernel_ms_per_step * 1e-3),
             "atomics_frac": (edges_per_step / (kernel_ms_per_step * 1e-3) / probes["atomics_distinct_per_s"]
                              if probes.get("atomics_distinct_per_s") else None),
+            # the same executor under counters: L2 atomic requests per step
+            # (equal to the edge count) and the L2 hit fraction
+            "atomics_counted_per_step": counters.get("l2_atomic_requests_per_step"),
+            "l2_hit_fraction": counters.get("l2_hit_fraction"),
         },
         "cpu_baseline": cpu,
         "rounds_sweep": sweep,
