@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 namespace tg {
@@ -50,15 +51,18 @@ __global__ void k_bucket_count(const IvDev* iv, uint32_t M, uint32_t shift, uint
   for (uint64_t b = x.lo >> shift; b <= (x.hi - 1) >> shift; ++b) atomicAdd(bcnt + b, 1u);
 }
 
+// bent holds nent entries (counted on the host with the same rule as
+// k_bucket_count; the host checks the two totals agree).
 __global__ void k_bucket_fill(const IvDev* iv, uint32_t M, uint32_t shift, const uint64_t* bptr, uint32_t* bfill,
-                              uint32_t* bent) {
+                              uint32_t* bent, uint64_t nent) {
   const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= M) return;
   const IvDev x = iv[a];
   if (x.lo >= x.hi) return;
   for (uint64_t b = x.lo >> shift; b <= (x.hi - 1) >> shift; ++b) {
     const uint32_t slot = atomicAdd(bfill + b, 1u);
-    bent[bptr[b] + slot] = a;
+    const uint64_t pos = bptr[b] + slot;
+    if (pos < nent) bent[pos] = a;
   }
 }
 
@@ -368,13 +372,31 @@ hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr_p, const void* r
   while (((space + (1ull << shift) - 1) >> shift) > (1ull << 26)) shift++;
   const uint64_t nbuckets = (space + (1ull << shift) - 1) >> shift;
   std::vector<IvDev> iv(M ? M : 1);
+  uint64_t nent = 0;  // bucket entries: one per (non-empty interval, bucket it touches)
   for (uint32_t k = 0; k < N; ++k)
     for (uint64_t a = req_ptr[k]; a < req_ptr[k + 1]; ++a) {
       iv[a].lo = reqs[a].lo;
       iv[a].hi = reqs[a].hi;
       iv[a].priv = reqs[a].priv;
       iv[a].task = k;
+      if (reqs[a].hi > reqs[a].lo) nent += ((reqs[a].hi - 1) >> shift) - (reqs[a].lo >> shift) + 1;
     }
+  // The edge count is read back through one pinned word, allocated once per
+  // process (outside the timed region) and shared under a lock.
+  static std::mutex pinned_mu;
+  static uint64_t* pinned = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(pinned_mu);
+    if (!pinned) {
+      void* p = nullptr;
+      const hipError_t pe = hipHostMalloc(&p, 64, hipHostMallocDefault);
+      if (pe != hipSuccess) {
+        err = "hipHostMalloc of the read-back word";
+        return pe;
+      }
+      pinned = (uint64_t*)p;
+    }
+  }
   hipStream_t st;
   hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -387,7 +409,7 @@ hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr_p, const void* r
   IvDev* d_iv = nullptr;
   uint64_t *d_req = nullptr, *d_bptr = nullptr, *d_row = nullptr;
   uint32_t *d_bcnt = nullptr, *d_bent = nullptr, *d_rcnt = nullptr, *d_col = nullptr;
-  uint64_t nent = 0, E = 0;
+  uint64_t E = 0;
   const uint32_t M32 = (uint32_t)M;
   auto cleanup = [&]() {
     (void)hipFree(d_iv); (void)hipFree(d_req); (void)hipFree(d_bptr); (void)hipFree(d_row);
@@ -402,6 +424,7 @@ hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr_p, const void* r
   ICHK(hipMalloc(&d_bptr, (nbuckets + 1) * 8));
   ICHK(hipMalloc(&d_rcnt, (size_t)N * 4));
   ICHK(hipMalloc(&d_row, ((size_t)N + 1) * 8));
+  ICHK(hipMalloc(&d_bent, (nent ? nent : 1) * 4));
   // uploads are ordered on the inference stream itself (the host vectors
   // outlive the final stream synchronisation)
   ICHK(hipMemcpyAsync(d_iv, iv.data(), iv.size() * sizeof(IvDev), hipMemcpyHostToDevice, st));
@@ -412,12 +435,10 @@ hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr_p, const void* r
     hipLaunchKernelGGL(k_bucket_count, dim3((M32 + 255) / 256), dim3(256), 0, st, d_iv, M32, shift, d_bcnt);
     ICHK(hipGetLastError());
   }
-  ICHK(scan_counts(d_bcnt, nbuckets, d_bptr, st));
-  ICHK(hipMemcpy(&nent, d_bptr + nbuckets, 8, hipMemcpyDeviceToHost));
-  ICHK(hipMalloc(&d_bent, (nent ? nent : 1) * 4));
+  ICHK(scan_counts(d_bcnt, nbuckets, d_bptr, st));  // d_bptr[nbuckets] == nent
   ICHK(hipMemsetAsync(d_bcnt, 0, nbuckets * 4, st));
   if (M32) {
-    hipLaunchKernelGGL(k_bucket_fill, dim3((M32 + 255) / 256), dim3(256), 0, st, d_iv, M32, shift, d_bptr, d_bcnt, d_bent);
+    hipLaunchKernelGGL(k_bucket_fill, dim3((M32 + 255) / 256), dim3(256), 0, st, d_iv, M32, shift, d_bptr, d_bcnt, d_bent, nent);
     ICHK(hipGetLastError());
   }
   const uint32_t rblocks = (uint32_t)(((uint64_t)N * 64 + 255) / 256);
@@ -425,7 +446,19 @@ hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr_p, const void* r
                      (const uint64_t*)nullptr, (uint32_t*)nullptr);
   ICHK(hipGetLastError());
   ICHK(scan_counts(d_rcnt, N, d_row, st));
-  ICHK(hipMemcpy(&E, d_row + N, 8, hipMemcpyDeviceToHost));
+  {
+    // ordered after the count pass on the inference stream itself
+    std::lock_guard<std::mutex> lk(pinned_mu);
+    ICHK(hipMemcpyAsync(pinned, d_row + N, 8, hipMemcpyDeviceToHost, st));
+    ICHK(hipMemcpyAsync(pinned + 1, d_bptr + nbuckets, 8, hipMemcpyDeviceToHost, st));
+    ICHK(hipStreamSynchronize(st));
+    E = pinned[0];
+    if (pinned[1] != nent) {
+      err = "bucket entry count differs between host and device";
+      cleanup();
+      return hipErrorUnknown;
+    }
+  }
   if (E >= 0xFFFFFFFFull) { err = "inferred DAG has too many edges"; cleanup(); return hipErrorInvalidValue; }
   ICHK(hipMalloc(&d_col, (E ? E : 1) * 4));
   hipLaunchKernelGGL(k_rows<true>, dim3(rblocks), dim3(256), 0, st, d_iv, d_req, N, shift, d_bptr, d_bent, d_rcnt,
@@ -439,8 +472,9 @@ hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr_p, const void* r
   (void)hipEventElapsedTime(&ms, e0, e1);
   res.ms = ms;
   res.col.resize(E);
-  ICHK(hipMemcpy(res.row_ptr.data(), d_row, ((size_t)N + 1) * 8, hipMemcpyDeviceToHost));
-  if (E) ICHK(hipMemcpy(res.col.data(), d_col, E * 4, hipMemcpyDeviceToHost));
+  ICHK(hipMemcpyAsync(res.row_ptr.data(), d_row, ((size_t)N + 1) * 8, hipMemcpyDeviceToHost, st));
+  if (E) ICHK(hipMemcpyAsync(res.col.data(), d_col, E * 4, hipMemcpyDeviceToHost, st));
+  ICHK(hipStreamSynchronize(st));
   cleanup();
 #undef ICHK
   return hipSuccess;
