@@ -103,6 +103,7 @@ def main():
     ap.add_argument("--graphs", type=int, default=4096, help="batch: number of graphs")
     ap.add_argument("--requests", type=int, default=10000, help="serving: measured requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: arrivals per second")
+    ap.add_argument("--slots", type=int, default=4, help="serving: launch slots (streams) of the server, 1..4")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (its executor is single-device); use --gpus 1",

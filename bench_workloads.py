@@ -153,7 +153,7 @@ def run_serving(args, stream):
         handles.append(tg.graph_from_implicit(x) if isinstance(x, wl.ImplicitGraph) else tg.graph_from_explicit(x))
         if i % 1000 == 0:
             log(f"serving: built {i} requests, {time.perf_counter() - t0:.0f} s")
-    srv = tg.tg_server_create(64 << 30, slots=4, max_batch=64)
+    srv = tg.tg_server_create(64 << 30, slots=args.slots, max_batch=64)
     tickets = [None] * len(reqs)
 
     def client():
@@ -192,7 +192,7 @@ def run_serving(args, stream):
         parity &= bool(np.array_equal(tg.tg_graph_read_digests(handles[i].handle), ref["digest"]))
     return _base(tasks / span_s, span_s * 1e3, len(lat), warm,
                  {"workload": f"serving: Poisson {args.rate:.0f} req/s, sizes LogNormal(median 4096, sigma 1) in "
-                              "[64, 2^20], explicit/implicit 1:1, 64 GB budget, 4 launch slots"},
+                              f"[64, 2^20], explicit/implicit 1:1, 64 GB budget, {args.slots} launch slots"},
                  latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "max": float(lat.max())},
                  offered_req_per_s=args.rate, server=stats, parity_32_requests=parity)
