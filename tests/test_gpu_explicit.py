@@ -225,7 +225,7 @@ def test_watchdog_path_then_recovery(gpu):
     check_explicit(g, eg, oracle_explicit(eg))
 
 
-@pytest.mark.parametrize("gang,wg_waves", [(2, 1), (3, 4), (8, 16)])
+@pytest.mark.parametrize("gang,wg_waves", [(2, 1), (3, 4), (8, 16), (32, 1)])
 @pytest.mark.parametrize("n", [64, 1024, 65536])
 def test_patterns_gangs(gpu, n, gang, wg_waves):
     """Explicit graphs with a gang of workgroups per task: payload words are

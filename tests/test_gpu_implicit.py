@@ -105,10 +105,11 @@ def test_comparators_implicit(gpu, mode):
     _check_exec(g, ig, _ref(ig))
 
 
-GANGS = [dict(mapping=3, wg_waves=1, gang=2), dict(mapping=3, wg_waves=4, gang=3), dict(mapping=3, wg_waves=16, gang=8)]
+GANGS = [dict(mapping=3, wg_waves=1, gang=2), dict(mapping=3, wg_waves=4, gang=3), dict(mapping=3, wg_waves=16, gang=8),
+         dict(mapping=3, wg_waves=4, gang=16), dict(mapping=3, wg_waves=2, gang=32)]
 
 
-@pytest.mark.parametrize("kw", GANGS, ids=["g2w1", "g3w4", "g8w16"])
+@pytest.mark.parametrize("kw", GANGS, ids=["g2w1", "g3w4", "g8w16", "g16w4", "g32w2"])
 @pytest.mark.parametrize("P,S,iters", [(8, 128, 4), (33, 256, 3)])
 def test_halo_small_gangs(gpu, P, S, iters, kw):
     """A gang of workgroups on several CUs per task: the read-write elements
