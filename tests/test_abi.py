@@ -90,4 +90,13 @@ def test_bad_config_rejected_before_launch(tglib):
     cfg = tg.make_config(mapping=7)
     # not finalised -> state error takes precedence
     assert tglib.tg_graph_execute(g, ctypes.byref(cfg), None) == tg.TG_ESTATE
+    # finalised (host-only for explicit graphs): every out-of-range field is
+    # refused before any device work
+    ev = ctypes.c_uint32()
+    assert tglib.tg_task_add(g, None, 0, 1, ctypes.byref(ev)) == 0
+    assert tglib.tg_graph_finalize(g) == 0
+    for kw in (dict(mapping=4), dict(mapping=3, gang=1), dict(mapping=3, gang=33), dict(window=65),
+               dict(wg_waves=17), dict(idle_sleep=65), dict(schedule=6), dict(mapping=2, wg_waves=17)):
+        cfg = tg.make_config(**kw)
+        assert tglib.tg_graph_execute(g, ctypes.byref(cfg), None) == tg.TG_EINVAL, kw
     tglib.tg_graph_destroy(g)
