@@ -817,7 +817,9 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
       }
     }
   };
-  const uint32_t nthreads = N >= (1u << 17) ? std::max(1u, std::min(8u, std::thread::hardware_concurrency())) : 1u;
+  // records are written in position order (scattered): worth threads from a
+  // few thousand tasks per thread (serving batches are ~10^5 tasks)
+  const uint32_t nthreads = N >= (1u << 14) ? std::max(1u, std::min(8u, std::thread::hardware_concurrency())) : 1u;
   if (nthreads <= 1) {
     build_range(0, N);
   } else {

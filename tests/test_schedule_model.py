@@ -116,7 +116,7 @@ def test_emulator_rejects_bad_arguments(tglib):
 
 
 def test_large_layout_built_in_parallel(tglib):
-    """Layouts of at least 2^17 tasks build their records on several host
+    """Layouts of at least 2^14 tasks build their records on several host
     threads; two graphs of that size together still run exactly once and in
     dependence order in the worker-loop model."""
     egs = [wl.pattern_graph("stencil", 512, 200, seed=1, n=64), wl.pattern_graph("random", 300, 200, seed=2, n=64)]
