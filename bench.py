@@ -106,7 +106,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="serving: launch slots (streams) of the server, 1..4")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (its executor is single-device); use --gpus 1",
+        print("bench.py: the executor runs on one GPU only (it is single-device); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
