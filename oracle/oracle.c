@@ -19,7 +19,7 @@
  *     the result equals running the tasks sequentially in program order.
  *
  * Readings where the paper is silent (the paper uses a floating-point busy
- * loop as task body, Section 6.1; this build uses an exact integer body):
+ * loop as task body, Section 6.1; here the body is an exact integer mix):
  *   - mix_round(x) = M(xorshift32(x)), xorshift32 = Marsaglia's (13,17,5)
  *     triple, M(y) = y*0x9E3779B1 + 0x7F4A7C15 mod 2^32; mix_R = R rounds.
  *   - sm64 = SplitMix64 output function (Steele, Lea, Flood 2014);
