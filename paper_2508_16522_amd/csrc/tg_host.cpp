@@ -132,12 +132,25 @@ tg_status null_stream_fence() {
   return TG_OK;
 }
 
+// Stream for this thread's uploads; unset, they go to the NULL stream.  The
+// serving builder threads set their slot's stream (idle while its batch is
+// built) so that their copies do not queue behind one another on the NULL
+// stream.  Either way an upload has finished when it returns.
+thread_local hipStream_t t_copy_stream = nullptr;
+
 template <class T>
 tg_status upload(DevBuf& d, const std::vector<T>& h) {
   tg_status s = d.alloc(h.size() * sizeof(T));
   if (s != TG_OK) return s;
   const uint64_t t0 = steady_ns();
-  if (!h.empty()) HIPCHK(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (!h.empty()) {
+    if (t_copy_stream) {
+      HIPCHK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, t_copy_stream));
+      HIPCHK(hipStreamSynchronize(t_copy_stream));
+    } else {
+      HIPCHK(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+  }
   t_copy_ns += steady_ns() - t0;
   return TG_OK;
 }
@@ -2289,7 +2302,9 @@ void slot_builder(tg_server srv, tg_server_s::Slot* sl) {
     cfg.workers = srv->workers;
     const uint64_t h0 = t_hook_ns, c0 = t_copy_ns;
     const uint64_t t0 = now_ns();
+    t_copy_stream = sl->st;
     tg_status st = build_layout(gs, cfg, sl->lay, nullptr, false);
+    t_copy_stream = nullptr;
     const uint64_t t1 = now_ns();
     if (st == TG_OK && hipEventRecord(sl->ev0, sl->st) != hipSuccess) st = TG_EDEVICE;
     if (st == TG_OK) st = launch_layout(*sl->lay, cfg, gs, sl->st);
