@@ -122,11 +122,12 @@ struct DevBuf {
   T* as() const { return (T*)p; }
 };
 
-// Host-to-device copies and memsets here run on the NULL stream; for
-// pageable host memory a copy may still be in flight when hipMemcpy returns,
-// and the NULL stream is not ordered with the non-blocking streams kernels
-// may be launched on.  Every function that prepares device data for a launch
-// therefore ends with this fence.
+// Host-to-device copies and memsets here run on the NULL stream (except the
+// uploads of the serving builders, on their slot's stream; upload() waits
+// for those); for pageable host memory a copy may still be in flight when
+// hipMemcpy returns, and the NULL stream is not ordered with the non-blocking
+// streams kernels may be launched on.  Every function that prepares device
+// data for a launch therefore ends with this fence.
 tg_status null_stream_fence() {
   HIPCHK(hipStreamSynchronize(nullptr));
   return TG_OK;
