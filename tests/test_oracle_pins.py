@@ -331,3 +331,97 @@ def test_invalid_requirements_refused():
                           hi=np.array([8, 12], np.uint64), priv=np.array([2, 1], np.uint32), space=12)
     with pytest.raises(RuntimeError):
         oracle.implicit_program_order(1, ig.req_ptr, ig.lo, ig.hi, ig.priv, 1, 12)
+
+
+# ------------------------------------------- literal vectors of the body
+
+def _golden():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "mix_h32_vectors.json")) as f:
+        return json.load(f)
+
+
+def test_mix_vectors_literal():
+    """The mix at R = 0, 1, 2, 16, 64 on four inputs, against vectors
+    computed outside this repository; the pure-Python mix agrees too."""
+    g = _golden()
+    for row in g["mix"]:
+        x = int(row["x"], 16)
+        for key in ("R0", "R1", "R2", "R16", "R64"):
+            R = int(key[1:])
+            want = int(row[key], 16)
+            assert oracle.mix(x, R) == want, (hex(x), R)
+            assert C.mix_py(x, R) == want
+            assert int(C.mix_np(np.array([x], np.uint32), R)[0]) == want
+    assert int(g["mul_inverse"], 16) == C.MUL_INV
+
+
+def test_sm64_h32_vectors_literal():
+    """SplitMix64 from states 0 and 1 and h32 for the explicit (stream 1,
+    including id = 1) and implicit (stream 2) initial values."""
+    g = _golden()
+    for z, v in g["sm64"].items():
+        assert oracle.sm64(int(z)) == int(v, 16)
+        assert C.sm64_py(int(z)) == int(v, 16)
+    for row in g["h32"]:
+        want = int(row["value"], 16)
+        assert oracle.h32(row["seed"], row["stream"], row["idx"]) == want, row
+        assert C.h32_py(row["seed"], row["stream"], row["idx"]) == want
+        assert int(wl.h32(row["seed"], row["stream"], np.array([row["idx"]], np.uint64))[0]) == want
+
+
+# ---------------------------------------- implicit body, task by task
+
+def _check_implicit_rederived(ig):
+    ref = oracle.implicit_program_order(ig.N, ig.req_ptr, ig.lo, ig.hi, ig.priv, ig.rounds, ig.space, seed=ig.seed)
+    A, dig = C.implicit_program_np(ig)
+    bad = np.nonzero(ref["digest"] != dig)[0]
+    assert bad.size == 0, f"digests of tasks {bad[:8]} differ from the re-derivation"
+    assert np.array_equal(ref["A"], A), "final array differs from the re-derivation"
+    assert ref["checksum"] == C.checksum_py(dig)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_implicit_multi_interval_rederived(seed):
+    """Every task of a program whose tasks each declare >= 2 read-write and
+    >= 2 read-only intervals in shuffled order, with task ids k > 0 and
+    several mix rounds: the oracle's final array, every digest and the
+    checksum equal a numpy re-derivation in program order.  This pins the
+    task-id term, the written-element ordinal carried across intervals and
+    the read-only sum over several intervals."""
+    rng = np.random.default_rng(300 + seed)
+    ig = C.multi_interval_program(24, 400, rng, rounds=1 + seed, seed=seed)
+    for k in range(ig.N):
+        p = ig.priv[int(ig.req_ptr[k]):int(ig.req_ptr[k + 1])]
+        assert (p == 2).sum() >= 2 and (p == 1).sum() >= 2
+    _check_implicit_rederived(ig)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_implicit_random_regions_rederived(seed):
+    rng = np.random.default_rng(400 + seed)
+    ig = wl.random_regions(40, 200, 5, 30, rng, rounds=2, seed=seed)
+    _check_implicit_rederived(ig)
+
+
+def test_implicit_halo_rederived():
+    ig = wl.halo_graph(7, 64, 4, seed=5, rounds=3)
+    _check_implicit_rederived(ig)
+
+
+def test_implicit_zero_rounds_closed_form():
+    """R = 0: every written element becomes A ^ c ^ k, so a task that only
+    writes (no read-only interval) xors its id into its elements; applying
+    the same task id twice restores the array."""
+    req_ptr = np.array([0, 1, 2], np.uint64)
+    lo = np.array([3, 3], np.uint64)
+    hi = np.array([11, 11], np.uint64)
+    priv = np.array([2, 2], np.uint32)
+    ig = wl.ImplicitGraph(N=2, req_ptr=req_ptr, lo=lo, hi=hi, priv=priv, space=16, rounds=0, seed=6)
+    r = oracle.implicit_program_order(2, req_ptr, lo, hi, priv, 0, 16, seed=6)
+    A0 = wl.h32(6, 2, np.arange(16, dtype=np.uint64))
+    # task 0 xors 0, task 1 xors 1: net effect A ^ 1 on [3, 11)
+    want = A0.copy()
+    want[3:11] ^= np.uint32(1)
+    assert np.array_equal(r["A"], want)
