@@ -66,24 +66,29 @@ def _csr_from_lists(N: int, lists) -> tuple[np.ndarray, np.ndarray]:
     return ptr, flat
 
 
-def _grid_csr(W: int, T: int, per_step_preds) -> tuple[np.ndarray, np.ndarray]:
-    """Assemble a CSR from per-timestep lane lists.  per_step_preds(t) returns
-    (counts[W], flat_lanes) for timestep t >= 1 (lanes of timestep t-1)."""
+def _csr_from_steps(W: int, T: int, counts: np.ndarray, lanes: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """CSR of a grid graph from per-task predecessor counts (tasks of
+    timesteps 1..T-1, row-major) and their predecessor lanes (lanes of the
+    previous timestep, task after task)."""
     N = W * T
-    counts = np.zeros(N, np.int64)
-    chunks = []
-    for t in range(1, T):
-        c, lanes = per_step_preds(t)
-        counts[t * W:(t + 1) * W] = c
-        chunks.append(lanes.astype(np.int64) + (t - 1) * W)
     ptr = np.zeros(N + 1, np.uint64)
-    ptr[1:] = np.cumsum(counts)
-    flat = np.concatenate(chunks).astype(np.uint32) if chunks else np.zeros(0, np.uint32)
-    return ptr, flat
+    if T > 1:
+        ptr[W + 1:] = np.cumsum(counts.reshape(-1))
+    t_of = np.repeat(np.arange(1, T, dtype=np.int64), W)
+    flat = lanes + np.repeat((t_of - 1) * W, counts.reshape(-1))
+    return ptr, flat.astype(np.uint32)
 
 
 def _log2_floor(W: int) -> int:
     return W.bit_length() - 1
+
+
+def _pairs_to_csr(W, T, first, second):
+    """first, second: (T-1, W) predecessor lanes (second = -1 when absent)."""
+    counts = 1 + (second >= 0).astype(np.int64)
+    pairs = np.stack([first, second], axis=2).reshape(-1, 2)
+    lanes = pairs[pairs >= 0]
+    return _csr_from_steps(W, T, counts, lanes)
 
 
 def pattern_graph(pattern: str, W: int, T: int, seed: int = 0, n: int = 64, rounds: int = 0) -> ExplicitGraph:
@@ -101,6 +106,8 @@ def pattern_graph(pattern: str, W: int, T: int, seed: int = 0, n: int = 64, roun
     random  : min(5, |window|) distinct lanes of the window
               [max(0,i-16), min(W-1,i+16)] by a partial Fisher-Yates shuffle
               with draws h32(seed, 4, id*8+d); stored ascending.
+    Predecessor lists are built for all timesteps at once (arrays of shape
+    (T-1, W, ...)).
     """
     if pattern not in PATTERNS:
         raise ValueError(pattern)
@@ -108,83 +115,80 @@ def pattern_graph(pattern: str, W: int, T: int, seed: int = 0, n: int = 64, roun
         raise ValueError("W and T must be >= 1")
     N = W * T
     lanes = np.arange(W, dtype=np.int64)
+    steps = np.arange(1, T, dtype=np.int64)[:, None]  # (T-1, 1)
+    L = _log2_floor(W)
     if pattern == "none":
         ptr, flat = np.zeros(N + 1, np.uint64), np.zeros(0, np.uint32)
     elif pattern == "stencil":
         lo = np.maximum(lanes - 1, 0)
         hi = np.minimum(lanes + 1, W - 1)
         c = hi - lo + 1
-        lst = np.concatenate([np.arange(a, b + 1) for a, b in zip(lo, hi)])
-
-        def step(t):
-            return c, lst
-        ptr, flat = _grid_csr(W, T, step)
+        row = np.concatenate([np.arange(a, b + 1) for a, b in zip(lo, hi)])
+        ptr, flat = _csr_from_steps(W, T, np.tile(c, T - 1), np.tile(row, T - 1))
     elif pattern == "fft":
-        L = _log2_floor(W)
-
-        def step(t):
-            if L == 0:
-                return np.ones(W, np.int64), lanes
-            partner = lanes ^ (1 << (t % L))
+        if L == 0:
+            ptr, flat = _csr_from_steps(W, T, np.ones((T - 1) * W, np.int64), np.tile(lanes, T - 1))
+        else:
+            partner = lanes[None, :] ^ (1 << (steps % L))
             ok = partner < W
-            c = 1 + ok.astype(np.int64)
-            lo_l = np.minimum(lanes, partner)
-            hi_l = np.maximum(lanes, partner)
-            # two entries per lane, the second dropped where the partner is out of range
-            pairs = np.stack([np.where(ok, lo_l, lanes), hi_l], 1)
-            keep = np.stack([np.ones(W, bool), ok], 1)
-            return c, pairs[keep]
-        ptr, flat = _grid_csr(W, T, step)
+            first = np.where(ok, np.minimum(lanes[None, :], partner), lanes[None, :])
+            second = np.where(ok, np.maximum(lanes[None, :], partner), -1)
+            ptr, flat = _pairs_to_csr(W, T, first, second)
     elif pattern == "tree":
-        L = _log2_floor(W)
-        P = 1 << L
-
-        def step(t):
-            if L == 0:
-                return np.ones(W, np.int64), lanes
-            p = (t - 1) % (2 * L)
-            first = lanes.copy()
-            second = np.full(W, -1, np.int64)
-            if p < L:
-                s_ = 1 << (L - 1 - p)
-                act = (lanes < P) & (lanes % s_ == 0)
-                first = np.where(act, lanes - (lanes % (2 * s_)), lanes)
-            else:
-                s_ = 1 << (p - L)
-                act = (lanes < P) & (lanes % (2 * s_) == 0)
-                second = np.where(act, lanes + s_, -1)
-            c = 1 + (second >= 0).astype(np.int64)
-            pairs = np.stack([first, second], 1)
-            return c, pairs[pairs >= 0]
-        ptr, flat = _grid_csr(W, T, step)
+        if L == 0:
+            ptr, flat = _csr_from_steps(W, T, np.ones((T - 1) * W, np.int64), np.tile(lanes, T - 1))
+        else:
+            P = 1 << L
+            p = (steps - 1) % (2 * L)  # (T-1, 1)
+            out = p < L
+            s_out = np.where(out, 1 << np.maximum(L - 1 - p, 0), 1)
+            s_in = np.where(out, 1, 1 << np.maximum(p - L, 0))
+            li = lanes[None, :]
+            act_out = out & (li < P) & (li % s_out == 0)
+            first = np.where(act_out, li - (li % (2 * s_out)), li)
+            act_in = ~out & (li < P) & (li % (2 * s_in) == 0)
+            second = np.where(act_in, li + s_in, -1)
+            ptr, flat = _pairs_to_csr(W, T, np.broadcast_to(first, (T - 1, W)), np.broadcast_to(second, (T - 1, W)))
     else:  # random
-        ptr = np.zeros(N + 1, np.uint64)
-        counts = np.zeros(N, np.int64)
-        chunks = []
         lo = np.maximum(lanes - 16, 0)
         hi = np.minimum(lanes + 16, W - 1)
         wlen = hi - lo + 1
         m = np.minimum(5, wlen)
-        maxlen = max(int(wlen.max()), 5)
-        for t in range(1, T):
-            ids = t * W + lanes
-            # candidate windows, padded; only the first wlen entries are valid
-            cand = lo[:, None] + np.arange(maxlen)[None, :]
+        S = T - 1
+        if S == 0:
+            ptr, flat = np.zeros(N + 1, np.uint64), np.zeros(0, np.uint32)
+        else:
+            # Partial Fisher-Yates over each task's window c[x] = lo + x, run
+            # on all tasks at once.  Only positions 0..4 and the swap targets
+            # are ever written, so the window is kept as its initial values
+            # plus an ordered list of (position, value) writes.
+            ids = (steps * W + lanes[None, :]).reshape(-1)
+            R_ = ids.size
+            lo_r = np.tile(lo, S)
+            mm = np.tile(m, S)
+            wl_ = np.tile(wlen, S)
+            writes = []  # (positions, values), in write order
+
+            def value_at(x):
+                v = lo_r + x
+                for wp, wv in writes:  # later writes win
+                    v = np.where(wp == x, wv, v)
+                return v
+
+            ids8 = ids.astype(np.uint64) * np.uint64(8)
             for d in range(5):
-                act = d < m
-                r = h32(seed, 4, ids.astype(np.uint64) * np.uint64(8) + np.uint64(d)).astype(np.int64)
-                span = np.maximum(wlen - d, 1)
-                j = d + (r % span)
-                rows = np.nonzero(act)[0]
-                a = cand[rows, d].copy()
-                cand[rows, d] = cand[rows, j[rows]]
-                cand[rows, j[rows]] = a
-            sel = np.sort(np.where(np.arange(5)[None, :] < m[:, None], cand[:, :5], np.iinfo(np.int64).max), axis=1)
-            flat_t = sel[sel != np.iinfo(np.int64).max]
-            counts[t * W:(t + 1) * W] = m
-            chunks.append(flat_t + (t - 1) * W)
-        ptr[1:] = np.cumsum(counts)
-        flat = np.concatenate(chunks).astype(np.uint32) if chunks else np.zeros(0, np.uint32)
+                act = d < mm
+                r = h32(seed, 4, ids8 + np.uint64(d)).astype(np.int64)
+                j = d + (r % np.maximum(wl_ - d, 1))
+                vd = value_at(d)
+                vj = value_at(j)
+                writes.append((np.where(act, d, -1), vj))
+                writes.append((np.where(act, j, -1), vd))
+            first5 = np.stack([value_at(d) for d in range(5)], axis=1)
+            big = np.iinfo(np.int64).max
+            sel = np.sort(np.where(np.arange(5)[None, :] < mm[:, None], first5, big), axis=1)
+            lanes_flat = sel[sel != big]
+            ptr, flat = _csr_from_steps(W, T, mm, lanes_flat)
     return ExplicitGraph(N=N, pred_ptr=ptr, preds=flat, n=n, rounds=rounds, seed=seed, W=W, T=T,
                          pattern=pattern)
 
