@@ -1,25 +1,32 @@
 #!/usr/bin/env python3
 """Throughput of the task-DAG executor on one MI355X.
 
-Workload (one "step"): the five Task Bench shaped graphs -- no dependences,
+Headline (one "step"): the five Task Bench shaped graphs -- no dependences,
 1-D stencil, FFT butterfly, binary tree, random 5-of-33 -- each 1024 wide and
 1000 timesteps deep (1,024,000 tasks, 256-word payloads), every task with 0
 mix rounds, so a step measures the executor's overhead: counter resets,
 ready-window scans, payload hand-off and edge signals for 5,120,000 tasks.
-The five independent graphs of a step run as one batched persistent launch
-(their critical paths overlap); each graph's own launch time is reported
-beside it.  Graphs are compiled and the launch shape autotuned once, outside
-the timed region; inputs are resident in HBM when timing starts.
+The five independent graphs of a step run as one batched persistent launch.
+Graphs are compiled and the launch shape autotuned once, outside the timed
+region; inputs are resident in HBM when timing starts.
 
-Printed: one JSON line with tasks/s (value), per-task overhead, METG(50)
-from a sweep of mix rounds, the roofline of the executor kernel, the
-comparators (one kernel per task, hipGraph replay) on a capped sub-graph and
-the sequential CPU oracle timed on this host.
+The same JSON line carries every other configuration:
+  patterns    : each of the five graphs alone -- tasks/s, HBM fraction,
+                latency fraction (levels x the measured dependent hand-off),
+                per-task overhead, and METG(50) from its own mix-round sweep;
+  rounds_sweep: METG(50) of the batched step;
+  comparators : per pattern (1024 x 50), the persistent executor vs one
+                kernel launch per task vs hipGraph replays, same graph;
+  small_stencil, implicit (the 65,536-task halo program), batch (4096
+  graphs in one launch), serving (Poisson replay), cpu_baseline (the
+  sequential oracle on a bounded sample, pinned to one core).
 """
 from __future__ import annotations
 
 import argparse
+import contextlib
 import json
+import math
 import os
 import sys
 import time
@@ -28,7 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 W, T, NWORDS = 1024, 1000, 256
-SWEEP_ROUNDS = (0, 4, 8, 16, 64, 256, 1024, 4096)
+SWEEP_ROUNDS = (0, 4, 8, 16, 32, 64, 256, 1024, 4096)
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 
 
@@ -47,7 +54,6 @@ def algorithmic_bytes(eg) -> int:
 def metg50(gran_us, eff):
     """Smallest granularity with efficiency >= 0.5, interpolated in log space
     between the two sweep points that bracket 0.5 (Task Bench METG(50))."""
-    import math
     pts = sorted(zip(gran_us, eff))
     for (g0, e0), (g1, e1) in zip(pts, pts[1:]):
         if e0 < 0.5 <= e1:
@@ -82,26 +88,162 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = sorted(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = list(range(os.cpu_count() or 1))
+    return {"cpu_model": model, "nproc": os.cpu_count(), "allowed_cores": len(allowed)}, allowed
+
+
+@contextlib.contextmanager
+def pinned_to(core):
+    """Run the calling thread on one core (as taskset -c core would)."""
+    old = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {core})
+    try:
+        yield
+    finally:
+        os.sched_setaffinity(0, old)
+
+
+def timed_execs(tg, g, cfg, stream, reps):
+    """Mean executor-kernel time of reps executions after one warm-up."""
+    import numpy as np
+    tg.tg_graph_execute(g.handle, cfg, stream)
+    tg.tg_graph_wait(g.handle)
+    for _ in range(reps):
+        tg.tg_graph_execute(g.handle, cfg, stream)
+    return float(np.mean(tg.tg_graph_kernel_times(g.handle, reps)))
+
+
+# launch shapes timed for each graph alone (the best one is kept)
+def alone_shapes(tg):
+    return [("wavefronts x resident, column", tg.make_config(mapping=1, schedule=tg.TG_SCHED_COLUMN)),
+            ("wavefronts x resident, level", tg.make_config(mapping=1, schedule=tg.TG_SCHED_LEVEL)),
+            ("wavefronts x 1024, level", tg.make_config(mapping=1, workers=1024, schedule=tg.TG_SCHED_LEVEL))]
+
+
+def leg_patterns(tg, wl, egs, gs, probes, stream):
+    """Each C2 graph alone: best of three launch shapes at R = 0 (tasks/s,
+    HBM and latency fractions, per-task overhead), then its own mix-round
+    sweep in that shape (efficiency against the measured mix rate) and
+    METG(50)."""
+    pi = probes["mix_word_rounds_per_s"]
+    hop_ns = probes.get("handoff_ns")
+    out = {}
+    for p, eg, g in zip(wl.PATTERNS, egs, gs):
+        best = None
+        for name, cfg in alone_shapes(tg):
+            ms = timed_execs(tg, g, cfg, stream, 3)
+            workers, _ = tg.tg_graph_exec_info(g.handle)
+            if best is None or ms < best[1]:
+                best = (name, ms, cfg, workers)
+        name, ms, cfg, workers = best
+        levels = T if p != "none" else 1
+        rec = {"launch": name, "workers": workers, "kernel_ms": ms, "tasks_per_s": eg.N / (ms * 1e-3),
+               "algorithmic_bytes": algorithmic_bytes(eg),
+               "hbm_frac": algorithmic_bytes(eg) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+               "edges": eg.E, "levels": levels,
+               "per_task_overhead_ns": ms * 1e6 * workers / eg.N,
+               "throughput_ns_per_task": ms * 1e6 / eg.N}
+        if hop_ns:
+            rec["latency_floor_ms"] = levels * hop_ns * 1e-6
+            rec["latency_frac"] = levels * hop_ns * 1e-6 / ms
+        rows = []
+        for R in SWEEP_ROUNDS:
+            tg.tg_graph_set_rounds(g.handle, R)
+            rms = timed_execs(tg, g, cfg, stream, 2 if R >= 1024 else 3) if R else ms
+            U = eg.N * eg.n * R
+            rows.append({"rounds": R, "ms": rms, "efficiency": (U / (rms * 1e-3)) / pi if R else 0.0,
+                         "granularity_us": rms * 1e3 * workers / eg.N})
+        tg.tg_graph_set_rounds(g.handle, 0)
+        rec["sweep"] = rows
+        rec["metg50_us"] = metg50([r["granularity_us"] for r in rows if r["rounds"]],
+                                  [r["efficiency"] for r in rows if r["rounds"]])
+        out[p] = rec
+        log(f"alone {p}: {ms:.3f} ms ({name}), {rec['tasks_per_s'] / 1e6:.0f} M tasks/s, hbm {rec['hbm_frac']:.3f}, "
+            f"latency frac {rec.get('latency_frac', 0):.3f}, METG(50) {rec['metg50_us']}")
+    return out
+
+
+def leg_comparators(tg, wl, stream, steps):
+    """Per pattern, on one 1024 x `steps` graph: the persistent executor (its
+    best shape), one kernel launch per task, the hipGraph with one node per
+    task and one dependency per edge, and the captured per-task launch
+    sequence; median of 5 after a warm-up (which also instantiates the
+    hipGraphs, timed separately)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    out = {}
+    for p in wl.PATTERNS:
+        eg = wl.pattern_graph(p, W, steps, seed=0, n=NWORDS, rounds=0)
+        g = tg.graph_from_explicit(eg)
+        ref = oracle.exec_explicit(eg.N, eg.n, eg.pred_ptr, eg.preds, 0, want_payload=False)
+        cfg = tg.make_config(mapping=1, schedule=tg.TG_SCHED_COLUMN)
+        res = {}
+        ok = True
+        for name, fn in [("persistent", lambda: tg.tg_graph_execute(g.handle, cfg, stream)),
+                         ("per_task_launch", lambda: tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_PER_TASK, stream)),
+                         ("hipgraph_dag_replay", lambda: tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_HIPGRAPH, stream)),
+                         ("hipgraph_captured_replay",
+                          lambda: tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_HIPGRAPH_CAPTURED, stream))]:
+            t_b = time.perf_counter()
+            fn()
+            tg.tg_graph_wait(g.handle)
+            first_s = time.perf_counter() - t_b
+            ms = []
+            for _ in range(5):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn()
+                b.record(stream)
+                tg.tg_graph_wait(g.handle)
+                b.synchronize()
+                ms.append(a.elapsed_time(b))
+            ok &= bool(np.array_equal(tg.tg_graph_read_digests(g.handle), ref["digest"]))
+            med = float(np.median(ms))
+            res[name] = {"ms_median": med, "tasks_per_s": eg.N / (med * 1e-3), "first_call_s": first_s}
+        res["parity"] = ok
+        res["persistent_over_per_task"] = res["per_task_launch"]["ms_median"] / res["persistent"]["ms_median"]
+        res["persistent_over_hipgraph"] = min(res["hipgraph_dag_replay"]["ms_median"],
+                                              res["hipgraph_captured_replay"]["ms_median"]) / res["persistent"]["ms_median"]
+        out[p] = res
+        log(f"comparators {p}: " + ", ".join(f"{k} {v['ms_median']:.2f} ms" for k, v in res.items() if isinstance(v, dict)))
+        del g
+    return {"graph": f"each pattern {W} x {steps}, n={NWORDS}, R=0 ({W * steps} tasks); hipGraphs of 5 x 10^4 "
+                     "nodes instantiate in seconds, so larger graphs are not used", "patterns": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-sweep", action="store_true", help="skip the mix-round sweep (METG)")
-    ap.add_argument("--no-comparators", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--skip", default="", help="comma list of legs to leave out: patterns, sweep, comparators, cpu, "
+                                               "implicit, batch, serving")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--no-alone", action="store_true", help="skip timing each graph alone")
     ap.add_argument("--schedule", type=int, default=0,
                     help="with --no-tune: the batch's schedule (1 list, 2 level, 3 spread, 4 column; 0 default)")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="run only the copy-bandwidth probe (short runs under a counter profiler)")
-    ap.add_argument("--comparator-steps", type=int, default=50, help="timesteps of the comparator sub-graph")
+    ap.add_argument("--comparator-steps", type=int, default=50, help="timesteps of the comparator graphs")
     ap.add_argument("--workload", default="step", choices=["step", "implicit", "batch", "serving"],
-                    help="step (default): the five-graph step; implicit: the 2^16-task halo program; "
-                         "batch: 4096 uneven graphs in one launch; serving: Poisson request replay")
+                    help="step (default): every leg, the five-graph step as headline; implicit / batch / "
+                         "serving: that leg alone on its own line")
     ap.add_argument("--graphs", type=int, default=4096, help="batch: number of graphs")
-    ap.add_argument("--requests", type=int, default=10000, help="serving: measured requests")
+    ap.add_argument("--requests", type=int, default=4000, help="serving: measured requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: arrivals per second")
     ap.add_argument("--slots", type=int, default=4, help="serving: launch slots (streams) of the server, 1..4")
     args = ap.parse_args()
@@ -109,10 +251,12 @@ def main():
         print("bench.py: the executor runs on one GPU only (it is single-device); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    skip = set(x for x in args.skip.split(",") if x)
 
     import numpy as np
     import torch
 
+    import bench_workloads as bw
     from paper_2508_16522_amd import taskgraph as tg
     from paper_2508_16522_amd import workloads as wl
 
@@ -121,11 +265,8 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    if args.workload != "step":
-        import bench_workloads
-        out = getattr(bench_workloads, "run_" + args.workload)(args, stream)
-        print(json.dumps(out), flush=True)
-        return
+    t_start = time.time()
+    leg_s = {}
 
     # ---------------------------------------------------------- probes
     if args.copy_probe_only:
@@ -133,12 +274,20 @@ def main():
     else:
         probes = {
             "mix_word_rounds_per_s": tg.tg_probe(tg.TG_PROBE_MIX_RATE),
+            "alu_peak_word_rounds_per_s": bw.ALU_PEAK_WORD_ROUNDS,
             "copy_bytes_per_s": tg.tg_probe(tg.TG_PROBE_COPY_BW),
             "atomics_distinct_per_s": tg.tg_probe(tg.TG_PROBE_ATOMIC_DISTINCT),
             "atomics_contended_per_s": tg.tg_probe(tg.TG_PROBE_ATOMIC_CONTENDED),
             "launches_per_s": tg.tg_probe(tg.TG_PROBE_LAUNCH_RATE),
+            "handoff_ns": tg.tg_probe(tg.TG_PROBE_HANDOFF_NS),
         }
     log(f"probes: {probes}")
+    if args.workload != "step":
+        rec = getattr(bw, "run_" + args.workload)(args, stream, probes)
+        print(json.dumps(bw.base_line(rec["tasks_per_s"], rec.get("exec_ms", rec.get("span_s", 0) * 1e3),
+                                      args.steps, args.warmup, {"workload": rec["workload"]}, leg=rec,
+                                      probes=probes)), flush=True)
+        return
 
     # --------------------------------------------------------- workload
     t0 = time.time()
@@ -150,25 +299,8 @@ def main():
     compile_ms = [tg.tg_graph_timings(g.handle)["compile_ms"] for g in gs]
     log(f"built {len(gs)} graphs ({tasks_per_step} tasks) in {time.time() - t0:.1f}s; compile ms {compile_ms}")
 
-    # each graph alone (autotuned), for reference
-    tuned = {}
-    solo_ms = {}
-    for p, g in zip(wl.PATTERNS, gs):
-        if args.no_alone:
-            break
-        if args.no_tune:
-            tuned[p] = None
-            tg.tg_graph_execute(g.handle, None, stream)
-            tg.tg_graph_wait(g.handle)
-        else:
-            cfg, ms = tg.tg_graph_autotune(g.handle, reps=2)
-            tuned[p] = cfg
-        for _ in range(3):
-            tg.tg_graph_execute(g.handle, None, stream)
-        solo_ms[p] = float(np.mean(tg.tg_graph_kernel_times(g.handle, 3)))
-        log(f"alone {p}: {solo_ms[p]:.3f} ms ({tuned[p]})")
-
     # the step: one batched launch over the five graphs
+    t0 = time.time()
     batch = tg.tg_batch_create([g.handle for g in gs], tg.make_config(schedule=args.schedule))
     if not args.no_tune:
         bcfg, bms = tg.tg_batch_autotune(batch, reps=2)
@@ -202,42 +334,60 @@ def main():
     kernel_ms_per_step = float(np.mean(kt))
     achieved_gbs = bytes_per_step / (kernel_ms_per_step * 1e-3) / 1e9
     log(f"step {ms_per_step:.3f} ms (wall {wall * 1e3 / args.steps:.3f} ms); kernel {kernel_ms_per_step:.3f} ms")
+    leg_s["step"] = time.time() - t0
 
-    # parity of the last timed step against the oracle (digests, checksum)
+    # -------------------------------------------- oracle: parity and baseline
     parity = None
     cpu = None
-    if not args.no_cpu:
+    if "cpu" not in skip:
         import oracle
-        # three passes over the step (~10-15 s of CPU work); the first one's
-        # results are the parity reference
+        t0 = time.time()
+        info, allowed = cpu_info()
+        core = allowed[0]
+        # three passes over the step (~10-15 s of CPU work) on one pinned core;
+        # the first pass's results are the parity reference
         cpu_steps = 3
-        t_cpu = time.perf_counter()
-        for i in range(cpu_steps):
-            out = [oracle.exec_explicit(eg.N, eg.n, eg.pred_ptr, eg.preds, eg.rounds, seed=eg.seed, want_payload=False)
-                   for eg in egs]
-            if i == 0:
-                refs = out
-        cpu_s = time.perf_counter() - t_cpu
+        with pinned_to(core):
+            t_cpu = time.perf_counter()
+            for i in range(cpu_steps):
+                out = [oracle.exec_explicit(eg.N, eg.n, eg.pred_ptr, eg.preds, eg.rounds, seed=eg.seed,
+                                            want_payload=False) for eg in egs]
+                if i == 0:
+                    refs = out
+            cpu_s = time.perf_counter() - t_cpu
         tg.tg_batch_wait(batch)
         parity = all(np.array_equal(tg.tg_graph_read_digests(g.handle), r["digest"]) and
                      tg.tg_graph_checksum(g.handle) == r["checksum"] for g, r in zip(gs, refs))
         cpu = {"value": cpu_steps * tasks_per_step / cpu_s, "unit": "tasks/s", "cores": 1, "kind": "oracle",
                "sample": f"{cpu_steps} full steps: the five {W}x{T} graphs ({tasks_per_step} tasks each step), "
-                         f"0 mix rounds, sequential C oracle (gcc -O2), one thread; {cpu_s:.1f} s"}
-        log(f"cpu oracle: {cpu_s:.1f} s; parity {parity}")
+                         f"0 mix rounds, sequential C oracle (gcc -O2, compiler auto-vectorisation allowed), one "
+                         f"thread pinned to core {core}; {cpu_s:.1f} s",
+               "ns_per_task": cpu_s * 1e9 / (cpu_steps * tasks_per_step), "pinned_core": core, **info}
+        log(f"cpu oracle: {cpu_s:.1f} s; parity {parity}; {info}")
+        leg_s["cpu"] = time.time() - t0
 
-    # ----------------------------------------------- mix-round sweep (METG)
+    # ----------------------------------------------- each graph alone + METG
+    patterns = None
+    if "patterns" not in skip:
+        t0 = time.time()
+        patterns = leg_patterns(tg, wl, egs, gs, probes, stream)
+        leg_s["patterns"] = time.time() - t0
+
+    # ------------------------------------ mix-round sweep of the step (METG)
     sweep = None
-    if not args.no_sweep:
+    if "sweep" not in skip:
+        t0 = time.time()
         pi = probes["mix_word_rounds_per_s"]
         rows = []
+        shape0 = bcfg
+        shape64 = None
         for R in SWEEP_ROUNDS:
             tg.tg_batch_set_rounds(batch, R)
-            # the launch shape is re-tuned for each task size up to 256 rounds;
-            # larger sizes keep the shape tuned at 256
-            if not args.no_tune and 0 < R <= 256:
-                tcfg, tms = tg.tg_batch_autotune(batch, reps=1)
-                log(f"sweep R={R}: autotuned {tcfg} {tms:.3f} ms")
+            # the launch shape is tuned at R = 0 (timed step) and once more at
+            # R = 64; rounds from 64 on use the second shape
+            if R == 64 and not args.no_tune:
+                shape64, tms = tg.tg_batch_autotune(batch, reps=1)
+                log(f"sweep R=64: autotuned {shape64} {tms:.3f} ms")
             rcfg, _ = tg.tg_batch_info(batch)
             slots = rcfg["workers"]
             step()  # warm
@@ -247,19 +397,18 @@ def main():
             ms = float(np.mean(tg.tg_batch_kernel_times(batch, reps)))
             U = tasks_per_step * NWORDS * R
             eff = (U / (ms * 1e-3)) / pi if R else 0.0
-            # granularity: run time per task per concurrent worker (Task Bench METG x-axis)
             gran_us = ms * 1e3 * slots / tasks_per_step
             rows.append({"rounds": R, "ms": ms, "efficiency": eff, "granularity_us": gran_us,
+                         "frac_of_alu_peak": (U / (ms * 1e-3)) / bw.ALU_PEAK_WORD_ROUNDS if R else 0.0,
                          "launch": {k: rcfg[k] for k in ("mapping", "workers", "wg_waves", "notify", "schedule")}})
             log(f"sweep R={R}: {ms:.3f} ms eff {eff:.3f} gran {gran_us:.2f} us")
         tg.tg_batch_set_rounds(batch, 0)
         m = metg50([r["granularity_us"] for r in rows if r["rounds"]], [r["efficiency"] for r in rows if r["rounds"]])
-        sweep = {"rows": rows, "metg50_us": m, "peak_word_rounds_per_s": pi}
+        sweep = {"rows": rows, "metg50_us": m, "peak_word_rounds_per_s": pi, "shape_r0": shape0, "shape_r64": shape64}
+        leg_s["sweep"] = time.time() - t0
 
     # ----------------------------------------------------- small stencil
-    # the small configuration: stencil 8x16, 64-word payloads, 16 rounds;
-    # launch + per-level latency, checked against the oracle
-    small = None
+    t0 = time.time()
     eg1 = wl.pattern_graph("stencil", 8, 16, seed=0, n=64, rounds=16)
     g1 = tg.graph_from_explicit(eg1)
     tg.tg_graph_execute(g1.handle, None, stream)
@@ -272,51 +421,46 @@ def main():
     tg.tg_graph_wait(g1.handle)
     torch.cuda.synchronize()
     small = {"graph": "stencil 8x16, n=64, R=16 (128 tasks, 16 levels)", "ms_per_execution": e0.elapsed_time(e1) / 20,
-          "kernel_ms": float(np.mean(tg.tg_graph_kernel_times(g1.handle, 20)))}
-    if not args.no_cpu:
+             "kernel_ms": float(np.mean(tg.tg_graph_kernel_times(g1.handle, 20)))}
+    if probes.get("handoff_ns"):
+        small["latency_floor_ms"] = 16 * probes["handoff_ns"] * 1e-6
+        small["latency_frac"] = small["latency_floor_ms"] / small["kernel_ms"]
+    if "cpu" not in skip:
         import oracle
         r1 = oracle.exec_explicit(eg1.N, eg1.n, eg1.pred_ptr, eg1.preds, eg1.rounds, seed=0, want_payload=False)
         small["parity"] = bool(tg.tg_graph_checksum(g1.handle) == r1["checksum"] and
-                            np.array_equal(tg.tg_graph_read_digests(g1.handle), r1["digest"]))
+                               np.array_equal(tg.tg_graph_read_digests(g1.handle), r1["digest"]))
     log(f"small stencil: {small}")
     del g1
+    leg_s["small"] = time.time() - t0
 
     # ------------------------------------------------------- comparators
     comps = None
-    if not args.no_comparators:
-        eg = wl.pattern_graph("stencil", W, args.comparator_steps, seed=0, n=NWORDS, rounds=0)
-        g = tg.graph_from_explicit(eg)
-        res = {}
-        tg.tg_graph_execute(g.handle, None, stream)
-        tg.tg_graph_wait(g.handle)
-        for name, fn in [("persistent", lambda: tg.tg_graph_execute(g.handle, None, stream)),
-                         ("per_task_launch", lambda: tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_PER_TASK, stream)),
-                         ("hipgraph_replay", lambda: tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_HIPGRAPH, stream))]:
-            t_b = time.perf_counter()
-            fn()  # warm (builds and instantiates the hipGraph the first time)
-            tg.tg_graph_wait(g.handle)
-            build_s = time.perf_counter() - t_b
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            fn()
-            b.record(stream)
-            tg.tg_graph_wait(g.handle)
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b)
-            res[name] = {"ms": ms, "tasks_per_s": eg.N / (ms * 1e-3), "first_call_s": build_s}
-        ref = None
-        try:
-            import oracle
-            ref = oracle.exec_explicit(eg.N, eg.n, eg.pred_ptr, eg.preds, 0, want_payload=False)
-            res["parity"] = bool(np.array_equal(tg.tg_graph_read_digests(g.handle), ref["digest"]))
-        except ImportError:
-            pass
-        comps = {"graph": f"stencil {W}x{args.comparator_steps}, n={NWORDS}, R=0 ({eg.N} tasks)", **res}
-        log(f"comparators: {comps}")
-        del g
+    if "comparators" not in skip:
+        t0 = time.time()
+        comps = leg_comparators(tg, wl, stream, args.comparator_steps)
+        leg_s["comparators"] = time.time() - t0
 
+    # free the step's device memory before the large legs
     counters = counters_from_profile(kernel_source_hash())
     traffic = counters.get("hbm_bytes_per_step")
+    tg.tg_batch_destroy(batch)
+    del gs
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+
+    legs = {}
+    for name in ("implicit", "batch", "serving"):
+        if name in skip:
+            continue
+        t0 = time.time()
+        legs[name] = getattr(bw, "run_" + name)(args, stream, probes)
+        leg_s[name] = time.time() - t0
+        log(f"{name}: {time.time() - t0:.0f} s")
+        gc.collect()
+        torch.cuda.empty_cache()
+
     out = {
         "metric": "tasks/sec + per-task overhead (ns) + min effective task granularity, 1 GPU",
         "value": value,
@@ -332,13 +476,15 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"Task Bench shaped graphs none/stencil/fft/tree/random, {W} wide x {T} timesteps, "
-                        f"{NWORDS}-word payloads, 0 mix rounds (one step = the five graphs)",
+                        f"{NWORDS}-word payloads, 0 mix rounds (one step = the five graphs in one batched launch)",
             "tasks_per_step": tasks_per_step,
             "launch": bcfg,
         },
-        "alone_ms": solo_ms,
-        "alone_launch": tuned,
-        "per_task_overhead_ns": 1e9 / value,
+        # per-task overhead at R = 0: kernel time x concurrent workers / tasks
+        # (the time one task occupies its worker); the reciprocal throughput
+        # is given beside it
+        "per_task_overhead_ns": kernel_ms_per_step * 1e6 * bcfg["workers"] / tasks_per_step,
+        "throughput_ns_per_task": 1e9 / value,
         "metg50_us": sweep["metg50_us"] if sweep else None,
         "parity": parity,
         "roofline": {
@@ -348,31 +494,33 @@ def main():
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_exec_wave / k_exec_block (persistent executor)",
+            "kernel": "k_exec_wave (persistent executor)",
             "algorithmic_bytes_per_step": bytes_per_step,
             "kernel_ms_per_step": kernel_ms_per_step,
-            # the same bytes against the copy bandwidth this GPU measured
             "frac_of_measured_copy": (achieved_gbs * 1e9 / probes["copy_bytes_per_s"]
                                       if probes.get("copy_bytes_per_s") else None),
-            # one device atomic per edge: against the measured distinct-address rate
             "atomics_per_step": edges_per_step,
             "atomics_per_s": edges_per_step / (kernel_ms_per_step * 1e-3),
             "atomics_frac": (edges_per_step / (kernel_ms_per_step * 1e-3) / probes["atomics_distinct_per_s"]
                              if probes.get("atomics_distinct_per_s") else None),
-            # the same executor under counters: L2 atomic requests per step
-            # (equal to the edge count) and the L2 hit fraction
             "atomics_counted_per_step": counters.get("l2_atomic_requests_per_step"),
             "l2_hit_fraction": counters.get("l2_hit_fraction"),
+            "latency_floor_ms": T * probes["handoff_ns"] * 1e-6 if probes.get("handoff_ns") else None,
+            "latency_frac": (T * probes["handoff_ns"] * 1e-6 / kernel_ms_per_step
+                             if probes.get("handoff_ns") else None),
         },
         "cpu_baseline": cpu,
+        "patterns": patterns,
         "rounds_sweep": sweep,
         "small_stencil": small,
         "comparators": comps,
+        **legs,
         "probes": probes,
         "compile_ms": dict(zip(wl.PATTERNS, compile_ms)),
         "batch_layout_ms": btimes,
+        "leg_seconds": leg_s,
+        "total_seconds": time.time() - t_start,
     }
-    tg.tg_batch_destroy(batch)
     print(json.dumps(out), flush=True)
 
 

@@ -133,7 +133,23 @@ typedef struct {
   uint32_t idle_sleep;
   uint32_t schedule;
   uint32_t gang;
+  uint32_t dispatch;
+  uint32_t tile;
+  uint32_t shards;
 } tg_exec_config;
+/*   dispatch     : TG_DISPATCH_LISTS (default): each worker polls the counters
+ *                  of its own compiled list (schedule, window, notify apply).
+ *                  TG_DISPATCH_QUEUE: ready tasks flow through a ticket queue
+ *                  (Algorithm 1 EXECUTE_OP on the vertex a COMPLETED_EDGE
+ *                  made ready): the decrement that empties a counter makes
+ *                  its task ready; the finishing worker keeps one ready
+ *                  successor as its next task and pushes the others into the
+ *                  queue shard of its XCD (one atomic per wavefront); idle
+ *                  workers claim tiles of tickets (own shard first, then the
+ *                  others).  Wavefront and workgroup mappings only.
+ *   tile         : queue: tickets claimed per pop (1..64, default 1).
+ *   shards       : queue: queue shards (1, 2, 4 or 8; default 8, one per XCD). */
+enum { TG_DISPATCH_LISTS = 1, TG_DISPATCH_QUEUE = 2 };
 
 enum { TG_MAP_WAVE = 1, TG_MAP_WORKGROUP = 2, TG_MAP_GANG = 3 };
 enum { TG_SCHED_LIST = 1, TG_SCHED_LEVEL = 2, TG_SCHED_SPREAD = 3, TG_SCHED_COLUMN = 4, TG_SCHED_BALANCED = 5 };
@@ -192,6 +208,27 @@ tg_status tg_task_add_regions_many(tg_graph g, uint32_t ntasks, const uint64_t* 
                                    const tg_region_req* reqs, const uint32_t* mix_rounds,
                                    uint32_t uniform_rounds, tg_event* first_event);
 
+/* Payload retention of an explicit graph (call before tg_graph_finalize).
+ * By default (TG_KEEP_ALL) every task's payload stays in device memory after
+ * an execution, so memory is #tasks x payload words.  With TG_KEEP_SINKS a
+ * task's payload memory is reused once every task that reads it has
+ * finished: compilation gives each task a payload slot (dependence-level
+ * order, oldest usable free slot first) and adds, for each reused slot, an
+ * anti-dependence edge from every reader of the slot's previous contents to
+ * its new owner -- the counters of Algorithm 1 then order the reuse, so the
+ * memory is about the payloads alive across two or three dependence levels.
+ * Payloads of tasks without successors are kept.  TG_KEEP_NONE reuses those
+ * too (only digests are results).  Anti-dependence edges always go to a
+ * later dependence level: levels and the critical path are unchanged, and
+ * so are digests and kept payloads.  tg_graph_read_payload of a task whose
+ * slot was reused gives TG_ESTATE.  TG_EBUSY after finalize, TG_EINVAL for
+ * implicit graphs. */
+enum { TG_KEEP_ALL = 0, TG_KEEP_SINKS = 1, TG_KEEP_NONE = 2 };
+tg_status tg_graph_set_retention(tg_graph g, uint32_t mode);
+/* Payload slots of a finalised explicit graph: slot_of[v] (may be NULL; one
+ * entry per task), the number of slots and the device bytes they take. */
+tg_status tg_graph_payload_slots(tg_graph g, uint32_t* slot_of, uint64_t* nslots, uint64_t* bytes);
+
 /* Compile the graph (Algorithm 1, Compile): merge duplicate predecessors,
  * build the out-edge CSR and in-degree counters, compute the level-ordered
  * schedule, allocate device state.  Implicit mode first infers the dependence
@@ -232,6 +269,11 @@ tg_status tg_graph_checksum(tg_graph g, uint64_t* out);
  * of task j in ascending order.  row_ptr has #tasks+1 entries; col holds up to
  * cap_e entries; *e receives the edge count (TG_ENOMEM if it exceeds cap_e). */
 tg_status tg_graph_read_dag(tg_graph g, uint64_t* row_ptr, uint32_t* col, uint64_t cap_e, uint64_t* e);
+/* The edges the executor's counters follow, as an out-edge CSR (format as
+ * tg_graph_read_dag): the DAG itself, plus the anti-dependence edges of
+ * reused payload slots (tg_graph_set_retention), or the reduced DAG after
+ * tg_graph_reduce_edges. */
+tg_status tg_graph_read_exec_dag(tg_graph g, uint64_t* row_ptr, uint32_t* col, uint64_t cap_e, uint64_t* e);
 /* Dependence reduction (Section 5 names transitive reduction as an
  * optimisation of inferred dependences).  tg_reduce_dag: for a DAG given as
  * an out-edge CSR over n vertices whose ids are a topological order (every
@@ -305,6 +347,16 @@ tg_status tg_graph_exec_info(tg_graph g, uint32_t* workers, uint32_t* started);
 tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t nworkers, uint32_t window,
                               uint32_t schedule, uint64_t seed, uint64_t* order, uint64_t* executed, uint64_t* makespan,
                               uint64_t* bound);
+/* Host-only model of the ready-queue dispatch (TG_DISPATCH_QUEUE) over
+ * graphs[0..ngraphs): nworkers workers with the kernels' steps (claim by
+ * compare-and-swap on a shard's head, tickets reserved on its tail before the
+ * slots are written, one ready successor kept per completion, the finished
+ * count flushed by idle workers) interleaved in a seeded order at every
+ * access to shared state.  order (total #tasks entries) receives the
+ * execution order as (graph index << 32 | event); TG_ETIMEOUT if the model
+ * does not terminate. */
+tg_status tg_emulate_queue(const tg_graph* graphs, uint32_t ngraphs, uint32_t nworkers, uint32_t shards, uint32_t tile,
+                           uint64_t seed, uint64_t* order, uint64_t* executed);
 /* After a diagnostic launch (diag=1) of the graph on its own: per task (by
  * event) the pending in-edge counter, the number of times it ran, its worker
  * and its entry in that worker's list; optionally (wprog != NULL, nworkers =
@@ -342,7 +394,11 @@ enum {
   TG_PROBE_COPY_BW = 2,          /* bytes/s read + written by a streaming copy */
   TG_PROBE_ATOMIC_DISTINCT = 3,  /* device-scope u32 atomics/s on distinct addresses */
   TG_PROBE_ATOMIC_CONTENDED = 4, /* device-scope u32 atomics/s on one address */
-  TG_PROBE_LAUNCH_RATE = 5       /* empty kernel launches/s, back to back */
+  TG_PROBE_LAUNCH_RATE = 5,      /* empty kernel launches/s, back to back */
+  TG_PROBE_HANDOFF_NS = 6        /* ns of one dependent hop between wavefronts on two
+                                    XCDs: see the signal, load the 1 KB payload, store
+                                    one, drain the stores, signal with one atomic
+                                    (the per-level floor of a dependence chain) */
 };
 tg_status tg_probe(uint32_t kind, double* value);
 
@@ -380,10 +436,12 @@ tg_status tg_server_destroy(tg_server srv);
 /* ------------------------------------------------------- comparators */
 
 /* Plain comparators of the same graph: one kernel launch per task in creation
- * order on `stream` (mode 1), or replay of a captured hipGraph with one kernel
- * node per task and one dependency per edge (mode 2; the hipGraph is built on
- * the first call and cached).  Results are identical to tg_graph_execute. */
-enum { TG_CMP_PER_TASK = 1, TG_CMP_HIPGRAPH = 2 };
+ * order on `stream` (mode 1); replay of a hipGraph with one kernel node per
+ * task and one dependency per edge (mode 2); replay of the mode-1 launch
+ * sequence captured from a stream into a hipGraph (mode 3).  Each hipGraph is
+ * built and instantiated on the first call and cached until the graph's
+ * layout changes.  Results are identical to tg_graph_execute. */
+enum { TG_CMP_PER_TASK = 1, TG_CMP_HIPGRAPH = 2, TG_CMP_HIPGRAPH_CAPTURED = 3 };
 tg_status tg_graph_execute_comparator(tg_graph g, uint32_t mode, void* stream);
 
 #ifdef __cplusplus

@@ -13,6 +13,7 @@
 // any ready-window length.
 #include "taskgraph.h"
 #include "tg_internal.h"
+#include "tg_ledger.h"
 
 #include <algorithm>
 #include <atomic>
@@ -51,6 +52,20 @@ tg_status fail(tg_status s, const char* fmt, ...) {
   g_err = buf;
   return s;
 }
+
+}  // namespace
+
+tg_status tg_set_error(tg_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+namespace {
 
 #define HIPCHK(x)                                                                          \
   do {                                                                                     \
@@ -183,6 +198,7 @@ tg_status device_info(DevInfo& di) {
 struct Config {
   uint32_t mapping = 1, workers = 0, window = 64, wg_waves = 4, watchdog_ms = 5000, spin_limit = 0, diag = 0;
   uint32_t idle_sleep = 2, notify = 0, schedule = TG_SCHED_LEVEL, gang = 1;
+  uint32_t dispatch = TG_DISPATCH_LISTS, tile = 1, shards = 8;
 };
 
 Config resolve(const tg_exec_config* c) {
@@ -199,6 +215,9 @@ Config resolve(const tg_exec_config* c) {
     if (c->idle_sleep) r.idle_sleep = c->idle_sleep;
     if (c->schedule) r.schedule = c->schedule;
     if (c->gang) r.gang = c->gang;
+    if (c->dispatch) r.dispatch = c->dispatch;
+    if (c->tile) r.tile = c->tile;
+    if (c->shards) r.shards = c->shards;
   }
   if (r.mapping != TG_MAP_GANG) r.gang = 1;
   return r;
@@ -213,6 +232,13 @@ tg_status check_config(const Config& c) {
   if (c.idle_sleep < 1 || c.idle_sleep > 64) return fail(TG_EINVAL, "idle_sleep must be in [1, 64]");
   if (c.wg_waves < 1 || c.wg_waves > 16) return fail(TG_EINVAL, "wg_waves must be in [1, 16]");
   if (c.schedule < TG_SCHED_LIST || c.schedule > TG_SCHED_BALANCED) return fail(TG_EINVAL, "schedule must be 1..5");
+  if (c.dispatch != TG_DISPATCH_LISTS && c.dispatch != TG_DISPATCH_QUEUE) return fail(TG_EINVAL, "dispatch must be 1 or 2");
+  if (c.dispatch == TG_DISPATCH_QUEUE) {
+    if (c.mapping == TG_MAP_GANG) return fail(TG_EINVAL, "the ready queue serves wavefront and workgroup workers");
+    if (c.tile < 1 || c.tile > 64) return fail(TG_EINVAL, "tile must be in [1, 64]");
+    if (c.shards != 1 && c.shards != 2 && c.shards != 4 && c.shards != 8)
+      return fail(TG_EINVAL, "shards must be 1, 2, 4 or 8");
+  }
   return TG_OK;
 }
 
@@ -220,15 +246,47 @@ tg_status check_config(const Config& c) {
 
 // --------------------------------------------------------------- layout
 
+static void ledger_forget(const void* key);
+
 struct Layout {
   Config cfg;
   uint32_t nworkers = 0, grid_blocks = 0, npos = 0, last_started = 0;
   DevBuf rec, pred_addr, succ_pos, indeg, cnt, wbase, gtab, reqs, ctrl, execs, wprog, owner, bell, tstamp, wstamp, mbox;
+  DevBuf q, qctl, qfin, qsrc;  // ready-queue dispatch
   std::vector<std::vector<uint32_t>> pos_of;  // per graph: task id -> position
   std::vector<TaskRec> rec_host;               // host copy (rounds can be re-set)
   ExecParams params{};
   double plan_ms = 0, build_ms = 0;  // host time: schedule + records, whole layout incl. upload
+  // residency ledger: kernel variant, co-resident units this layout's launch
+  // occupies, the variant's calibrated capacity, device, completion event
+  int dev = 0;
+  uint64_t variant = 0, units = 0, capacity = 0;
+  hipEvent_t ev_done = nullptr;
+  Layout() = default;
+  Layout(const Layout&) = delete;
+  Layout& operator=(const Layout&) = delete;
+  ~Layout() {
+    ledger_forget(this);
+    if (ev_done) (void)hipEventDestroy(ev_done);
+  }
 };
+
+// Process-wide ledger of persistent launches in flight (see tg_ledger.h):
+// entries and their completion events, guarded by one lock that is held from
+// the decision to the recording of the new launch's completion event.
+static std::mutex g_ledger_mu;
+static std::vector<tg::Flight> g_flights;
+static std::vector<hipEvent_t> g_flight_ev;
+
+static void ledger_forget(const void* key) {
+  std::lock_guard<std::mutex> lk(g_ledger_mu);
+  for (size_t i = 0; i < g_flights.size(); ++i)
+    if (g_flights[i].key == key) {
+      g_flights.erase(g_flights.begin() + (ptrdiff_t)i);
+      g_flight_ev.erase(g_flight_ev.begin() + (ptrdiff_t)i);
+      return;
+    }
+}
 
 namespace {
 struct PlanCache;
@@ -255,6 +313,17 @@ struct tg_graph_s {
   bool reduced = false;
   std::vector<uint64_t> full_succ_ptr;
   std::vector<uint32_t> full_succ;
+  // explicit graphs with payload reuse (tg_graph_set_retention): succ holds
+  // the data edges plus the anti-dependence edges of reused payload slots,
+  // full_succ the data edges alone; topo is the level order the slots were
+  // assigned in (a topological order of both edge sets)
+  uint32_t retain = TG_KEEP_ALL;
+  bool anti = false;
+  uint32_t nslots = 0;               // payload slots on the device
+  std::vector<uint32_t> slot_of;     // slot of each task (empty: slot v for task v)
+  std::vector<uint32_t> slot_last;   // per slot: the task whose payload it holds at the end
+  std::vector<uint32_t> topo;
+  std::vector<uint32_t> xindeg;      // in-degree over the executed edges (counter reset values)
   std::vector<uint32_t> rw_base;  // implicit: per requirement, ordinal of its first written element
   DevBuf payload, data, digest;
   std::unique_ptr<Layout> solo;
@@ -275,9 +344,10 @@ struct tg_graph_s {
   static constexpr uint32_t kRing = 64;
   hipEvent_t rk0[kRing] = {}, rk1[kRing] = {};
   uint64_t launches = 0;
-  // comparator hipGraph
-  hipGraph_t hg = nullptr;
-  hipGraphExec_t hgx = nullptr;
+  // comparator hipGraphs: one kernel node per task with one dependency per
+  // edge (hg), and the per-task launch sequence captured from a stream (hgc)
+  hipGraph_t hg = nullptr, hgc = nullptr;
+  hipGraphExec_t hgx = nullptr, hgcx = nullptr;
   uint32_t N() const { return mode == TG_EXPLICIT ? (uint32_t)(pred_ptr.size() - 1) : (uint32_t)(req_ptr.size() - 1); }
 };
 
@@ -328,6 +398,8 @@ tg_status resident_workers(uint32_t mapping, uint32_t wg_waves, uint32_t* out) {
   int bpc = tg::exec_blocks_per_cu(mapping, wg_waves);
   if (bpc <= 0) return fail(TG_EDEVICE, "occupancy query failed");
   const uint32_t per_block = mapping == TG_MAP_WAVE ? 4u : 1u;
+  // the probe needs the whole device: let launches in flight finish first
+  HIPCHK(hipDeviceSynchronize());
   DevBuf ctrl;
   if ((s = ctrl.alloc(sizeof(tg::Ctrl))) != TG_OK) return s;
   uint32_t found = 0;
@@ -644,7 +716,7 @@ tg_status schedule_list(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw
   for (uint32_t gi = 0; gi < G; ++gi) {
     const tg_graph g = gs[gi];
     for (uint32_t v = 0; v < g->N(); ++v) {
-      pend[gbase[gi] + v] = (uint32_t)(g->dpred_ptr[v + 1] - g->dpred_ptr[v]);
+      pend[gbase[gi] + v] = g->xindeg[v];
       if (pend[gbase[gi] + v] == 0) push(gbase[gi] + v);
     }
   }
@@ -807,10 +879,12 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
         const uint64_t d0 = g->dpred_ptr[v], d1 = g->dpred_ptr[v + 1];
         r.npred = (uint32_t)(d1 - d0);
         if (expl) {
-          r.out = base + (uint64_t)v * wbytes;
+          const bool slots = !g->slot_of.empty();
+          r.out = base + (uint64_t)(slots ? g->slot_of[v] : v) * wbytes;
           r.pred_beg = (uint32_t)(pb + d0);
           for (uint64_t j = d0; j < d1; ++j) {
-            const uint64_t addr = base + (uint64_t)g->dpred[j] * wbytes;
+            const uint32_t p = g->dpred[j];
+            const uint64_t addr = base + (uint64_t)(slots ? g->slot_of[p] : p) * wbytes;
             if (j - d0 < tg::kInPred) r.pred[j - d0] = addr;
             H.pred_addr[pb + j] = addr;
           }
@@ -827,7 +901,7 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
           H.succ_pos[sb + j] = sp;
         }
         H.rec[pos[v]] = r;
-        H.indeg[pos[v]] = r.npred;
+        H.indeg[pos[v]] = g->xindeg[v];
       }
     }
   };
@@ -924,6 +998,17 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   L->npos = H.N;
   L->nworkers = H.nw;
   L->grid_blocks = cfg.mapping == TG_MAP_WAVE ? (H.nw + 3) / 4 : H.nw * cfg.gang;
+  {
+    DevInfo di;
+    if ((s = device_info(di)) != TG_OK) return s;
+    L->dev = di.dev;
+    L->variant = (cfg.mapping == TG_MAP_WAVE ? tg::flight_variant(TG_MAP_WAVE, 1, 1)
+                                             : tg::flight_variant(cfg.mapping, cfg.wg_waves, cfg.gang)) |
+                 ((uint64_t)cfg.dispatch << 60);
+    L->units = (uint64_t)H.nw * cfg.gang;  // wavefronts, or workgroups
+    L->capacity = cap32;
+    HIPCHK(hipEventCreateWithFlags(&L->ev_done, hipEventDisableTiming));
+  }
   L->pos_of = std::move(H.pos_of);
   const uint32_t N = H.N;
   if ((s = upload(L->rec, H.rec)) != TG_OK) return s;
@@ -967,6 +1052,28 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   P.window = cfg.window;
   P.spin_limit = cfg.spin_limit;
   P.watchdog_ticks = (uint64_t)cfg.watchdog_ms * 100000ull;
+  if (cfg.dispatch == TG_DISPATCH_QUEUE) {
+    // one ticket slot per task in each shard (every task is pushed at most
+    // once, into one shard), all empty; the sources are pushed at reset
+    std::vector<uint32_t> src;
+    for (uint32_t p = 0; p < N; ++p)
+      if (H.indeg[p] == 0) src.push_back(p);
+    if ((s = L->q.alloc((size_t)cfg.shards * N * 4)) != TG_OK) return s;
+    HIPCHK(hipMemset(L->q.p, 0xFF, (size_t)cfg.shards * N * 4));
+    if ((s = L->qctl.alloc((size_t)cfg.shards * tg::kQCtlStride * 8)) != TG_OK) return s;
+    HIPCHK(hipMemset(L->qctl.p, 0, (size_t)cfg.shards * tg::kQCtlStride * 8));
+    if ((s = L->qfin.alloc(256)) != TG_OK) return s;
+    HIPCHK(hipMemset(L->qfin.p, 0, 256));
+    if ((s = upload(L->qsrc, src)) != TG_OK) return s;
+    P.q = L->q.as<uint32_t>();
+    P.qctl = L->qctl.as<uint64_t>();
+    P.qfin = L->qfin.as<uint32_t>();
+    P.qsrc = L->qsrc.as<uint32_t>();
+    P.nsrc = (uint32_t)src.size();
+    P.qshards = cfg.shards;
+    P.qcap = N;
+    P.qtile = cfg.tile;
+  }
   if ((s = null_stream_fence()) != TG_OK) return s;
   L->plan_ms = plan_ms;
   L->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_build).count();
@@ -1051,6 +1158,161 @@ tg_status emulate_layout(const HostLayout& H, uint32_t window, uint64_t seed, ui
   }
   *executed = ex;
   return ex == N ? TG_OK : fail(TG_EINVAL, "executed %llu of %u tasks", (unsigned long long)ex, N);
+}
+
+// CPU model of the ready-queue dispatch (k_exec_wave_q): workers take one
+// step at a time in a seeded pseudo-random order, and every access to shared
+// state is a step of its own, so the model visits the interleavings the
+// kernels can produce -- a claim's read of (head, tail) and its
+// compare-and-swap, a push's reservation of tickets and the writes of the
+// slots, waiting for claimed slots that are still empty, the finished-count
+// flush and exit test.  It checks that every task runs exactly once, after
+// all its in-edges, and that every worker leaves.
+tg_status emulate_queue(const HostLayout& H, uint32_t nworkers, uint32_t shards, uint32_t tile, uint64_t seed,
+                        uint32_t* order, uint64_t* executed) {
+  const uint32_t N = H.N;
+  const uint32_t kNone = 0xFFFFFFFFu;
+  std::vector<uint32_t> cnt(H.indeg);
+  std::vector<std::vector<uint32_t>> slot(shards, std::vector<uint32_t>(N, kNone));
+  std::vector<uint32_t> head(shards, 0), tail(shards, 0);
+  uint32_t nsrc = 0;
+  for (uint32_t p = 0; p < N; ++p)
+    if (H.indeg[p] == 0) {
+      slot[nsrc % shards][nsrc / shards] = p;
+      nsrc++;
+    }
+  for (uint32_t s = 0; s < shards; ++s) tail[s] = (nsrc + shards - 1 - s) / shards;
+  uint64_t fin = 0, ex = 0;
+  std::vector<uint8_t> done(N, 0);
+  enum Phase { kLook, kCas, kWait, kPushWrite, kFlush };
+  struct W {
+    Phase ph = kLook;
+    uint32_t shard = 0, local = 0xFFFFFFFFu, probe = 0;
+    uint32_t seen_h = 0, seen_t = 0, claim_s = 0, claim_h = 0, claim_k = 0;
+    std::vector<uint32_t> tile;  // claimed positions not yet run
+    size_t tile_i = 0;
+    uint32_t ran = 0;
+    std::vector<uint32_t> pending;  // ready positions to write into reserved slots
+    uint32_t pbase = 0, ps = 0;
+    bool exited = false;
+  };
+  std::vector<W> ws(nworkers);
+  for (uint32_t w = 0; w < nworkers; ++w) ws[w].shard = (w / 4) % 8 % shards;
+  uint64_t rng = seed * 0x9E3779B97F4A7C15ull + 7;
+  auto next_rand = [&]() {
+    rng ^= rng << 13;
+    rng ^= rng >> 7;
+    rng ^= rng << 17;
+    return rng;
+  };
+  std::vector<uint32_t> live(nworkers);
+  for (uint32_t w = 0; w < nworkers; ++w) live[w] = w;
+  uint64_t steps = 0;
+  const uint64_t max_steps = 64ull * (N + 16) * (nworkers + 8) + 100000;
+  while (!live.empty()) {
+    if (++steps > max_steps) {
+      *executed = ex;
+      return fail(TG_ETIMEOUT, "queue model does not terminate after %llu of %u tasks", (unsigned long long)ex, N);
+    }
+    const size_t li = (size_t)(next_rand() % live.size());
+    W& x = ws[live[li]];
+    switch (x.ph) {
+      case kPushWrite: {  // write one reserved slot
+        slot[x.ps][x.pbase] = x.pending.back();
+        x.pending.pop_back();
+        x.pbase++;
+        if (x.pending.empty()) x.ph = kLook;
+        break;
+      }
+      case kWait: {  // the claimed slots, once written
+        bool all = true;
+        for (uint32_t i = 0; i < x.claim_k; ++i) all &= slot[x.claim_s][x.claim_h + i] != kNone;
+        if (!all) break;
+        x.tile.assign(slot[x.claim_s].begin() + x.claim_h, slot[x.claim_s].begin() + x.claim_h + x.claim_k);
+        x.tile_i = 0;
+        x.ph = kLook;
+        break;
+      }
+      case kCas: {
+        const uint32_t s = x.claim_s;
+        if (head[s] == x.seen_h) {
+          x.claim_k = std::min(tile, x.seen_t - x.seen_h);
+          x.claim_h = x.seen_h;
+          head[s] = x.seen_h + x.claim_k;
+          x.ph = kWait;
+        } else {
+          x.probe++;
+          x.ph = kLook;
+        }
+        break;
+      }
+      case kFlush: {  // report the tasks run, then test for the end
+        fin += x.ran;
+        x.ran = 0;
+        if (fin >= N) {
+          x.exited = true;
+          live[li] = live.back();
+          live.pop_back();
+        } else {
+          x.ph = kLook;
+          x.probe = 0;
+        }
+        break;
+      }
+      case kLook: {
+        uint32_t pos = kNone;
+        if (x.local != kNone) {
+          pos = x.local;
+          x.local = kNone;
+        } else if (x.tile_i < x.tile.size()) {
+          pos = x.tile[x.tile_i++];
+        }
+        if (pos != kNone) {  // run the task and signal its out-edges
+          if (done[pos] || cnt[pos] != 0) return fail(TG_EINVAL, "queue model: position %u run twice or early", pos);
+          done[pos] = 1;
+          if (order) order[ex] = pos;
+          ++ex;
+          x.ran++;
+          const TaskRec& r = H.rec[pos];
+          std::vector<uint32_t> ready;
+          for (uint32_t j = 0; j < r.nsucc; ++j) {
+            const uint32_t d = H.succ_pos[r.succ_beg + j];
+            if (cnt[d] == 0) return fail(TG_EINVAL, "queue model: counter underflow at %u", d);
+            if (--cnt[d] == 0) ready.push_back(d);
+          }
+          if (!ready.empty() && x.local == kNone) {
+            x.local = ready.front();
+            ready.erase(ready.begin());
+          }
+          if (!ready.empty()) {  // reserve the tickets now, write them in later steps
+            x.ps = x.shard;
+            x.pbase = tail[x.ps];
+            tail[x.ps] += (uint32_t)ready.size();
+            x.pending.assign(ready.rbegin(), ready.rend());
+            x.ph = kPushWrite;
+          }
+          break;
+        }
+        if (x.probe >= shards) {  // every shard looked empty
+          x.ph = kFlush;
+          break;
+        }
+        const uint32_t s = (x.shard + x.probe) % shards;
+        if (head[s] < tail[s]) {
+          x.claim_s = s;
+          x.seen_h = head[s];
+          x.seen_t = tail[s];
+          x.ph = kCas;
+        } else {
+          x.probe++;
+        }
+        break;
+      }
+    }
+  }
+  *executed = ex;
+  if (ex != N) return fail(TG_EINVAL, "queue model ran %llu of %u tasks", (unsigned long long)ex, N);
+  return TG_OK;
 }
 
 // Timed model of a layout: every worker runs the kernels' ready-window rule
@@ -1145,12 +1407,33 @@ void timed_makespan(const std::vector<tg_graph>& gs, const HostLayout& H, uint32
 
 bool same_layout(const Config& a, const Config& b) {
   return a.mapping == b.mapping && a.workers == b.workers && a.wg_waves == b.wg_waves && a.schedule == b.schedule &&
-         a.gang == b.gang;
+         a.gang == b.gang && a.dispatch == b.dispatch && (a.dispatch == TG_DISPATCH_LISTS || a.shards == b.shards);
 }
 
-// Launch reset + persistent executor for a layout.
+// Launch reset + persistent executor for a layout.  Under the ledger lock:
+// drop finished launches, make `st` wait for the in-flight launches this one
+// cannot overlap (tg_ledger.h), issue the kernels, record the completion
+// event and enter the launch.
 tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph>& gs, hipStream_t st,
                         hipEvent_t before_kernel = nullptr, hipEvent_t ring0 = nullptr, hipEvent_t ring1 = nullptr) {
+  std::lock_guard<std::mutex> ledger_lk(g_ledger_mu);
+  for (size_t i = 0; i < g_flights.size();) {
+    if (g_flights[i].key != &L && hipEventQuery(g_flight_ev[i]) == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    g_flights.erase(g_flights.begin() + (ptrdiff_t)i);
+    g_flight_ev.erase(g_flight_ev.begin() + (ptrdiff_t)i);
+  }
+  (void)hipGetLastError();  // a not-ready query is not an error of this launch
+  tg::Flight me;
+  me.key = &L;
+  me.dev = L.dev;
+  me.variant = L.variant;
+  me.workers = L.units;
+  me.capacity = L.capacity;
+  me.stream = (uintptr_t)st;
+  for (size_t i : tg::flights_to_follow(g_flights, me)) HIPCHK(hipStreamWaitEvent(st, g_flight_ev[i], 0));
   ExecParams P = L.params;
   P.window = cfg.window;
   P.spin_limit = cfg.spin_limit;
@@ -1158,6 +1441,7 @@ tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph
   P.idle_sleep = cfg.idle_sleep;
   P.notify = cfg.notify;
   P.watchdog_ticks = (uint64_t)cfg.watchdog_ms * 100000ull;
+  P.progress_ticks = P.watchdog_ticks / 16;
   P.execs = nullptr;
   P.wprog = nullptr;
   P.tstamp = nullptr;
@@ -1177,11 +1461,20 @@ tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph
     if (g->mode == TG_IMPLICIT) {
       HIPCHK(tg_launch_init_data(g->data.as<uint32_t>(), g->space, sm64_host(g->seed ^ (2ull << 32)), st));
     }
+  const bool queue = L.cfg.dispatch == TG_DISPATCH_QUEUE;
+  if (queue) P.qtile = cfg.tile;
   HIPCHK(tg::launch_reset(P, st));
+  if (queue) HIPCHK(tg::launch_queue_reset(P, st));
   if (before_kernel) HIPCHK(hipEventRecord(before_kernel, st));
   if (ring0) HIPCHK(hipEventRecord(ring0, st));
-  if (L.npos) HIPCHK(tg::launch_exec(P, cfg.mapping, cfg.wg_waves, L.grid_blocks, st));
+  if (L.npos) {
+    if (queue) HIPCHK(tg::launch_exec_queue(P, cfg.mapping, cfg.wg_waves, L.grid_blocks, st));
+    else HIPCHK(tg::launch_exec(P, cfg.mapping, cfg.wg_waves, L.grid_blocks, st));
+  }
   if (ring1) HIPCHK(hipEventRecord(ring1, st));
+  HIPCHK(hipEventRecord(L.ev_done, st));
+  g_flights.push_back(me);
+  g_flight_ev.push_back(L.ev_done);
   return TG_OK;
 }
 
@@ -1220,6 +1513,86 @@ tg_status graph_wait(tg_graph g) {
   return check_abort(g->last_layout);
 }
 
+// Buffer lifetimes (payload slots).  Algorithm 1 starts a vertex when the
+// counter of its pending in-edges reaches zero; the same counters can order
+// the reuse of payload memory.  Tasks are visited in dependence-level order
+// (ties by id).  When the last consumer of a task p has been visited, p's
+// slot becomes free for tasks of a later level than that consumer; under
+// TG_KEEP_NONE a task without consumers frees its slot at once.  A task
+// takes the oldest free slot it may use (else a new one), and for each task
+// whose reads of the slot's previous contents must finish first (the
+// previous owner's consumers, or the previous owner itself if it had none)
+// an anti-dependence edge to the new owner is added to the executed edges.
+// Every such edge goes from a lower to a higher level, so the levels, the
+// critical path and the schedules' level order are unchanged, and a payload
+// is overwritten only after every task that reads it has finished.
+void assign_slots(tg_graph g) {
+  const uint32_t N = g->N();
+  uint32_t maxlevel = 0;
+  for (uint32_t lv : g->level) maxlevel = std::max(maxlevel, lv);
+  std::vector<uint64_t> lstart((size_t)maxlevel + 2, 0);
+  for (uint32_t lv : g->level) lstart[lv + 1]++;
+  for (size_t i = 1; i < lstart.size(); ++i) lstart[i] += lstart[i - 1];
+  g->topo.assign(N, 0);
+  for (uint32_t v = 0; v < N; ++v) g->topo[lstart[g->level[v]]++] = v;
+  struct Freed {
+    uint32_t slot, min_level, by;
+    bool self;  // by itself (a task without consumers), else by's consumers
+  };
+  std::deque<Freed> freeq;
+  std::vector<uint32_t> remaining(N);
+  for (uint32_t v = 0; v < N; ++v) remaining[v] = (uint32_t)(g->succ_ptr[v + 1] - g->succ_ptr[v]);
+  g->slot_of.assign(N, 0);
+  g->slot_last.clear();
+  std::vector<std::pair<uint32_t, uint32_t>> extra;  // anti-dependence edges (from, to)
+  for (uint32_t v : g->topo) {
+    uint32_t slot;
+    if (!freeq.empty() && freeq.front().min_level <= g->level[v]) {
+      const Freed f = freeq.front();
+      freeq.pop_front();
+      slot = f.slot;
+      if (f.self) {
+        extra.emplace_back(f.by, v);
+      } else {
+        for (uint64_t j = g->succ_ptr[f.by]; j < g->succ_ptr[f.by + 1]; ++j) extra.emplace_back(g->succ[j], v);
+      }
+    } else {
+      slot = (uint32_t)g->slot_last.size();
+      g->slot_last.push_back(v);
+    }
+    g->slot_of[v] = slot;
+    g->slot_last[slot] = v;
+    for (uint64_t j = g->dpred_ptr[v]; j < g->dpred_ptr[v + 1]; ++j) {
+      const uint32_t p = g->dpred[j];
+      if (--remaining[p] == 0) freeq.push_back(Freed{g->slot_of[p], g->level[v] + 1, p, false});
+    }
+    if (g->retain == TG_KEEP_NONE && g->succ_ptr[v + 1] == g->succ_ptr[v])
+      freeq.push_back(Freed{slot, g->level[v] + 1, v, true});
+  }
+  g->nslots = (uint32_t)g->slot_last.size();
+  // executed edges: data edges plus the anti-dependence edges not already
+  // among them, rows ascending
+  std::vector<std::pair<uint32_t, uint32_t>> all;
+  all.reserve(g->succ.size() + extra.size());
+  for (uint32_t u = 0; u < N; ++u)
+    for (uint64_t j = g->succ_ptr[u]; j < g->succ_ptr[u + 1]; ++j) all.emplace_back(u, g->succ[j]);
+  all.insert(all.end(), extra.begin(), extra.end());
+  std::sort(all.begin(), all.end());
+  all.erase(std::unique(all.begin(), all.end()), all.end());
+  g->full_succ_ptr = g->succ_ptr;
+  g->full_succ = g->succ;
+  g->succ_ptr.assign((size_t)N + 1, 0);
+  g->succ.resize(all.size());
+  std::fill(g->xindeg.begin(), g->xindeg.end(), 0u);
+  for (size_t i = 0; i < all.size(); ++i) {
+    g->succ_ptr[all[i].first + 1]++;
+    g->succ[i] = all[i].second;
+    g->xindeg[all[i].second]++;
+  }
+  for (uint32_t u = 0; u < N; ++u) g->succ_ptr[u + 1] += g->succ_ptr[u];
+  g->anti = true;  // the executed edges are kept apart from the data edges
+}
+
 tg_status finalize_explicit(tg_graph g) {
   const uint32_t N = g->N();
   // distinct predecessor sets
@@ -1251,6 +1624,10 @@ tg_status finalize_explicit(tg_graph g) {
     for (uint64_t j = g->dpred_ptr[v]; j < g->dpred_ptr[v + 1]; ++j) lv = std::max(lv, g->level[g->dpred[j]] + 1);
     g->level[v] = lv;
   }
+  g->xindeg.resize(N);
+  for (uint32_t v = 0; v < N; ++v) g->xindeg[v] = (uint32_t)(g->dpred_ptr[v + 1] - g->dpred_ptr[v]);
+  g->nslots = N;
+  if (g->retain != TG_KEEP_ALL) assign_slots(g);
   return TG_OK;
 }
 
@@ -1262,7 +1639,7 @@ tg_status ensure_device(tg_graph g) {
   g->released = false;
   if ((g->mode == TG_EXPLICIT && !g->payload.p) || (g->mode == TG_IMPLICIT && !g->data.p) || !g->digest.p) g->dev_gen++;
   if (g->mode == TG_EXPLICIT && !g->payload.p) {
-    if ((s = g->payload.alloc((size_t)N * g->n * 4)) != TG_OK) return s;
+    if ((s = g->payload.alloc((size_t)g->nslots * g->n * 4)) != TG_OK) return s;
   }
   if (g->mode == TG_IMPLICIT && !g->data.p) {
     if ((s = g->data.alloc((size_t)g->space * 4)) != TG_OK) return s;
@@ -1276,6 +1653,21 @@ tg_status ensure_device(tg_graph g) {
 
 // Timing events of a graph's own launches, created at its first one (graphs
 // that only ever run inside batches or the server never need them).
+// The comparator's hipGraph copies the solo layout's device addresses (task
+// records, graph table, positions) into its kernel nodes, so it must never
+// outlive that layout: every place that replaces or releases the solo
+// layout goes through here, after the graph's executions have finished.
+void drop_solo(tg_graph g) {
+  if (g->hgx) (void)hipGraphExecDestroy(g->hgx);
+  if (g->hg) (void)hipGraphDestroy(g->hg);
+  if (g->hgcx) (void)hipGraphExecDestroy(g->hgcx);
+  if (g->hgc) (void)hipGraphDestroy(g->hgc);
+  g->hgx = g->hgcx = nullptr;
+  g->hg = g->hgc = nullptr;
+  g->solo.reset();
+  g->last_layout = nullptr;
+}
+
 tg_status ensure_events(tg_graph g) {
   if (!g->ev0) HIPCHK(hipEventCreate(&g->ev0));
   if (!g->ev1) HIPCHK(hipEventCreate(&g->ev1));
@@ -1306,9 +1698,8 @@ static tg_status tg_finalize_implicit(tg_graph g) {
     if (run > 0xFFFFFFFFull) return fail(TG_EINVAL, "task %u writes more than 2^32 elements", k);
   }
   InferResult res;
-  std::string err;
-  hipError_t e = tg_infer_dag_raw(N, g->req_ptr.data(), g->reqs.data(), g->reqs.size(), g->space, res, err);
-  if (e != hipSuccess) return fail(TG_EDEVICE, "dependence inference failed at %s: %s", err.c_str(), hipGetErrorString(e));
+  tg_status is = tg_infer_dag_host(N, g->req_ptr.data(), g->reqs.data(), g->reqs.size(), g->space, res);
+  if (is != TG_OK) return is;
   g->infer_ms = res.ms;
   g->succ_ptr = std::move(res.row_ptr);
   g->succ = std::move(res.col);
@@ -1328,6 +1719,8 @@ static tg_status tg_finalize_implicit(tg_graph g) {
     for (uint64_t x = g->dpred_ptr[k]; x < g->dpred_ptr[k + 1]; ++x) lv = std::max(lv, g->level[g->dpred[x]] + 1);
     g->level[k] = lv;
   }
+  g->xindeg.resize(N);
+  for (uint32_t k = 0; k < N; ++k) g->xindeg[k] = (uint32_t)(g->dpred_ptr[k + 1] - g->dpred_ptr[k]);
   return TG_OK;
 }
 
@@ -1478,7 +1871,7 @@ tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfgp, void* stream)
   if (s != TG_OK) return s;
   if (!g->solo || !same_layout(g->solo->cfg, cfg)) {
     if (g->inflight && (s = graph_wait(g)) != TG_OK) return s;
-    g->solo.reset();
+    drop_solo(g);
     std::vector<tg_graph> gs{g};
     if (!g->plans) g->plans = std::make_shared<PlanCache>();
     if ((s = build_layout(gs, cfg, g->solo, g->plans.get())) != TG_OK) return s;
@@ -1551,9 +1944,12 @@ tg_status tg_graph_read_payload(tg_graph g, tg_event v, uint32_t* host_out, uint
   if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
   if (v >= g->N() || n != g->n) return fail(TG_EINVAL, "bad event or payload size");
   if (!g->payload.p) return fail(TG_ESTATE, "graph was never executed");
+  const uint32_t slot = g->slot_of.empty() ? v : g->slot_of[v];
+  if (!g->slot_of.empty() && g->slot_last[slot] != v)
+    return fail(TG_ESTATE, "the payload of task %u was released: its slot holds task %u's", v, g->slot_last[slot]);
   tg_status s = graph_wait(g);
   if (s != TG_OK) return s;
-  HIPCHK(hipMemcpy(host_out, g->payload.as<uint32_t>() + (size_t)v * g->n, (size_t)n * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(host_out, g->payload.as<uint32_t>() + (size_t)slot * g->n, (size_t)n * 4, hipMemcpyDeviceToHost));
   return TG_OK;
 }
 
@@ -1584,14 +1980,49 @@ tg_status tg_graph_checksum(tg_graph g, uint64_t* out) {
 tg_status tg_graph_read_dag(tg_graph g, uint64_t* row_ptr, uint32_t* col, uint64_t cap_e, uint64_t* e) {
   if (!g || !row_ptr || !e) return fail(TG_EINVAL, "NULL argument");
   if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
-  const std::vector<uint64_t>& rp = g->reduced ? g->full_succ_ptr : g->succ_ptr;
-  const std::vector<uint32_t>& cl = g->reduced ? g->full_succ : g->succ;
+  const bool apart = g->reduced || g->anti;
+  const std::vector<uint64_t>& rp = apart ? g->full_succ_ptr : g->succ_ptr;
+  const std::vector<uint32_t>& cl = apart ? g->full_succ : g->succ;
   *e = cl.size();
   memcpy(row_ptr, rp.data(), rp.size() * sizeof(uint64_t));
   if (cl.size() > cap_e) return fail(TG_ENOMEM, "col capacity %llu < %zu edges", (unsigned long long)cap_e, cl.size());
   if (!cl.empty()) {
     if (!col) return fail(TG_EINVAL, "col is NULL");
     memcpy(col, cl.data(), cl.size() * 4);
+  }
+  return TG_OK;
+}
+
+tg_status tg_graph_set_retention(tg_graph g, uint32_t mode) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (g->mode != TG_EXPLICIT) return fail(TG_EINVAL, "payload retention applies to explicit graphs");
+  if (mode != TG_KEEP_ALL && mode != TG_KEEP_SINKS && mode != TG_KEEP_NONE)
+    return fail(TG_EINVAL, "unknown retention mode %u", mode);
+  if (g->finalized) return fail(TG_EBUSY, "set the retention before tg_graph_finalize");
+  g->retain = mode;
+  return TG_OK;
+}
+
+tg_status tg_graph_payload_slots(tg_graph g, uint32_t* slot_of, uint64_t* nslots, uint64_t* bytes) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  if (g->mode != TG_EXPLICIT) return fail(TG_EINVAL, "payloads exist in explicit mode only");
+  if (slot_of)
+    for (uint32_t v = 0; v < g->N(); ++v) slot_of[v] = g->slot_of.empty() ? v : g->slot_of[v];
+  if (nslots) *nslots = g->nslots;
+  if (bytes) *bytes = (uint64_t)g->nslots * g->n * 4ull;
+  return TG_OK;
+}
+
+tg_status tg_graph_read_exec_dag(tg_graph g, uint64_t* row_ptr, uint32_t* col, uint64_t cap_e, uint64_t* e) {
+  if (!g || !row_ptr || !e) return fail(TG_EINVAL, "NULL argument");
+  if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  *e = g->succ.size();
+  memcpy(row_ptr, g->succ_ptr.data(), g->succ_ptr.size() * sizeof(uint64_t));
+  if (g->succ.size() > cap_e) return fail(TG_ENOMEM, "col capacity %llu < %zu edges", (unsigned long long)cap_e, g->succ.size());
+  if (!g->succ.empty()) {
+    if (!col) return fail(TG_EINVAL, "col is NULL");
+    memcpy(col, g->succ.data(), g->succ.size() * 4);
   }
   return TG_OK;
 }
@@ -1629,10 +2060,10 @@ tg_status tg_graph_reduce_edges(tg_graph g, uint64_t* removed) {
   }
   g->dpred_ptr.swap(pp);
   g->dpred.swap(pr);
+  for (uint32_t k = 0; k < N; ++k) g->xindeg[k] = (uint32_t)(g->dpred_ptr[k + 1] - g->dpred_ptr[k]);
   g->reduced = true;
   // layouts and schedules were built on the full edge set
-  g->solo.reset();
-  g->last_layout = nullptr;
+  drop_solo(g);
   g->plans.reset();
   g->has_tuned = false;
   if (removed) *removed = g->full_succ.size() - g->succ.size();
@@ -1816,6 +2247,19 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
     }
   }
   cand.push_back(mk(TG_MAP_WAVE, rw, 0, 1));
+  // ready-queue dispatch
+  for (uint32_t tile : {1u, 4u}) {
+    for (uint32_t w : {rw, rw / 2}) {
+      tg_exec_config c = mk(TG_MAP_WAVE, w, 0, 0);
+      c.dispatch = TG_DISPATCH_QUEUE;
+      c.tile = tile;
+      cand.push_back(c);
+    }
+    tg_exec_config c = mk(TG_MAP_WORKGROUP, rg4, 4, 0);
+    c.dispatch = TG_DISPATCH_QUEUE;
+    c.tile = tile;
+    cand.push_back(c);
+  }
   double best_t = 1e300;
   tg_exec_config best_c = cand[0];
   for (const auto& c : cand) {
@@ -1841,8 +2285,7 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
 tg_status tg_graph_destroy(tg_graph g) {
   if (!g) return TG_OK;
   (void)graph_wait(g);
-  if (g->hgx) (void)hipGraphExecDestroy(g->hgx);
-  if (g->hg) (void)hipGraphDestroy(g->hg);
+  drop_solo(g);
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
   if (g->evk) (void)hipEventDestroy(g->evk);
@@ -1967,6 +2410,9 @@ tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks, double
     cfg->idle_sleep = c.idle_sleep;
     cfg->schedule = c.schedule;
     cfg->gang = c.mapping == TG_MAP_GANG ? c.gang : 0;
+    cfg->dispatch = c.dispatch;
+    cfg->tile = c.dispatch == TG_DISPATCH_QUEUE ? c.tile : 0;
+    cfg->shards = c.dispatch == TG_DISPATCH_QUEUE ? c.shards : 0;
   }
   if (tasks) *tasks = b->lay->npos;
   return TG_OK;
@@ -2008,6 +2454,19 @@ tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, dou
     }
   }
   cand.push_back(mk(TG_MAP_WAVE, rw, 0, 1));
+  // ready-queue dispatch
+  for (uint32_t tile : {1u, 4u}) {
+    for (uint32_t w : {rw, rw / 2}) {
+      Config c = mk(TG_MAP_WAVE, w, 0, 0);
+      c.dispatch = TG_DISPATCH_QUEUE;
+      c.tile = tile;
+      cand.push_back(c);
+    }
+    Config c = mk(TG_MAP_WORKGROUP, rg4, 4, 0);
+    c.dispatch = TG_DISPATCH_QUEUE;
+    c.tile = tile;
+    cand.push_back(c);
+  }
   double best_t = 1e300;
   Config best_c = cand[0];
   for (const auto& c : cand) {
@@ -2137,6 +2596,28 @@ tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t
   return s;
 }
 
+tg_status tg_emulate_queue(const tg_graph* graphs, uint32_t ngraphs, uint32_t nworkers, uint32_t shards, uint32_t tile,
+                           uint64_t seed, uint64_t* order, uint64_t* executed) {
+  if (!graphs || !ngraphs || !order || !executed) return fail(TG_EINVAL, "NULL argument");
+  if (nworkers == 0 || tile < 1 || tile > 64 || (shards != 1 && shards != 2 && shards != 4 && shards != 8))
+    return fail(TG_EINVAL, "nworkers >= 1, tile in [1,64], shards 1, 2, 4 or 8");
+  std::vector<tg_graph> gs(graphs, graphs + ngraphs);
+  for (auto g : gs) {
+    if (!g) return fail(TG_EINVAL, "NULL graph");
+    if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  }
+  HostLayout H;
+  tg_status s = plan_layout(gs, 1, TG_SCHED_LEVEL, H);
+  if (s != TG_OK) return s;
+  std::vector<uint32_t> ord(H.N);
+  s = emulate_queue(H, nworkers, shards, tile, seed, ord.data(), executed);
+  std::vector<uint64_t> key_of(H.N);
+  for (uint32_t gi = 0; gi < gs.size(); ++gi)
+    for (uint32_t v = 0; v < gs[gi]->N(); ++v) key_of[H.pos_of[gi][v]] = ((uint64_t)gi << 32) | v;
+  for (uint64_t i = 0; i < *executed; ++i) order[i] = key_of[ord[i]];
+  return s;
+}
+
 tg_status tg_graph_exec_info(tg_graph g, uint32_t* workers, uint32_t* started) {
   if (!g || !workers || !started) return fail(TG_EINVAL, "NULL argument");
   if (!g->solo) return fail(TG_ESTATE, "graph was never executed");
@@ -2149,7 +2630,8 @@ tg_status tg_graph_execute_comparator(tg_graph g, uint32_t mode, void* stream) {
   if (!g) return fail(TG_EINVAL, "graph is NULL");
   if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
   if (g->inflight) return fail(TG_EBUSY, "previous execution not waited for");
-  if (mode != TG_CMP_PER_TASK && mode != TG_CMP_HIPGRAPH) return fail(TG_EINVAL, "unknown comparator %u", mode);
+  if (mode != TG_CMP_PER_TASK && mode != TG_CMP_HIPGRAPH && mode != TG_CMP_HIPGRAPH_CAPTURED)
+    return fail(TG_EINVAL, "unknown comparator %u", mode);
   tg_status s;
   if (!g->solo) {
     std::vector<tg_graph> gs{g};
@@ -2164,14 +2646,47 @@ tg_status tg_graph_execute_comparator(tg_graph g, uint32_t mode, void* stream) {
   if (g->mode == TG_IMPLICIT) {
     HIPCHK(tg_launch_init_data(g->data.as<uint32_t>(), g->space, sm64_host(g->seed ^ (2ull << 32)), st));
   }
+  // creation order is topological for the data edges; with anti-dependence
+  // edges the level order the slots were assigned in is used
+  auto task_at = [&](uint32_t i) { return g->anti ? g->topo[i] : i; };
   if (mode == TG_CMP_PER_TASK) {
-    for (uint32_t v = 0; v < N; ++v) HIPCHK(tg::launch_one_task(P, L.pos_of[0][v], st));
+    for (uint32_t i = 0; i < N; ++i) HIPCHK(tg::launch_one_task(P, L.pos_of[0][task_at(i)], st));
+  } else if (mode == TG_CMP_HIPGRAPH_CAPTURED) {
+    if (!g->hgcx) {
+      // the per-task launch sequence, captured once from a private stream
+      hipStream_t cs = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      for (uint32_t i = 0; i < N && ce == hipSuccess; ++i) ce = tg::launch_one_task(P, L.pos_of[0][task_at(i)], cs);
+      hipGraph_t cg = nullptr;
+      const hipError_t ee = hipStreamEndCapture(cs, &cg);
+      (void)hipStreamDestroy(cs);
+      if (ce != hipSuccess || ee != hipSuccess) {
+        if (cg) (void)hipGraphDestroy(cg);
+        return fail(TG_EDEVICE, "stream capture of the per-task launches: %s",
+                    hipGetErrorString(ce != hipSuccess ? ce : ee));
+      }
+      g->hgc = cg;
+      HIPCHK(hipGraphInstantiate(&g->hgcx, g->hgc, nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(g->hgcx, st));
   } else {
     if (!g->hgx) {
       HIPCHK(hipGraphCreate(&g->hg, 0));
       std::vector<hipGraphNode_t> node(N);
       std::vector<hipGraphNode_t> deps;
-      for (uint32_t v = 0; v < N; ++v) {
+      // predecessors over the executed edges
+      std::vector<uint64_t> xp(N + 1, 0);
+      for (uint32_t x : g->succ) xp[x + 1]++;
+      for (uint32_t k = 0; k < N; ++k) xp[k + 1] += xp[k];
+      std::vector<uint32_t> xpr(g->succ.size());
+      {
+        std::vector<uint64_t> fill(xp.begin(), xp.end() - 1);
+        for (uint32_t j = 0; j < N; ++j)
+          for (uint64_t a = g->succ_ptr[j]; a < g->succ_ptr[j + 1]; ++a) xpr[fill[g->succ[a]]++] = j;
+      }
+      for (uint32_t i = 0; i < N; ++i) {
+        const uint32_t v = task_at(i);
         uint32_t pos = L.pos_of[0][v];
         void* args[2] = {(void*)&P, (void*)&pos};
         hipKernelNodeParams kp;
@@ -2183,7 +2698,7 @@ tg_status tg_graph_execute_comparator(tg_graph g, uint32_t mode, void* stream) {
         kp.kernelParams = args;
         kp.extra = nullptr;
         deps.clear();
-        for (uint64_t j = g->dpred_ptr[v]; j < g->dpred_ptr[v + 1]; ++j) deps.push_back(node[g->dpred[j]]);
+        for (uint64_t j = xp[v]; j < xp[v + 1]; ++j) deps.push_back(node[xpr[j]]);
         HIPCHK(hipGraphAddKernelNode(&node[v], g->hg, deps.empty() ? nullptr : deps.data(), deps.size(), &kp));
       }
       HIPCHK(hipGraphInstantiate(&g->hgx, g->hg, nullptr, nullptr, 0));
@@ -2260,7 +2775,7 @@ uint64_t now_ns() {
 uint64_t graph_device_bytes(tg_graph g) {
   const uint64_t N = g->N(), E = g->succ.size();
   uint64_t b = N * 4;  // digests
-  b += g->mode == TG_EXPLICIT ? N * g->n * 4ull : g->space * 4ull;
+  b += g->mode == TG_EXPLICIT ? (uint64_t)g->nslots * g->n * 4ull : g->space * 4ull;
   b += N * (sizeof(TaskRec) + 4 + 4 + 4 + 4) + E * (8 + 4);
   return b + 4096;
 }
@@ -2272,8 +2787,7 @@ void release_graph_device(tg_graph g) {
   g->payload.release();
   g->data.release();
   g->digest.release();
-  g->solo.reset();
-  g->last_layout = nullptr;
+  drop_solo(g);
   g->inflight = false;
   g->released = true;
 }

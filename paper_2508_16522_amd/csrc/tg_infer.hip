@@ -51,8 +51,7 @@ __global__ void k_bucket_count(const IvDev* iv, uint32_t M, uint32_t shift, uint
   for (uint64_t b = x.lo >> shift; b <= (x.hi - 1) >> shift; ++b) atomicAdd(bcnt + b, 1u);
 }
 
-// bent holds nent entries (counted on the host with the same rule as
-// k_bucket_count; the host checks the two totals agree).
+// bent holds nent entries (the total of the scanned bucket counts).
 __global__ void k_bucket_fill(const IvDev* iv, uint32_t M, uint32_t shift, const uint64_t* bptr, uint32_t* bfill,
                               uint32_t* bent, uint64_t nent) {
   const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -117,6 +116,58 @@ __global__ __launch_bounds__(256) void k_rows(const IvDev* iv, const uint64_t* r
     }
   }
   if (!FILL && lane == 0) rowcnt[j] = count;
+}
+
+// Interval table and input checks, one thread per task: task k's
+// requirements rq[req_ptr[k] .. req_ptr[k+1]) become IvDev entries tagged
+// with k.  summary[0] += total length of the non-empty intervals,
+// summary[1] += their number (one atomic per wavefront), summary[2] |=
+// error bits: 1 = row pointers decrease or pass the interval count, 2 = an
+// interval with lo > hi or beyond the index space, 4 = an unknown privilege,
+// 8 = a read-write interval overlapping another interval of its own task.
+__global__ __launch_bounds__(256) void k_make_iv(const tg_region_req* rq, const uint64_t* req_ptr, uint32_t N,
+                                                 uint64_t M, uint64_t space, IvDev* iv,
+                                                 unsigned long long* summary) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long len = 0, cnt = 0;
+  uint32_t err = 0;
+  if (k < N) {
+    const uint64_t b = req_ptr[k], e = req_ptr[k + 1];
+    if (e < b || e > M) {
+      err |= 1u;
+    } else {
+      for (uint64_t a = b; a < e; ++a) {
+        const tg_region_req q = rq[a];
+        IvDev x;
+        x.lo = q.lo;
+        x.hi = q.hi;
+        x.task = k;
+        x.priv = q.priv;
+        iv[a] = x;
+        if (q.lo > q.hi || q.hi > space) err |= 2u;
+        if (q.priv != TG_RO && q.priv != TG_RW) err |= 4u;
+        if (q.hi > q.lo) {
+          len += q.hi - q.lo;
+          ++cnt;
+        }
+        for (uint64_t a2 = b; a2 < e; ++a2) {
+          if (a2 == a) continue;
+          const tg_region_req r = rq[a2];
+          if ((q.priv == TG_RW || r.priv == TG_RW) && q.lo < q.hi && r.lo < r.hi && q.lo < r.hi && r.lo < q.hi)
+            err |= 8u;
+        }
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    len += __shfl_xor(len, o, 64);
+    cnt += __shfl_xor(cnt, o, 64);
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    atomicAdd(summary + 0, len);
+    atomicAdd(summary + 1, cnt);
+  }
+  if (err) atomicOr((unsigned int*)(summary + 2), err);
 }
 
 // ---------------------------------------------------------------- scan
@@ -184,57 +235,86 @@ __global__ void k_scan_total(uint64_t* out, uint64_t n, const uint32_t* in) {
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = n ? out[n - 1] + in[n - 1] : 0;
 }
 
-// In-place exclusive scan of u64 (used recursively for block sums).
-static hipError_t scan_u64_inplace(uint64_t* data, uint64_t n, std::vector<void*>& tmp, hipStream_t st) {
-  if (n <= 1) {
-    if (n == 1) return hipMemsetAsync(data, 0, 8, st);
-    return hipSuccess;
+// Device memory of one inference: allocated with hipMalloc (freed when the
+// workspace goes away), or carved in order from a fixed region (the
+// allocation-free entry point's scratch array), in which case a request
+// that does not fit fails and names the array.
+struct Workspace {
+  uint8_t* base = nullptr;  // fixed region; null: allocate
+  size_t cap = 0, used = 0;
+  std::vector<void*> owned;
+  const char* missing = nullptr;  // array that did not fit the fixed region
+  Workspace() = default;
+  Workspace(const Workspace&) = delete;
+  Workspace& operator=(const Workspace&) = delete;
+  ~Workspace() {
+    for (void* p : owned) (void)hipFree(p);
   }
+  hipError_t get(size_t bytes, const char* name, void** out) {
+    bytes = bytes ? (bytes + 255) & ~(size_t)255 : 256;
+    if (base) {
+      if (bytes > cap - used) {
+        missing = name;
+        return hipErrorOutOfMemory;
+      }
+      *out = base + used;
+      used += bytes;
+      return hipSuccess;
+    }
+    const hipError_t e = hipMalloc(out, bytes);
+    if (e == hipSuccess) owned.push_back(*out);
+    return e;
+  }
+};
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// Clears device words with a kernel (callers may record the work into a HIP
+// graph, where memset nodes are avoided).
+static hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// In-place exclusive scan of u64 (used recursively for block sums).
+static hipError_t scan_u64_inplace(uint64_t* data, uint64_t n, Workspace& ws, hipStream_t st) {
+  if (n <= 1) return n == 1 ? fill_u32((uint32_t*)data, 2, 0, st) : hipSuccess;
   const uint64_t nb = (n + 1023) / 1024;
   void* bs = nullptr;
-  hipError_t e = hipMalloc(&bs, nb * 8);
+  hipError_t e = ws.get(nb * 8, "scan partial sums", &bs);
   if (e != hipSuccess) return e;
-  tmp.push_back(bs);
   hipLaunchKernelGGL(k_scan_u64_block, dim3((uint32_t)nb), dim3(256), 0, st, data, n, (uint64_t*)bs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (nb > 1) {
-    if ((e = scan_u64_inplace((uint64_t*)bs, nb, tmp, st)) != hipSuccess) return e;
+    if ((e = scan_u64_inplace((uint64_t*)bs, nb, ws, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, data, n, (const uint64_t*)bs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-// out[0..n] = exclusive scan of in[0..n) with out[n] = total.
-static hipError_t scan_counts(const uint32_t* in, uint64_t n, uint64_t* out, hipStream_t st) {
-  std::vector<void*> tmp;
-  hipError_t e = hipSuccess;
-  if (n == 0) {
-    e = hipMemsetAsync(out, 0, 8, st);
-  } else {
-    const uint64_t nb = (n + 1023) / 1024;
-    void* bs = nullptr;
-    e = hipMalloc(&bs, nb * 8);
-    if (e == hipSuccess) {
-      tmp.push_back(bs);
-      hipLaunchKernelGGL(k_scan_block, dim3((uint32_t)nb), dim3(256), 0, st, in, n, out, (uint64_t*)bs);
-      e = hipGetLastError();
-      if (e == hipSuccess && nb > 1) {
-        e = scan_u64_inplace((uint64_t*)bs, nb, tmp, st);
-        if (e == hipSuccess) {
-          hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, out, n, (const uint64_t*)bs);
-          e = hipGetLastError();
-        }
-      }
-      if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, out, n, in);
-        e = hipGetLastError();
-      }
-    }
+// out[0..n] = exclusive scan of in[0..n) with out[n] = total (stream-ordered).
+static hipError_t scan_counts(const uint32_t* in, uint64_t n, uint64_t* out, Workspace& ws, hipStream_t st) {
+  if (n == 0) return fill_u32((uint32_t*)out, 2, 0, st);
+  const uint64_t nb = (n + 1023) / 1024;
+  void* bs = nullptr;
+  hipError_t e = ws.get(nb * 8, "scan partial sums", &bs);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_block, dim3((uint32_t)nb), dim3(256), 0, st, in, n, out, (uint64_t*)bs);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (nb > 1) {
+    if ((e = scan_u64_inplace((uint64_t*)bs, nb, ws, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, out, n, (const uint64_t*)bs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipError_t e2 = hipStreamSynchronize(st);
-  for (void* p : tmp) (void)hipFree(p);
-  return e != hipSuccess ? e : e2;
+  hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, st, out, n, in);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------- row sort
@@ -346,136 +426,181 @@ hipError_t tg_launch_init_data(uint32_t* A, uint64_t space, uint64_t key2, hipSt
 
 // ------------------------------------------------------------ host driver
 
-// Infers the conflict DAG of the n_reqs intervals of N tasks.
-hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr_p, const void* reqs_p, uint64_t n_reqs, uint64_t space,
-                            InferResult& res, std::string& err) {
-  using namespace tg;
-  const tg_region_req* reqs = (const tg_region_req*)reqs_p;
-  const std::vector<uint64_t> req_ptr(req_ptr_p, req_ptr_p + (size_t)N + 1);
-  const uint64_t M = n_reqs;
-  res.row_ptr.assign((size_t)N + 1, 0);
-  res.col.clear();
-  if (N == 0) return hipSuccess;
-  // bucket width: the power of two nearest the mean non-empty interval length
-  long double tot = 0;
-  uint64_t nonempty = 0;
-  for (uint64_t a = 0; a < M; ++a)
-    if (reqs[a].hi > reqs[a].lo) {
-      tot += (long double)(reqs[a].hi - reqs[a].lo);
-      nonempty++;
-    }
+namespace {
+
+using tg::IvDev;
+using tg::Workspace;
+
+// Bucket width 2^shift: the power of two nearest the mean non-empty interval
+// length, widened until the index space needs at most max_buckets buckets.
+uint32_t choose_shift(unsigned long long total_len, unsigned long long nonempty, uint64_t space,
+                      uint64_t max_buckets) {
   uint32_t shift = 0;
   if (nonempty) {
-    const long double mean = tot / nonempty;
+    const long double mean = (long double)total_len / (long double)nonempty;
     while (shift < 40 && (long double)(1ull << (shift + 1)) <= mean * 1.41421356L) shift++;
   }
-  while (((space + (1ull << shift) - 1) >> shift) > (1ull << 26)) shift++;
-  const uint64_t nbuckets = (space + (1ull << shift) - 1) >> shift;
-  std::vector<IvDev> iv(M ? M : 1);
-  uint64_t nent = 0;  // bucket entries: one per (non-empty interval, bucket it touches)
-  for (uint32_t k = 0; k < N; ++k)
-    for (uint64_t a = req_ptr[k]; a < req_ptr[k + 1]; ++a) {
-      iv[a].lo = reqs[a].lo;
-      iv[a].hi = reqs[a].hi;
-      iv[a].priv = reqs[a].priv;
-      iv[a].task = k;
-      if (reqs[a].hi > reqs[a].lo) nent += ((reqs[a].hi - 1) >> shift) - (reqs[a].lo >> shift) + 1;
-    }
-  // The edge count is read back through one pinned word, allocated once per
-  // process (outside the timed region) and shared under a lock.
+  while (((space + (1ull << shift) - 1) >> shift) > max_buckets) shift++;
+  return shift;
+}
+
+// Copies `bytes` of device memory to host memory on `st` and waits: through
+// the pinned staging word when one is given, else straight into `host`.
+hipError_t read_back(void* host, const void* dev, size_t bytes, uint64_t* pinned, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(pinned ? (void*)pinned : host, dev, bytes, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && pinned) memcpy(host, pinned, bytes);
+  return e;
+}
+
+// Inference proper, on device inputs, all work ordered on `st`:
+//   rq[M], req_ptr[N+1] : the requirements (device);
+//   row[N+1]            : receives the out-edge row pointers (device);
+//   *col                : receives the successors: when alloc_col is set a
+//                         buffer of the exact size is taken from the
+//                         workspace, else *col (capacity col_cap) is used
+//                         and a larger edge count fails with TG_ENOMEM;
+//   *E                  : the edge count (set also on TG_ENOMEM).
+// Returns when the DAG is complete on the device.
+tg_status infer_core(Workspace& ws, uint32_t N, uint64_t M, uint64_t space, const tg_region_req* rq,
+                     const uint64_t* req_ptr, uint64_t max_buckets, hipStream_t st, uint64_t* pinned,
+                     uint64_t* row, uint32_t** col, bool alloc_col, uint64_t col_cap, uint64_t* E) {
+  hipError_t e;
+#define ICHK(x, what)                                                                                   \
+  do {                                                                                                  \
+    e = (x);                                                                                            \
+    if (e != hipSuccess) {                                                                              \
+      if (ws.missing) return tg_set_error(TG_ENOMEM, "dependence inference: %s do not fit the scratch array", ws.missing); \
+      return tg_set_error(TG_EDEVICE, "dependence inference (%s): %s", what, hipGetErrorString(e));     \
+    }                                                                                                   \
+  } while (0)
+  *E = 0;
+  if (M >= 0xFFFFFFFFull) return tg_set_error(TG_EINVAL, "too many region requirements");
+  const uint32_t M32 = (uint32_t)M;
+  IvDev* iv = nullptr;
+  unsigned long long* summary = nullptr;
+  ICHK(ws.get(M * sizeof(IvDev), "intervals", (void**)&iv), "interval table");
+  ICHK(ws.get(64, "summary", (void**)&summary), "summary");
+  ICHK(tg::fill_u32((uint32_t*)summary, 16, 0, st), "clear");
+  hipLaunchKernelGGL(tg::k_make_iv, dim3((N + 255) / 256), dim3(256), 0, st, rq, req_ptr, N, M, space, iv, summary);
+  ICHK(hipGetLastError(), "k_make_iv");
+  unsigned long long sum[3] = {0, 0, 0};
+  ICHK(read_back(sum, summary, sizeof(sum), pinned, st), "summary read-back");
+  if (sum[2]) {
+    const uint32_t b = (uint32_t)sum[2];
+    return tg_set_error(TG_EINVAL, "region requirements: %s%s%s%s", (b & 1) ? "row pointers not ascending; " : "",
+                        (b & 2) ? "interval with lo > hi or outside the index space; " : "",
+                        (b & 4) ? "unknown privilege; " : "",
+                        (b & 8) ? "read-write interval overlapping another interval of its task" : "");
+  }
+  const uint32_t shift = choose_shift(sum[0], sum[1], space, max_buckets);
+  const uint64_t nb = (space + (1ull << shift) - 1) >> shift;
+  uint32_t* bcnt = nullptr;
+  uint64_t* bptr = nullptr;
+  ICHK(ws.get(nb * 4, "bucket counts", (void**)&bcnt), "bucket counts");
+  ICHK(ws.get((nb + 1) * 8, "bucket offsets", (void**)&bptr), "bucket offsets");
+  ICHK(tg::fill_u32(bcnt, nb, 0, st), "clear");
+  if (M32) {
+    hipLaunchKernelGGL(tg::k_bucket_count, dim3((M32 + 255) / 256), dim3(256), 0, st, iv, M32, shift, bcnt);
+    ICHK(hipGetLastError(), "k_bucket_count");
+  }
+  ICHK(tg::scan_counts(bcnt, nb, bptr, ws, st), "bucket scan");
+  uint64_t nent = 0;
+  ICHK(read_back(&nent, bptr + nb, 8, pinned, st), "bucket total read-back");
+  uint32_t* bent = nullptr;
+  ICHK(ws.get(nent * 4, "bucket entries", (void**)&bent), "bucket entries");
+  ICHK(tg::fill_u32(bcnt, nb, 0, st), "clear");
+  if (M32) {
+    hipLaunchKernelGGL(tg::k_bucket_fill, dim3((M32 + 255) / 256), dim3(256), 0, st, iv, M32, shift, bptr, bcnt, bent,
+                       nent);
+    ICHK(hipGetLastError(), "k_bucket_fill");
+  }
+  uint32_t* rcnt = nullptr;
+  ICHK(ws.get((size_t)N * 4, "row counts", (void**)&rcnt), "row counts");
+  const uint32_t rblocks = (uint32_t)(((uint64_t)N * 64 + 255) / 256);
+  hipLaunchKernelGGL(tg::k_rows<false>, dim3(rblocks), dim3(256), 0, st, iv, req_ptr, N, shift, bptr, bent, rcnt,
+                     (const uint64_t*)nullptr, (uint32_t*)nullptr);
+  ICHK(hipGetLastError(), "k_rows (count)");
+  ICHK(tg::scan_counts(rcnt, N, row, ws, st), "row scan");
+  ICHK(read_back(E, row + N, 8, pinned, st), "edge count read-back");
+  if (*E >= 0xFFFFFFFFull) return tg_set_error(TG_EINVAL, "inferred DAG has too many edges (%llu)", (unsigned long long)*E);
+  if (alloc_col) {
+    ICHK(ws.get(*E * 4, "edges", (void**)col), "edge array");
+  } else if (*E > col_cap) {
+    return tg_set_error(TG_ENOMEM, "inferred DAG has %llu edges, capacity %llu", (unsigned long long)*E,
+                        (unsigned long long)col_cap);
+  }
+  if (*E) {
+    hipLaunchKernelGGL(tg::k_rows<true>, dim3(rblocks), dim3(256), 0, st, iv, req_ptr, N, shift, bptr, bent, rcnt, row,
+                       *col);
+    ICHK(hipGetLastError(), "k_rows (fill)");
+    hipLaunchKernelGGL(tg::k_sort_rows, dim3(N), dim3(256), 0, st, row, N, *col);
+    ICHK(hipGetLastError(), "k_sort_rows");
+  }
+  ICHK(hipStreamSynchronize(st), "inference");
+#undef ICHK
+  return TG_OK;
+}
+
+}  // namespace
+
+// Finalize path: requirements from host memory, DAG back to host memory;
+// device buffers allocated for the call.  The edge count and the two other
+// small counts come back through one pinned staging buffer, allocated once
+// per process (outside any timed region) and shared under a lock.
+tg_status tg_infer_dag_host(uint32_t N, const uint64_t* req_ptr, const void* reqs, uint64_t M, uint64_t space,
+                            InferResult& res) {
+  res.row_ptr.assign((size_t)N + 1, 0);
+  res.col.clear();
+  res.ms = 0;
+  if (N == 0) return TG_OK;
   static std::mutex pinned_mu;
   static uint64_t* pinned = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(pinned_mu);
-    if (!pinned) {
-      void* p = nullptr;
-      const hipError_t pe = hipHostMalloc(&p, 64, hipHostMallocDefault);
-      if (pe != hipSuccess) {
-        err = "hipHostMalloc of the read-back word";
-        return pe;
-      }
-      pinned = (uint64_t*)p;
-    }
+  std::lock_guard<std::mutex> lk(pinned_mu);
+  if (!pinned) {
+    void* p = nullptr;
+    const hipError_t pe = hipHostMalloc(&p, 64, hipHostMallocDefault);
+    if (pe != hipSuccess) return tg_set_error(TG_EDEVICE, "hipHostMalloc of the read-back buffer: %s", hipGetErrorString(pe));
+    pinned = (uint64_t*)p;
   }
-  hipStream_t st;
+  hipStream_t st = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    err = "hipStreamCreateWithFlags (an earlier launch may have failed)";
-    return e;
-  }
-  hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  IvDev* d_iv = nullptr;
-  uint64_t *d_req = nullptr, *d_bptr = nullptr, *d_row = nullptr;
-  uint32_t *d_bcnt = nullptr, *d_bent = nullptr, *d_rcnt = nullptr, *d_col = nullptr;
-  uint64_t E = 0;
-  const uint32_t M32 = (uint32_t)M;
-  auto cleanup = [&]() {
-    (void)hipFree(d_iv); (void)hipFree(d_req); (void)hipFree(d_bptr); (void)hipFree(d_row);
-    (void)hipFree(d_bcnt); (void)hipFree(d_bent); (void)hipFree(d_rcnt); (void)hipFree(d_col);
-    (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipStreamDestroy(st);
-  };
-#define ICHK(x) do { e = (x); if (e != hipSuccess) { err = #x; cleanup(); return e; } } while (0)
-  if (M >= 0xFFFFFFFFull) { err = "too many region requirements"; cleanup(); return hipErrorInvalidValue; }
-  ICHK(hipMalloc(&d_iv, iv.size() * sizeof(IvDev)));
-  ICHK(hipMalloc(&d_req, req_ptr.size() * 8));
-  ICHK(hipMalloc(&d_bcnt, nbuckets * 4));
-  ICHK(hipMalloc(&d_bptr, (nbuckets + 1) * 8));
-  ICHK(hipMalloc(&d_rcnt, (size_t)N * 4));
-  ICHK(hipMalloc(&d_row, ((size_t)N + 1) * 8));
-  ICHK(hipMalloc(&d_bent, (nent ? nent : 1) * 4));
-  // uploads are ordered on the inference stream itself (the host vectors
-  // outlive the final stream synchronisation)
-  ICHK(hipMemcpyAsync(d_iv, iv.data(), iv.size() * sizeof(IvDev), hipMemcpyHostToDevice, st));
-  ICHK(hipMemcpyAsync(d_req, req_ptr.data(), req_ptr.size() * 8, hipMemcpyHostToDevice, st));
-  ICHK(hipEventRecord(e0, st));
-  ICHK(hipMemsetAsync(d_bcnt, 0, nbuckets * 4, st));
-  if (M32) {
-    hipLaunchKernelGGL(k_bucket_count, dim3((M32 + 255) / 256), dim3(256), 0, st, d_iv, M32, shift, d_bcnt);
-    ICHK(hipGetLastError());
-  }
-  ICHK(scan_counts(d_bcnt, nbuckets, d_bptr, st));  // d_bptr[nbuckets] == nent
-  ICHK(hipMemsetAsync(d_bcnt, 0, nbuckets * 4, st));
-  if (M32) {
-    hipLaunchKernelGGL(k_bucket_fill, dim3((M32 + 255) / 256), dim3(256), 0, st, d_iv, M32, shift, d_bptr, d_bcnt, d_bent, nent);
-    ICHK(hipGetLastError());
-  }
-  const uint32_t rblocks = (uint32_t)(((uint64_t)N * 64 + 255) / 256);
-  hipLaunchKernelGGL(k_rows<false>, dim3(rblocks), dim3(256), 0, st, d_iv, d_req, N, shift, d_bptr, d_bent, d_rcnt,
-                     (const uint64_t*)nullptr, (uint32_t*)nullptr);
-  ICHK(hipGetLastError());
-  ICHK(scan_counts(d_rcnt, N, d_row, st));
+  if (e != hipSuccess) return tg_set_error(TG_EDEVICE, "hipStreamCreateWithFlags: %s", hipGetErrorString(e));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  tg_status s = TG_OK;
   {
-    // ordered after the count pass on the inference stream itself
-    std::lock_guard<std::mutex> lk(pinned_mu);
-    ICHK(hipMemcpyAsync(pinned, d_row + N, 8, hipMemcpyDeviceToHost, st));
-    ICHK(hipMemcpyAsync(pinned + 1, d_bptr + nbuckets, 8, hipMemcpyDeviceToHost, st));
-    ICHK(hipStreamSynchronize(st));
-    E = pinned[0];
-    if (pinned[1] != nent) {
-      err = "bucket entry count differs between host and device";
-      cleanup();
-      return hipErrorUnknown;
+    Workspace ws;
+    tg_region_req* d_rq = nullptr;
+    uint64_t *d_req = nullptr, *d_row = nullptr;
+    uint32_t* d_col = nullptr;
+    uint64_t E = 0;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess ||
+        (e = ws.get(M * sizeof(tg_region_req), "requirements", (void**)&d_rq)) != hipSuccess ||
+        (e = ws.get(((size_t)N + 1) * 8, "row pointers", (void**)&d_req)) != hipSuccess ||
+        (e = ws.get(((size_t)N + 1) * 8, "rows", (void**)&d_row)) != hipSuccess ||
+        (M && (e = hipMemcpyAsync(d_rq, reqs, M * sizeof(tg_region_req), hipMemcpyHostToDevice, st)) != hipSuccess) ||
+        (e = hipMemcpyAsync(d_req, req_ptr, ((size_t)N + 1) * 8, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipEventRecord(e0, st)) != hipSuccess) {
+      s = tg_set_error(TG_EDEVICE, "dependence inference set-up: %s", hipGetErrorString(e));
+    } else {
+      s = infer_core(ws, N, M, space, d_rq, d_req, 1ull << 26, st, pinned, d_row, &d_col, true, 0, &E);
     }
+    if (s == TG_OK) {
+      res.col.resize(E);
+      if ((e = hipEventRecord(e1, st)) != hipSuccess ||
+          (e = hipMemcpyAsync(res.row_ptr.data(), d_row, ((size_t)N + 1) * 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+          (E && (e = hipMemcpyAsync(res.col.data(), d_col, E * 4, hipMemcpyDeviceToHost, st)) != hipSuccess) ||
+          (e = hipStreamSynchronize(st)) != hipSuccess) {
+        s = tg_set_error(TG_EDEVICE, "dependence inference read-back: %s", hipGetErrorString(e));
+      } else {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) res.ms = ms;
+      }
+    }
+    (void)hipStreamSynchronize(st);
   }
-  if (E >= 0xFFFFFFFFull) { err = "inferred DAG has too many edges"; cleanup(); return hipErrorInvalidValue; }
-  ICHK(hipMalloc(&d_col, (E ? E : 1) * 4));
-  hipLaunchKernelGGL(k_rows<true>, dim3(rblocks), dim3(256), 0, st, d_iv, d_req, N, shift, d_bptr, d_bent, d_rcnt,
-                     d_row, d_col);
-  ICHK(hipGetLastError());
-  hipLaunchKernelGGL(k_sort_rows, dim3(N), dim3(256), 0, st, d_row, N, d_col);
-  ICHK(hipGetLastError());
-  ICHK(hipEventRecord(e1, st));
-  ICHK(hipStreamSynchronize(st));
-  float ms = 0;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  res.ms = ms;
-  res.col.resize(E);
-  ICHK(hipMemcpyAsync(res.row_ptr.data(), d_row, ((size_t)N + 1) * 8, hipMemcpyDeviceToHost, st));
-  if (E) ICHK(hipMemcpyAsync(res.col.data(), d_col, E * 4, hipMemcpyDeviceToHost, st));
-  ICHK(hipStreamSynchronize(st));
-  cleanup();
-#undef ICHK
-  return hipSuccess;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(st);
+  return s;
 }

@@ -76,8 +76,14 @@ struct Ctrl {
   uint32_t stuck_worker, stuck_pos, stuck_cnt, stuck_h, stuck_wcnt;  // first abort
   uint32_t resident;   // residency probe: workers that saw every worker check in
   uint32_t sticky;     // aborts of earlier launches since the host last looked
-  uint32_t pad[55];
+  uint32_t pad0[23];
+  // device clock (s_memrealtime) of the most recent task start any worker
+  // published (atomic max; each worker publishes at most once per
+  // ExecParams::progress_ticks); on its own 128-byte line
+  uint64_t progress;
+  uint32_t pad1[30];
 };
+static_assert(sizeof(Ctrl) == 256 && offsetof(Ctrl, progress) == 128, "control block layout");
 
 struct ExecParams {
   const TaskRec* rec;
@@ -106,7 +112,20 @@ struct ExecParams {
   uint32_t residency_probe;    // 1: check in, wait for all workers (bounded), exit
   uint32_t gang;               // workgroups per gang (mapping 3), else 1
   uint64_t watchdog_ticks;     // s_memrealtime ticks (100 MHz)
+  uint64_t progress_ticks;     // a worker publishes Ctrl::progress at most this often
+  // ready-queue dispatch (kernels k_exec_wave_q / k_exec_block_q)
+  uint32_t* q;                 // qshards x qcap ticket slots (kQEmpty when free)
+  uint64_t* qctl;              // per shard, at kQCtlStride u64: tail << 32 | head
+  uint32_t* qfin;              // tasks finished, flushed by idle workers
+  const uint32_t* qsrc;        // positions without in-edges (pushed at reset)
+  uint32_t nsrc;
+  uint32_t qshards;            // power of two, 1..8
+  uint32_t qcap;               // slots per shard (the task count)
+  uint32_t qtile;              // tickets claimed per pop (1..64)
 };
+
+constexpr uint32_t kQEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kQCtlStride = 16;  // u64 words between shard control words (128 bytes)
 
 constexpr uint32_t kBellStride = 32;  // u32 words between doorbells (128 bytes)
 // Gang mailbox, kMboxStride u32 per gang: [0] sequence number of the last
@@ -121,6 +140,11 @@ constexpr uint32_t kMaxGang = 32;
 hipError_t launch_reset(const ExecParams& p, hipStream_t s);
 hipError_t launch_exec(const ExecParams& p, uint32_t mapping, uint32_t wg_waves, uint32_t grid_blocks,
                        hipStream_t s);
+// Ready-queue dispatch: clear the slots used by the previous launch, then
+// seed the queue with the sources (after launch_reset, before the executor).
+hipError_t launch_queue_reset(const ExecParams& p, hipStream_t s);
+hipError_t launch_exec_queue(const ExecParams& p, uint32_t mapping, uint32_t wg_waves, uint32_t grid_blocks,
+                             hipStream_t s);
 // Occupancy: blocks per CU for the executor kernel of this mapping.
 int exec_blocks_per_cu(uint32_t mapping, uint32_t wg_waves);
 // One task per launch (comparator): runs position `pos` with no counters.
@@ -132,13 +156,21 @@ const void* one_task_kernel();
 #include <string>
 #include <vector>
 
+#include "taskgraph.h"
+
+// Records the message of a failure for tg_last_error() on the calling thread
+// and returns s (tg_host.cpp).
+tg_status tg_set_error(tg_status s, const char* fmt, ...);
+
 // Result of device dependence inference: out-edge CSR, rows ascending.
 struct InferResult {
   std::vector<uint64_t> row_ptr;
   std::vector<uint32_t> col;
   double ms = 0;  // device time of the inference kernels
 };
-// Defined in tg_infer.hip.  reqs points at n_reqs tg_region_req records.
-hipError_t tg_infer_dag_raw(uint32_t N, const uint64_t* req_ptr, const void* reqs, uint64_t n_reqs, uint64_t space,
-                            InferResult& res, std::string& err);
+// Dependence inference of a finalised implicit graph (tg_infer.hip):
+// requirements req_ptr[N+1] / reqs[n_reqs] (tg_region_req records) in host
+// memory, DAG returned in host memory, device buffers allocated per call.
+tg_status tg_infer_dag_host(uint32_t N, const uint64_t* req_ptr, const void* reqs, uint64_t n_reqs, uint64_t space,
+                            InferResult& res);
 hipError_t tg_launch_init_data(uint32_t* A, uint64_t space, uint64_t key2, hipStream_t s);

@@ -23,9 +23,12 @@
 //    its stores to complete (s_waitcnt vmcnt(0)).  Readers load with sc1.
 //    This avoids the L2 write-back that an agent-scope release fence issues
 //    on gfx950, which costs about 13 ns per publication device-wide.
-//  * Every wait is bounded: a worker that sees no progress for the watchdog
-//    interval raises the abort flag and returns, and every other worker
-//    returns when it sees the flag.
+//  * Every wait is bounded: a worker whose wait has lasted the watchdog
+//    interval aborts the launch only if no worker anywhere has started a
+//    task for that long (workers publish a device-wide progress stamp, at
+//    most once per 1/16 of the interval each); every other worker returns
+//    when it sees the abort flag.  A long critical path that keeps most
+//    workers idle therefore never trips the watchdog while it advances.
 #include "tg_internal.h"
 
 namespace tg {
@@ -399,6 +402,7 @@ struct WorkerState {
   uint32_t seen;              // last doorbell value read
   uint32_t spins;             // consecutive empty polls
   uint64_t last;              // time of the last task taken (realtime counter)
+  uint64_t pub;               // time this worker last published Ctrl::progress
   bool rescan;                // the window must be scanned before waiting
   uint32_t pf_pos;            // position whose record dword is held in pf_v
   uint32_t pf_v;              // per lane: dword lane % 32 of that record
@@ -426,6 +430,27 @@ __device__ __forceinline__ uint64_t ready_scan(uint32_t lane, const ExecParams& 
   return uni64(__ballot(valid && c == 0u));
 }
 
+// Global progress: a worker that takes a task publishes the time (atomic
+// max on one word), at most once per progress_ticks, so the word is written
+// rarely however many tasks run.
+__device__ __forceinline__ void publish_progress(const ExecParams& P, WorkerState& w, uint64_t now, bool lead) {
+  if (now - w.pub < P.progress_ticks) return;
+  w.pub = now;
+  if (lead) __hip_atomic_fetch_max(&P.ctrl->progress, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// True when nothing has progressed for the watchdog interval: neither this
+// wait (which began at `since`) nor any worker's published task start is
+// more recent than watchdog_ticks before `now`.  Clocks read by different
+// waves may differ slightly, so a stamp later than `now` counts as `now`.
+__device__ __forceinline__ bool stalled(const ExecParams& P, uint64_t since, uint64_t now) {
+  if (now - since <= P.watchdog_ticks) return false;
+  uint64_t g = __hip_atomic_load(&P.ctrl->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  g = ((uint64_t)uni((uint32_t)(g >> 32)) << 32) | uni((uint32_t)g);
+  if (g > now) return false;
+  return now - g > P.watchdog_ticks;
+}
+
 // One empty poll: back off, and every 64 polls check the abort flag and the
 // watchdog.  Returns false when the worker must stop.
 __device__ __forceinline__ bool idle_step(const ExecParams& P, WorkerState& w, uint32_t lane) {
@@ -435,7 +460,7 @@ __device__ __forceinline__ bool idle_step(const ExecParams& P, WorkerState& w, u
   if ((w.spins & 63u) != 0u) return true;
   if (uni(ld_coherent(&P.ctrl->abort)) != 0u) return false;
   const uint64_t now = __builtin_amdgcn_s_memrealtime();
-  if (now - w.last > P.watchdog_ticks || (P.spin_limit != 0u && w.spins >= P.spin_limit)) {
+  if (stalled(P, w.last, now) || (P.spin_limit != 0u && w.spins >= P.spin_limit)) {
     if (lane == 0) {
       const uint32_t prev = __hip_atomic_fetch_add(&P.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (prev == 0u) {
@@ -461,6 +486,7 @@ __device__ uint32_t next_task(const ExecParams& P, WorkerState& w, uint32_t lane
       w.done |= 1ull << b;
       w.spins = 0;
       w.last = __builtin_amdgcn_s_memrealtime();
+      publish_progress(P, w, w.last, lane == 0);
       return w.wb + w.h + b;
     }
     // slide the window past the finished prefix
@@ -525,6 +551,7 @@ __device__ __forceinline__ void worker_init(WorkerState& w, const ExecParams& P,
   w.seen = 0;
   w.spins = 0;
   w.last = __builtin_amdgcn_s_memrealtime();
+  w.pub = 0;
   w.rescan = true;
   w.pf_pos = kExit;
   w.pf_v = 0;
@@ -589,8 +616,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
 }
 
 // Bounded wait on a gang mailbox word: returns true once *p >= target; false
-// when the launch is being aborted or nothing arrived for the watchdog
-// interval (the waiter then raises the abort flag itself).
+// when the launch is being aborted or nothing progressed anywhere for the
+// watchdog interval (the waiter then raises the abort flag itself).
 __device__ bool gang_wait(const ExecParams& P, const uint32_t* p, uint32_t target) {
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   for (uint32_t spins = 1;; ++spins) {
@@ -598,7 +625,7 @@ __device__ bool gang_wait(const ExecParams& P, const uint32_t* p, uint32_t targe
     if ((spins & 63u) == 0u) {
       if (ld_coherent(&P.ctrl->abort) != 0u) return false;
       const bool limit = P.spin_limit != 0u && spins >= P.spin_limit;
-      if (limit || __builtin_amdgcn_s_memrealtime() - t0 > P.watchdog_ticks) {
+      if (limit || stalled(P, t0, __builtin_amdgcn_s_memrealtime())) {
         __hip_atomic_fetch_add(&P.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return false;
       }
@@ -693,6 +720,262 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   if (member == 0 && P.wprog && threadIdx.x == 0) P.wprog[gang] = w.h;
 }
 
+// ------------------------------------------------------ ready-queue dispatch
+//
+// The second dispatch of the executor (Algorithm 1's EXECUTE_OP on the
+// vertex a COMPLETED_EDGE made ready), without per-worker lists.  The
+// decrement that empties a counter (old value 1) makes its task ready.  A
+// worker keeps the first task its own completion made ready as its next task
+// (so a chain causes no queue traffic) and pushes the others into the
+// ticket queue of its XCD: one ballot of the ready lanes, one atomic add on
+// the shard's tail for all of them, each lane's slot from the count of ready
+// lanes below it.  A worker without work claims up to qtile consecutive
+// tickets of its own shard with one compare-and-swap on the head -- only
+// tickets already taken by pushers, so a claim never waits for a push that
+// may not come -- waits until the claimed slots are written, and runs their
+// tasks one by one; when its shard is empty it tries the others.  Workers
+// count the tasks they ran and add the count to one global word when they
+// find no work; they leave once it reaches the task total.  No worker waits
+// for a particular other worker, so this dispatch needs no co-residency.
+
+__device__ __forceinline__ uint64_t ld_coherent64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct QueueState {
+  uint32_t worker, shard;
+  uint32_t local;   // ready task kept by this worker (kExit: none)
+  uint32_t tile_v;  // per lane: the position in claimed ticket `lane`
+  uint32_t tile_n, tile_i;
+  uint32_t ran;     // tasks run since the last flush to qfin
+  uint32_t spins;
+  uint64_t last, pub;
+};
+
+// Workgroups are dealt to the 8 XCDs round-robin by workgroup index.
+__device__ __forceinline__ void queue_init(QueueState& q, const ExecParams& P, uint32_t worker) {
+  q.worker = worker;
+  q.shard = blockIdx.x & 7u & (P.qshards - 1u);
+  q.local = kExit;
+  q.tile_v = 0;
+  q.tile_n = q.tile_i = 0;
+  q.ran = 0;
+  q.spins = 0;
+  q.last = __builtin_amdgcn_s_memrealtime();
+  q.pub = 0;
+}
+
+__device__ __forceinline__ bool queue_idle(const ExecParams& P, QueueState& q, uint32_t lane) {
+  ++q.spins;
+  const uint32_t nap = q.spins < 64 ? 1u : P.idle_sleep;
+  for (uint32_t i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(2);
+  if ((q.spins & 63u) != 0u) return true;
+  if (uni(ld_coherent(&P.ctrl->abort)) != 0u) return false;
+  const uint64_t now = __builtin_amdgcn_s_memrealtime();
+  if (stalled(P, q.last, now) || (P.spin_limit != 0u && q.spins >= P.spin_limit)) {
+    if (lane == 0) {
+      const uint32_t prev = __hip_atomic_fetch_add(&P.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == 0u) {
+        st_coherent(&P.ctrl->stuck_worker, q.worker);
+        st_coherent(&P.ctrl->stuck_pos, kExit);
+        st_coherent(&P.ctrl->stuck_cnt, ld_coherent(P.qfin));
+        st_coherent(&P.ctrl->stuck_h, q.shard);
+        st_coherent(&P.ctrl->stuck_wcnt, P.npos);
+      }
+    }
+    return false;
+  }
+  return true;
+}
+
+// Claims a tile of tickets from some shard (own shard first).  Returns
+// false when every shard looked empty (or the launch is being aborted).
+__device__ bool queue_claim(const ExecParams& P, QueueState& q, uint32_t lane) {
+  for (uint32_t i = 0; i < P.qshards; ++i) {
+    const uint32_t s = (q.shard + i) & (P.qshards - 1u);
+    uint64_t* ctl = P.qctl + (size_t)s * kQCtlStride;
+    const uint64_t w = uni64(ld_coherent64(ctl));
+    const uint32_t h = (uint32_t)w, t = (uint32_t)(w >> 32);
+    if (h >= t) continue;
+    const uint32_t k = (t - h) < P.qtile ? (t - h) : P.qtile;
+    uint32_t seen = h;
+    if (lane == 0)
+      __hip_atomic_compare_exchange_strong((uint32_t*)ctl, &seen, h + k, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    if (rl(seen, 0) != h) continue;  // another worker took these tickets
+    // tickets h .. h+k-1 are ours; their pushers have already reserved them
+    const uint32_t* slot = P.q + (size_t)s * P.qcap + h;
+    uint32_t v = kQEmpty;
+    for (uint32_t spins = 1;; ++spins) {
+      if (lane < k && v == kQEmpty) v = ld_coherent(slot + lane);
+      if (uni64(__ballot(lane < k && v == kQEmpty)) == 0ull) break;
+      __builtin_amdgcn_s_sleep(1);
+      if ((spins & 1023u) == 0u && uni(ld_coherent(&P.ctrl->abort)) != 0u) return false;
+    }
+    q.tile_v = v;
+    q.tile_n = k;
+    q.tile_i = 0;
+    return true;
+  }
+  return false;
+}
+
+// Position of the worker's next task, or kExit when every task of the
+// launch has finished (or the launch is being aborted).  Run by one wave.
+__device__ uint32_t queue_next(const ExecParams& P, QueueState& q, uint32_t lane) {
+  for (;;) {
+    uint32_t pos = kExit;
+    if (q.local != kExit) {
+      pos = q.local;
+      q.local = kExit;
+    } else if (q.tile_i < q.tile_n) {
+      pos = __builtin_amdgcn_readlane(q.tile_v, q.tile_i);
+      ++q.tile_i;
+    }
+    if (pos != kExit) {
+      q.spins = 0;
+      q.last = __builtin_amdgcn_s_memrealtime();
+      if (q.last - q.pub >= P.progress_ticks) {
+        q.pub = q.last;
+        if (lane == 0) __hip_atomic_fetch_max(&P.ctrl->progress, q.last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      ++q.ran;
+      return pos;
+    }
+    if (queue_claim(P, q, lane)) continue;
+    // no work: report the tasks run so far, leave once all have finished
+    if (q.ran) {
+      if (lane == 0) __hip_atomic_fetch_add(P.qfin, q.ran, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      q.ran = 0;
+    }
+    if (uni(ld_coherent(P.qfin)) >= P.npos) return kExit;
+    if (!queue_idle(P, q, lane)) return kExit;
+  }
+}
+
+// One wave's part of a completion: `ready` marks the lanes whose decrement
+// emptied the counter of `dst`.  The scheduling wave (keep) holds on to the
+// first of them when it has no next task yet; the rest are pushed into the
+// wave's shard with one atomic on its tail.
+__device__ __forceinline__ void queue_push(const ExecParams& P, QueueState& q, bool keep, uint32_t lane, bool ready,
+                                           uint32_t dst) {
+  uint64_t m = uni64(__ballot(ready));
+  if (!m) return;
+  if (keep && q.local == kExit) {
+    const uint32_t first = (uint32_t)__builtin_ctzll(m);
+    q.local = __builtin_amdgcn_readlane(dst, first);
+    m &= m - 1;
+    if (lane == first) ready = false;
+    if (!m) return;
+  }
+  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+  uint32_t base = 0;
+  uint32_t* tail = (uint32_t*)(P.qctl + (size_t)q.shard * kQCtlStride) + 1;
+  if (lane == leader) base = __hip_atomic_fetch_add(tail, (uint32_t)__builtin_popcountll(m), __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+  base = __builtin_amdgcn_readlane(base, leader);
+  if (ready) {
+    const uint32_t below = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1ull));
+    st_coherent(P.q + (size_t)q.shard * P.qcap + base + below, dst);
+  }
+}
+
+// COMPLETED_EDGE for every out-edge, then the pushes (one per wave with
+// ready successors).  The payload stores are drained first, as in the list
+// dispatch.
+template <class Team>
+__device__ __forceinline__ void complete_edges_q(const Team& tm, const ExecParams& P, const Rec& r, QueueState& q,
+                                                 bool keep) {
+  vm_drain();
+  tm.sync();
+  const uint32_t lane = tm.t & 63u;
+  for (uint32_t j0 = 0; j0 < r.nsucc; j0 += tm.size()) {
+    const uint32_t j = j0 + tm.t;
+    bool ready = false;
+    uint32_t dst = 0;
+    if (j < r.nsucc) {
+      dst = j0 == 0 ? r.succ0 : P.succ_pos[r.succ_beg + j];
+      ready = __hip_atomic_fetch_sub(P.cnt + dst, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u;
+    }
+    queue_push(P, q, keep, lane, ready, dst);
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exec_wave_q(ExecParams P) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t worker = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (worker >= P.nworkers) return;
+  const WaveTeam tm{lane};
+  if (P.diag && lane == 0) __hip_atomic_fetch_add(&P.ctrl->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  QueueState q;
+  queue_init(q, P, worker);
+  for (;;) {
+    const uint32_t pos = queue_next(P, q, lane);
+    if (pos == kExit) break;
+    Rec r;
+    run_task(tm, P, pos, rec_dword(P, pos, lane), r);
+    complete_edges_q(tm, P, r, q, true);
+    if (P.tstamp && lane == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
+  }
+}
+
+// One workgroup per task: wave 0 takes the tasks and stages the record in
+// LDS; every wave pushes the successors its lanes made ready.
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exec_block_q(ExecParams P) {
+  __shared__ uint32_t lds[32];
+  __shared__ uint32_t cmd;
+  __shared__ uint32_t recl[32];
+  const uint32_t worker = blockIdx.x;
+  if (worker >= P.nworkers) return;
+  const BlockTeam tm{threadIdx.x, blockDim.x, lds};
+  const uint32_t lane = threadIdx.x & 63u;
+  if (P.diag && threadIdx.x == 0)
+    __hip_atomic_fetch_add(&P.ctrl->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  QueueState q;
+  queue_init(q, P, worker);
+  for (;;) {
+    if (threadIdx.x < 64) {
+      const uint32_t pos = queue_next(P, q, lane);
+      if (pos != kExit && lane < 32) recl[lane] = rec_dword(P, pos, lane);
+      if (lane == 0) cmd = pos;
+    }
+    __syncthreads();
+    const uint32_t pos = uni(cmd);
+    const uint32_t v = recl[lane & 31u];
+    __syncthreads();
+    if (pos == kExit) break;
+    Rec r;
+    run_task(tm, P, pos, v, r);
+    complete_edges_q(tm, P, r, q, threadIdx.x < 64);
+    if (P.tstamp && threadIdx.x == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
+    __syncthreads();
+  }
+}
+
+// Empties the slots the previous launch filled: [0, tail) of every shard
+// (the tails are still the previous launch's; k_queue_seed resets them).
+__global__ __launch_bounds__(256) void k_queue_clear(ExecParams P) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t s = 0; s < P.qshards; ++s) {
+    uint32_t t = (uint32_t)(P.qctl[(size_t)s * kQCtlStride] >> 32);
+    if (t > P.qcap) t = P.qcap;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < t; i += stride) P.q[(size_t)s * P.qcap + i] = kQEmpty;
+  }
+}
+
+// Sources dealt round-robin over the shards; heads, tails and the finished
+// count reset.
+__global__ __launch_bounds__(256) void k_queue_seed(ExecParams P) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint32_t i = gid; i < P.nsrc; i += stride) P.q[(size_t)(i % P.qshards) * P.qcap + i / P.qshards] = P.qsrc[i];
+  if (gid < P.qshards) {
+    const uint64_t cnt = (P.nsrc + P.qshards - 1u - gid) / P.qshards;
+    P.qctl[(size_t)gid * kQCtlStride] = cnt << 32;
+  }
+  if (gid == 0) *P.qfin = 0u;
+}
+
 // Residency probes: the executors' launch bounds and occupancy attributes
 // (so the same number of blocks fits per CU), kept as kernels of their own so
 // that kernel traces of real launches are not mixed with probe launches.
@@ -730,6 +1013,7 @@ __global__ __launch_bounds__(256) void k_reset(ExecParams P) {
   if (blockIdx.x == 0 && threadIdx.x == 0) P.ctrl->sticky += P.ctrl->abort;
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x < 8) (&P.ctrl->abort)[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.ctrl->progress = 0;
 }
 
 // Comparator: one launch runs one task; ordering comes from the stream or
@@ -762,6 +1046,27 @@ hipError_t launch_exec(const ExecParams& p, uint32_t mapping, uint32_t wg_waves,
   } else {
     hipLaunchKernelGGL(k_exec_gang, dim3(grid_blocks), dim3(wg_waves * 64u), 0, s, p);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_reset(const ExecParams& p, hipStream_t s) {
+  uint32_t blocks = (p.npos + 255u) / 256u;
+  if (blocks > 4096u) blocks = 4096u;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_queue_clear, dim3(blocks), dim3(256), 0, s, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  uint32_t sb = (p.nsrc + 255u) / 256u;
+  if (sb > 4096u) sb = 4096u;
+  if (sb == 0) sb = 1;
+  hipLaunchKernelGGL(k_queue_seed, dim3(sb), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_exec_queue(const ExecParams& p, uint32_t mapping, uint32_t wg_waves, uint32_t grid_blocks,
+                             hipStream_t s) {
+  if (mapping == 1) hipLaunchKernelGGL(k_exec_wave_q, dim3(grid_blocks), dim3(256), 0, s, p);
+  else hipLaunchKernelGGL(k_exec_block_q, dim3(grid_blocks), dim3(wg_waves * 64u), 0, s, p);
   return hipGetLastError();
 }
 

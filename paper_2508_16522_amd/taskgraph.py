@@ -24,7 +24,9 @@ TG_EXPLICIT, TG_IMPLICIT = 1, 2
 TG_RO, TG_RW = 1, 2
 TG_MAP_WAVE, TG_MAP_WORKGROUP, TG_MAP_GANG = 1, 2, 3
 TG_SCHED_LIST, TG_SCHED_LEVEL, TG_SCHED_SPREAD, TG_SCHED_COLUMN, TG_SCHED_BALANCED = 1, 2, 3, 4, 5
-TG_CMP_PER_TASK, TG_CMP_HIPGRAPH = 1, 2
+TG_DISPATCH_LISTS, TG_DISPATCH_QUEUE = 1, 2
+TG_CMP_PER_TASK, TG_CMP_HIPGRAPH, TG_CMP_HIPGRAPH_CAPTURED = 1, 2, 3
+TG_KEEP_ALL, TG_KEEP_SINKS, TG_KEEP_NONE = 0, 1, 2
 
 # Every symbol the header declares; the CPU test-suite checks the library
 # exports all of them.
@@ -40,6 +42,7 @@ EXPORTS = (
     "tg_server_create", "tg_server_submit", "tg_server_wait", "tg_server_stats", "tg_server_destroy",
     "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
     "tg_graph_execute_after", "tg_reduce_dag", "tg_graph_reduce_edges",
+    "tg_graph_set_retention", "tg_graph_payload_slots", "tg_graph_read_exec_dag", "tg_emulate_queue",
 )
 
 
@@ -58,7 +61,8 @@ class tg_exec_config(ctypes.Structure):
     _fields_ = [("mapping", ctypes.c_uint32), ("workers", ctypes.c_uint32), ("window", ctypes.c_uint32),
                 ("wg_waves", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32), ("spin_limit", ctypes.c_uint32),
                 ("diag", ctypes.c_uint32), ("notify", ctypes.c_uint32), ("idle_sleep", ctypes.c_uint32),
-                ("schedule", ctypes.c_uint32), ("gang", ctypes.c_uint32)]
+                ("schedule", ctypes.c_uint32), ("gang", ctypes.c_uint32), ("dispatch", ctypes.c_uint32),
+                ("tile", ctypes.c_uint32), ("shards", ctypes.c_uint32)]
 
 
 REQ_DTYPE = np.dtype([("lo", np.uint64), ("hi", np.uint64), ("priv", np.uint32), ("_pad", np.uint32)])
@@ -126,6 +130,10 @@ def load() -> ctypes.CDLL:
         "tg_graph_execute_after": (i32, [G, P, P, P, u32, P]),
         "tg_reduce_dag": (i32, [u32, P, P, P, P, P]),
         "tg_graph_reduce_edges": (i32, [G, P]),
+        "tg_graph_set_retention": (i32, [G, u32]),
+        "tg_graph_payload_slots": (i32, [G, P, P, P]),
+        "tg_graph_read_exec_dag": (i32, [G, P, P, u64, P]),
+        "tg_emulate_queue": (i32, [P, u32, u32, u32, u32, u64, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -268,9 +276,9 @@ def tg_graph_finalize(g):
 
 
 def make_config(mapping=0, workers=0, window=0, wg_waves=0, watchdog_ms=0, spin_limit=0, diag=0, notify=0,
-                idle_sleep=0, schedule=0, gang=0) -> tg_exec_config:
+                idle_sleep=0, schedule=0, gang=0, dispatch=0, tile=0, shards=0) -> tg_exec_config:
     return tg_exec_config(mapping, workers, window, wg_waves, watchdog_ms, spin_limit, diag, notify, idle_sleep,
-                          schedule, gang)
+                          schedule, gang, dispatch, tile, shards)
 
 
 def tg_graph_execute(g, cfg: tg_exec_config | None = None, stream=None):
@@ -351,6 +359,33 @@ def tg_graph_read_dag(g):
     return row_ptr, col[:e.value]
 
 
+def tg_graph_read_exec_dag(g):
+    """The edges the executor's counters follow, as an out-edge CSR."""
+    N = tg_graph_num_tasks(g)
+    row_ptr = np.zeros(N + 1, np.uint64)
+    e = ctypes.c_uint64()
+    st = load().tg_graph_read_exec_dag(g, _ptr(row_ptr), None, 0, ctypes.byref(e))
+    if st not in (TG_OK, TG_ENOMEM):
+        _check(st, "tg_graph_read_exec_dag")
+    col = np.zeros(max(e.value, 1), np.uint32)
+    _check(load().tg_graph_read_exec_dag(g, _ptr(row_ptr), _ptr(col), e.value, ctypes.byref(e)),
+           "tg_graph_read_exec_dag")
+    return row_ptr, col[:e.value]
+
+
+def tg_graph_set_retention(g, mode: int):
+    _check(load().tg_graph_set_retention(g, mode), "tg_graph_set_retention")
+
+
+def tg_graph_payload_slots(g):
+    """(slot of each task, number of slots, device bytes of the payloads)."""
+    N = tg_graph_num_tasks(g)
+    out = np.zeros(max(N, 1), np.uint32)
+    ns, nb = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load().tg_graph_payload_slots(g, _ptr(out), ctypes.byref(ns), ctypes.byref(nb)), "tg_graph_payload_slots")
+    return out[:N], ns.value, nb.value
+
+
 def tg_graph_timings(g):
     c, i, x = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _check(load().tg_graph_timings(g, ctypes.byref(c), ctypes.byref(i), ctypes.byref(x)), "tg_graph_timings")
@@ -385,6 +420,7 @@ def tg_graph_debug_state(g):
 
 
 TG_PROBE_MIX_RATE, TG_PROBE_COPY_BW, TG_PROBE_ATOMIC_DISTINCT, TG_PROBE_ATOMIC_CONTENDED, TG_PROBE_LAUNCH_RATE = 1, 2, 3, 4, 5
+TG_PROBE_HANDOFF_NS = 6
 
 
 def tg_probe(kind: int) -> float:
@@ -440,6 +476,19 @@ def tg_emulate_schedule(graphs, nworkers: int, window: int = 64, seed: int = 0, 
     o = order[:ex.value]
     pairs = np.stack([(o >> np.uint64(32)).astype(np.int64), (o & np.uint64(0xFFFFFFFF)).astype(np.int64)], axis=1)
     return st, pairs, mk.value, bd.value
+
+
+def tg_emulate_queue(graphs, nworkers: int, shards: int = 8, tile: int = 1, seed: int = 0):
+    """Host-only model of the ready-queue dispatch.  Returns (status, order)
+    with order an (executed, 2) array of (graph index, event)."""
+    hs = list(graphs) if isinstance(graphs, (list, tuple)) else [graphs]
+    total = sum(tg_graph_num_tasks(h) for h in hs)
+    arr = (ctypes.c_void_p * len(hs))(*[ctypes.cast(h, ctypes.c_void_p) for h in hs])
+    order = np.zeros(max(total, 1), np.uint64)
+    ex = ctypes.c_uint64()
+    st = load().tg_emulate_queue(arr, len(hs), nworkers, shards, tile, seed, _ptr(order), ctypes.byref(ex))
+    o = order[:ex.value]
+    return st, np.stack([(o >> np.uint64(32)).astype(np.int64), (o & np.uint64(0xFFFFFFFF)).astype(np.int64)], axis=1)
 
 
 def tg_graph_emulate_schedule(g, nworkers: int, window: int = 64, seed: int = 0, schedule: int = 0):
@@ -589,10 +638,12 @@ class Graph:
             pass
 
 
-def graph_from_explicit(eg, finalize: bool = True) -> Graph:
+def graph_from_explicit(eg, finalize: bool = True, retention: int = TG_KEEP_ALL) -> Graph:
     """Build a library graph from a workloads.ExplicitGraph (bulk add)."""
     h = tg_graph_create(TG_EXPLICIT, eg.n, 0, eg.seed)
     g = Graph(h, TG_EXPLICIT, eg.n)
+    if retention != TG_KEEP_ALL:
+        tg_graph_set_retention(h, retention)
     if eg.N:
         tg_task_add_many(h, eg.pred_ptr, eg.preds, None, eg.rounds)
     if finalize:

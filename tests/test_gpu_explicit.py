@@ -200,7 +200,7 @@ def test_c2_stencil_r16_sampled(gpu):
     check_explicit(g, eg, ref)
 
 
-@pytest.mark.parametrize("mode", [tg.TG_CMP_PER_TASK, tg.TG_CMP_HIPGRAPH])
+@pytest.mark.parametrize("mode", [tg.TG_CMP_PER_TASK, tg.TG_CMP_HIPGRAPH, tg.TG_CMP_HIPGRAPH_CAPTURED])
 def test_comparators(gpu, mode):
     eg = wl.pattern_graph("random", 24, 10, seed=4, n=256, rounds=3)
     ref = oracle_explicit(eg)
@@ -209,6 +209,26 @@ def test_comparators(gpu, mode):
         tg.tg_graph_execute_comparator(g.handle, mode)
         tg.tg_graph_wait(g.handle)
         check_explicit(g, eg, ref, payload_sample=16)
+
+
+def test_hipgraph_comparator_after_layout_change(gpu):
+    """The comparator's hipGraph holds the device addresses of the graph's
+    own layout.  A launch in another shape replaces that layout; the next
+    hipGraph comparator call must rebuild its graph rather than replay the
+    freed addresses."""
+    eg = wl.pattern_graph("random", 24, 10, seed=4, n=256, rounds=3)
+    ref = oracle_explicit(eg)
+    g = tg.graph_from_explicit(eg)
+    for cfg in (tg.make_config(mapping=2, wg_waves=2), tg.make_config(mapping=1, workers=64, schedule=4)):
+        tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_HIPGRAPH)
+        tg.tg_graph_wait(g.handle)
+        check_explicit(g, eg, ref, payload_sample=16)
+        run(g, cfg)
+        check_explicit(g, eg, ref, payload_sample=16)
+    tg.tg_graph_autotune(g.handle, reps=1)
+    tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_HIPGRAPH)
+    tg.tg_graph_wait(g.handle)
+    check_explicit(g, eg, ref, payload_sample=16)
 
 
 def test_watchdog_path_then_recovery(gpu):

@@ -96,7 +96,7 @@ def test_halo_program_r64_four_sweeps(gpu):
     _check_exec(g, ig, _ref(ig))
 
 
-@pytest.mark.parametrize("mode", [tg.TG_CMP_PER_TASK, tg.TG_CMP_HIPGRAPH])
+@pytest.mark.parametrize("mode", [tg.TG_CMP_PER_TASK, tg.TG_CMP_HIPGRAPH, tg.TG_CMP_HIPGRAPH_CAPTURED])
 def test_comparators_implicit(gpu, mode):
     ig = wl.halo_graph(6, 128, 3, seed=1, rounds=2)
     g = tg.graph_from_implicit(ig)
@@ -161,6 +161,22 @@ def test_halo_program_reduced_r64(gpu):
     removed = tg.tg_graph_reduce_edges(g.handle)
     assert full - removed == 1023 * (2 * 4 - 1)  # exact transitive reduction of the halo program
     run(g, tg.make_config(mapping=3, wg_waves=8, gang=8))
+    _check_exec(g, ig, _ref(ig))
+
+
+def test_hipgraph_comparator_after_reduction(gpu):
+    """Reducing the executed DAG replaces the graph's layout; the hipGraph
+    comparator built before must not be replayed afterwards."""
+    ig = wl.halo_graph(6, 128, 3, seed=1, rounds=2)
+    g = tg.graph_from_implicit(ig)
+    tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_HIPGRAPH)
+    tg.tg_graph_wait(g.handle)
+    _check_exec(g, ig, _ref(ig))
+    assert tg.tg_graph_reduce_edges(g.handle) > 0
+    tg.tg_graph_execute_comparator(g.handle, tg.TG_CMP_HIPGRAPH)
+    tg.tg_graph_wait(g.handle)
+    _check_exec(g, ig, _ref(ig))
+    run(g)
     _check_exec(g, ig, _ref(ig))
 
 

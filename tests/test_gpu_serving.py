@@ -122,3 +122,24 @@ def test_resubmit_while_pending_is_refused(gpu):
     for x, h in zip(graphs, handles):
         assert np.array_equal(tg.tg_graph_read_digests(h.handle), _ref(x)["digest"])
     assert np.array_equal(tg.tg_graph_read_digests(hs.handle), _ref(slow)["digest"])
+
+
+def test_hipgraph_comparator_after_serving(gpu):
+    """A served request releases the graph's device memory and layout; the
+    hipGraph comparator built before the request must not be replayed."""
+    eg = wl.pattern_graph("fft", 16, 12, seed=2, n=128, rounds=4)
+    h = tg.graph_from_explicit(eg)
+    ref = _ref(eg)
+    tg.tg_graph_execute_comparator(h.handle, tg.TG_CMP_HIPGRAPH)
+    tg.tg_graph_wait(h.handle)
+    assert np.array_equal(tg.tg_graph_read_digests(h.handle), ref["digest"])
+    srv = tg.tg_server_create(1 << 30, slots=1, max_batch=1)
+    try:
+        tg.tg_server_wait(srv, tg.tg_server_submit(srv, h.handle))
+    finally:
+        tg.tg_server_destroy(srv)
+    assert np.array_equal(tg.tg_graph_read_digests(h.handle), ref["digest"])
+    tg.tg_graph_execute_comparator(h.handle, tg.TG_CMP_HIPGRAPH)
+    tg.tg_graph_wait(h.handle)
+    assert np.array_equal(tg.tg_graph_read_digests(h.handle), ref["digest"])
+    assert tg.tg_graph_checksum(h.handle) == ref["checksum"]
