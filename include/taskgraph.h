@@ -294,6 +294,36 @@ tg_status tg_reduce_dag(uint32_t n, const uint64_t* row_ptr, const uint32_t* col
                         uint32_t* out_col, uint64_t* out_e);
 tg_status tg_graph_reduce_edges(tg_graph g, uint64_t* removed);
 
+/* Dependence inference on device-resident requirements (Section 2: tasks
+ * declare the data they access and the runtime discovers the dependences;
+ * Section 5: the result must equal sequential program order).  The kernels
+ * are those of an implicit graph's finalize; the conflict rule is the one
+ * stated at the top of this file: tasks j < k conflict iff an interval of j
+ * and an interval of k share an element and at least one of the two is
+ * read-write, and every conflicting pair is an edge j -> k (no reduction).
+ *   ntasks      : tasks in program order (at most 2^31 - 1).
+ *   req_ptr     : device, ntasks + 1 u64; task k's requirements are
+ *                 reqs[req_ptr[k] .. req_ptr[k+1]); req_ptr[0] = 0,
+ *                 non-decreasing, req_ptr[ntasks] = nreqs.
+ *   reqs        : device, nreqs tg_region_req records (32 bytes each);
+ *                 intervals lie inside [0, index_space); a task's read-write
+ *                 interval overlaps none of its own other intervals.
+ *   row_ptr     : device, ntasks + 1 u64, written: the out-edge CSR.
+ *   col         : device, col_cap u32, written: successors, each row
+ *                 ascending.
+ *   *num_edges  : host, written: the edge count (also when it exceeds
+ *                 col_cap, which returns TG_ENOMEM with col unwritten).
+ *   stream      : every kernel runs on it; the call returns when the DAG is
+ *                 complete (it waits for the stream, which therefore must not
+ *                 be capturing).
+ * The caller owns every array.  Scratch device memory (the interval table,
+ * buckets, counts, scan partials) is allocated with hipMalloc for the call
+ * and freed before it returns.  TG_EINVAL for a bad requirement list (the
+ * message names the fault), TG_EDEVICE for a HIP error. */
+tg_status tg_infer_dag(uint32_t ntasks, const uint64_t* req_ptr, const tg_region_req* reqs, uint64_t nreqs,
+                       uint64_t index_space, uint64_t* row_ptr, uint32_t* col, uint64_t col_cap, uint64_t* num_edges,
+                       void* stream);
+
 /* Times of the last finalize (host compile, device inference) and of the last
  * execution measured with HIP events, in milliseconds (0 when not measured). */
 tg_status tg_graph_timings(tg_graph g, double* compile_ms, double* infer_ms, double* exec_ms);

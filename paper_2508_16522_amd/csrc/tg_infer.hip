@@ -122,7 +122,8 @@ __global__ __launch_bounds__(256) void k_rows(const IvDev* iv, const uint64_t* r
 // requirements rq[req_ptr[k] .. req_ptr[k+1]) become IvDev entries tagged
 // with k.  summary[0] += total length of the non-empty intervals,
 // summary[1] += their number (one atomic per wavefront), summary[2] |=
-// error bits: 1 = row pointers decrease or pass the interval count, 2 = an
+// error bits: 1 = row pointers that do not run from 0 up to the interval
+// count without decreasing, 2 = an
 // interval with lo > hi or beyond the index space, 4 = an unknown privilege,
 // 8 = a read-write interval overlapping another interval of its own task.
 __global__ __launch_bounds__(256) void k_make_iv(const tg_region_req* rq, const uint64_t* req_ptr, uint32_t N,
@@ -133,6 +134,8 @@ __global__ __launch_bounds__(256) void k_make_iv(const tg_region_req* rq, const 
   uint32_t err = 0;
   if (k < N) {
     const uint64_t b = req_ptr[k], e = req_ptr[k + 1];
+    // the rows must partition [0, M): start at 0, never decrease, end at M
+    if ((k == 0 && b != 0) || (k == N - 1 && e != M)) err |= 1u;
     if (e < b || e > M) {
       err |= 1u;
     } else {
@@ -488,7 +491,8 @@ tg_status infer_core(Workspace& ws, uint32_t N, uint64_t M, uint64_t space, cons
   ICHK(read_back(sum, summary, sizeof(sum), pinned, st), "summary read-back");
   if (sum[2]) {
     const uint32_t b = (uint32_t)sum[2];
-    return tg_set_error(TG_EINVAL, "region requirements: %s%s%s%s", (b & 1) ? "row pointers not ascending; " : "",
+    return tg_set_error(TG_EINVAL, "region requirements: %s%s%s%s",
+                        (b & 1) ? "row pointers do not run from 0 to the requirement count without decreasing; " : "",
                         (b & 2) ? "interval with lo > hi or outside the index space; " : "",
                         (b & 4) ? "unknown privilege; " : "",
                         (b & 8) ? "read-write interval overlapping another interval of its task" : "");
@@ -603,4 +607,43 @@ tg_status tg_infer_dag_host(uint32_t N, const uint64_t* req_ptr, const void* req
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(st);
   return s;
+}
+
+// ------------------------------------------- inference on device arrays
+
+namespace {
+
+tg_status infer_args(uint32_t N, const uint64_t* req_ptr, const tg_region_req* reqs, uint64_t M, uint64_t* row_ptr,
+                     uint32_t* col, uint64_t col_cap, uint64_t* E) {
+  if (!E) return tg_set_error(TG_EINVAL, "num_edges is NULL");
+  *E = 0;
+  if (!req_ptr || !row_ptr) return tg_set_error(TG_EINVAL, "req_ptr and row_ptr must be device arrays of ntasks + 1 words");
+  if (M && !reqs) return tg_set_error(TG_EINVAL, "reqs is NULL but nreqs is %llu", (unsigned long long)M);
+  if (col_cap && !col) return tg_set_error(TG_EINVAL, "col is NULL but col_cap is %llu", (unsigned long long)col_cap);
+  // one workgroup per row sorts the rows: the grid limit bounds the task count
+  if (N > 0x7FFFFFFFu) return tg_set_error(TG_EINVAL, "ntasks %u exceeds 2^31 - 1", N);
+  return TG_OK;
+}
+
+// ntasks = 0: the DAG is one row pointer, 0.
+tg_status infer_empty(uint64_t* row_ptr, hipStream_t st) {
+  hipError_t e = tg::fill_u32((uint32_t*)row_ptr, 2, 0, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return tg_set_error(TG_EDEVICE, "dependence inference: %s", hipGetErrorString(e));
+  return TG_OK;
+}
+
+}  // namespace
+
+tg_status tg_infer_dag(uint32_t ntasks, const uint64_t* req_ptr, const tg_region_req* reqs, uint64_t nreqs,
+                       uint64_t index_space, uint64_t* row_ptr, uint32_t* col, uint64_t col_cap, uint64_t* num_edges,
+                       void* stream) {
+  tg_status s = infer_args(ntasks, req_ptr, reqs, nreqs, row_ptr, col, col_cap, num_edges);
+  if (s != TG_OK) return s;
+  const hipStream_t st = (hipStream_t)stream;
+  if (ntasks == 0) return infer_empty(row_ptr, st);
+  Workspace ws;
+  uint32_t* c = col;
+  return infer_core(ws, ntasks, nreqs, index_space, reqs, req_ptr, 1ull << 26, st, nullptr, row_ptr, &c, false,
+                    col_cap, num_edges);
 }

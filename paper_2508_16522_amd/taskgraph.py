@@ -43,6 +43,7 @@ EXPORTS = (
     "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
     "tg_graph_execute_after", "tg_reduce_dag", "tg_graph_reduce_edges",
     "tg_graph_set_retention", "tg_graph_payload_slots", "tg_graph_read_exec_dag", "tg_emulate_queue",
+    "tg_infer_dag",
 )
 
 
@@ -134,6 +135,7 @@ def load() -> ctypes.CDLL:
         "tg_graph_payload_slots": (i32, [G, P, P, P]),
         "tg_graph_read_exec_dag": (i32, [G, P, P, u64, P]),
         "tg_emulate_queue": (i32, [P, u32, u32, u32, u32, u64, P, P]),
+        "tg_infer_dag": (i32, [u32, P, P, u64, u64, P, P, u64, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -153,6 +155,11 @@ def _check(status: int, where: str):
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dptr(t):
+    """Device address of a torch tensor, or an address given as an int."""
+    return ctypes.c_void_p(t if isinstance(t, int) else t.data_ptr())
 
 
 def _stream(stream):
@@ -517,6 +524,17 @@ def tg_graph_reduce_edges(g) -> int:
     removed = ctypes.c_uint64()
     _check(load().tg_graph_reduce_edges(g, ctypes.byref(removed)), "tg_graph_reduce_edges")
     return removed.value
+
+
+def tg_infer_dag(ntasks: int, req_ptr, reqs, nreqs: int, index_space: int, row_ptr, col, col_cap: int,
+                 stream=None) -> int:
+    """Dependence inference on device arrays (torch tensors or addresses):
+    req_ptr u64[ntasks+1], reqs tg_region_req[nreqs] (32 bytes each), output
+    row_ptr u64[ntasks+1] and col u32[col_cap].  Returns the edge count."""
+    e = ctypes.c_uint64()
+    _check(load().tg_infer_dag(ntasks, _dptr(req_ptr), _dptr(reqs), nreqs, index_space, _dptr(row_ptr), _dptr(col),
+                               col_cap, ctypes.byref(e), _stream(stream)), "tg_infer_dag")
+    return e.value
 
 
 def tg_graph_execute_comparator(g, mode: int, stream=None):

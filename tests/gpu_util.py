@@ -38,3 +38,29 @@ def check_explicit(g, eg, ref, payload_sample=None):
 def run(g, cfg=None):
     tg.tg_graph_execute(g.handle, cfg)
     tg.tg_graph_wait(g.handle)
+
+
+def device_requirements(ig):
+    """An implicit graph's requirement list in device memory, in the layout
+    tg_infer_dag takes: (req_ptr u64[N+1], reqs tg_region_req[M]) as torch
+    tensors (int64 and uint8 views of the same bytes)."""
+    import torch
+    r = tg.reqs_array(ig.lo, ig.hi, ig.priv)
+    req_ptr = torch.from_numpy(np.ascontiguousarray(ig.req_ptr, np.uint64).view(np.int64)).cuda()
+    raw = r.view(np.uint8) if r.size else np.zeros(32, np.uint8)
+    reqs = torch.from_numpy(np.ascontiguousarray(raw)).cuda()
+    return req_ptr, reqs
+
+
+def infer_on_device(ig, col_cap=None, fn=None, stream=None):
+    """Runs tg_infer_dag (or fn, same arguments) on ig's requirements;
+    returns the CSR in host memory."""
+    import torch
+    req_ptr, reqs = device_requirements(ig)
+    row = torch.full((ig.N + 1,), -1, dtype=torch.int64, device="cuda")
+    cap = int(col_cap if col_cap is not None else max(ig.N * 8, 64))
+    col = torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()  # the inputs are in place before another stream reads them
+    E = (fn or tg.tg_infer_dag)(ig.N, req_ptr, reqs, int(ig.lo.size), ig.space, row, col, cap, stream)
+    torch.cuda.synchronize()
+    return row.cpu().numpy().view(np.uint64), col[:E].cpu().numpy().view(np.uint32)
