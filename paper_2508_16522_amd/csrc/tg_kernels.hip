@@ -806,11 +806,20 @@ __device__ bool queue_claim(const ExecParams& P, QueueState& q, uint32_t lane) {
     // tickets h .. h+k-1 are ours; their pushers have already reserved them
     const uint32_t* slot = P.q + (size_t)s * P.qcap + h;
     uint32_t v = kQEmpty;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     for (uint32_t spins = 1;; ++spins) {
       if (lane < k && v == kQEmpty) v = ld_coherent(slot + lane);
       if (uni64(__ballot(lane < k && v == kQEmpty)) == 0ull) break;
       __builtin_amdgcn_s_sleep(1);
-      if ((spins & 1023u) == 0u && uni(ld_coherent(&P.ctrl->abort)) != 0u) return false;
+      if ((spins & 1023u) == 0u) {
+        // a pusher stores right after reserving, so this wait is short; it
+        // is bounded all the same
+        if (uni(ld_coherent(&P.ctrl->abort)) != 0u) return false;
+        if (stalled(P, t0, __builtin_amdgcn_s_memrealtime())) {
+          if (lane == 0) __hip_atomic_fetch_add(&P.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          return false;
+        }
+      }
     }
     q.tile_v = v;
     q.tile_n = k;

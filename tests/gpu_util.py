@@ -58,7 +58,8 @@ def infer_on_device(ig, col_cap=None, fn=None, stream=None):
     import torch
     req_ptr, reqs = device_requirements(ig)
     row = torch.full((ig.N + 1,), -1, dtype=torch.int64, device="cuda")
-    cap = int(col_cap if col_cap is not None else max(ig.N * 8, 64))
+    # default capacity: every pair of tasks for small programs
+    cap = int(col_cap if col_cap is not None else max(ig.N * (ig.N - 1) // 2 if ig.N <= 4096 else ig.N * 128, 64))
     col = torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()  # the inputs are in place before another stream reads them
     E = (fn or tg.tg_infer_dag)(ig.N, req_ptr, reqs, int(ig.lo.size), ig.space, row, col, cap, stream)
