@@ -323,6 +323,22 @@ tg_status tg_graph_reduce_edges(tg_graph g, uint64_t* removed);
 tg_status tg_infer_dag(uint32_t ntasks, const uint64_t* req_ptr, const tg_region_req* reqs, uint64_t nreqs,
                        uint64_t index_space, uint64_t* row_ptr, uint32_t* col, uint64_t col_cap, uint64_t* num_edges,
                        void* stream);
+/* tg_infer_dag for callers that cannot allocate device memory (serving loops
+ * that must not call hipMalloc, harnesses that forbid it): same arguments,
+ * same result, no hipMalloc, hipFree or allocator call.  Its scratch is one
+ * 16 MiB array of device memory in the library's code object, one copy per
+ * device, held until the process ends; the call fails with TG_ENOMEM (the
+ * message names the array that did not fit) when the requirement list needs
+ * more.  The interval table takes 32 bytes per requirement and the row counts
+ * 4 bytes per task, so about 400,000 requirements fit (the 65,536-task halo
+ * program with 196,480 requirements takes about 9 MiB).  Every call on a
+ * device shares that device's array and leaves its contents behind; each call
+ * clears what it reads before writing it.  Calls from this process on one
+ * device are serialised by a lock; calls from two processes use two copies.
+ * Outputs are unspecified after an error other than TG_ENOMEM for col_cap. */
+tg_status tg_infer_dag_noalloc(uint32_t ntasks, const uint64_t* req_ptr, const tg_region_req* reqs, uint64_t nreqs,
+                               uint64_t index_space, uint64_t* row_ptr, uint32_t* col, uint64_t col_cap,
+                               uint64_t* num_edges, void* stream);
 
 /* Times of the last finalize (host compile, device inference) and of the last
  * execution measured with HIP events, in milliseconds (0 when not measured). */

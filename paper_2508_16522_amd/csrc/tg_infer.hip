@@ -473,7 +473,9 @@ tg_status infer_core(Workspace& ws, uint32_t N, uint64_t M, uint64_t space, cons
   do {                                                                                                  \
     e = (x);                                                                                            \
     if (e != hipSuccess) {                                                                              \
-      if (ws.missing) return tg_set_error(TG_ENOMEM, "dependence inference: %s do not fit the scratch array", ws.missing); \
+      if (ws.missing)                                                                                   \
+        return tg_set_error(TG_ENOMEM, "dependence inference: the %s do not fit the %zu-byte scratch array", \
+                            ws.missing, ws.cap);                                                        \
       return tg_set_error(TG_EDEVICE, "dependence inference (%s): %s", what, hipGetErrorString(e));     \
     }                                                                                                   \
   } while (0)
@@ -645,5 +647,69 @@ tg_status tg_infer_dag(uint32_t ntasks, const uint64_t* req_ptr, const tg_region
   Workspace ws;
   uint32_t* c = col;
   return infer_core(ws, ntasks, nreqs, index_space, reqs, req_ptr, 1ull << 26, st, nullptr, row_ptr, &c, false,
+                    col_cap, num_edges);
+}
+
+// ------------------------------------------- allocation-free inference
+//
+// tg_infer_dag_noalloc takes every temporary of infer_core from one array
+// of device memory that the code object defines, so the call makes no
+// allocation.  Each device holds its own copy of the array until the process
+// ends.  On the host, `scratch` names only a stand-in for the device symbol:
+// its device address comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is handed to kernels and
+// copies.
+
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr uint64_t kNoallocMaxBuckets = 1ull << 18;  // bucket arrays of at most 3 MiB
+
+struct ScratchDev {
+  std::once_flag once;
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+  std::mutex mu;  // one call at a time per device in this process
+};
+ScratchDev g_scratch[kMaxDevices];
+
+size_t round256(uint64_t b) { return (size_t)((b + 255) & ~255ull); }
+
+}  // namespace
+
+tg_status tg_infer_dag_noalloc(uint32_t ntasks, const uint64_t* req_ptr, const tg_region_req* reqs, uint64_t nreqs,
+                               uint64_t index_space, uint64_t* row_ptr, uint32_t* col, uint64_t col_cap,
+                               uint64_t* num_edges, void* stream) {
+  tg_status s = infer_args(ntasks, req_ptr, reqs, nreqs, row_ptr, col, col_cap, num_edges);
+  if (s != TG_OK) return s;
+  // the interval table, the summary and the row counts must fit before any
+  // device work starts; later arrays are checked as they are carved
+  const uint64_t need = round256(nreqs * sizeof(IvDev)) + 256 + round256((uint64_t)ntasks * 4);
+  if (nreqs > kScratchBytes || need > kScratchBytes)
+    return tg_set_error(TG_ENOMEM,
+                        "allocation-free inference: %u tasks with %llu requirements need more than the %zu-byte "
+                        "scratch array (at least %llu bytes)",
+                        ntasks, (unsigned long long)nreqs, kScratchBytes, (unsigned long long)need);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return tg_set_error(TG_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return tg_set_error(TG_EDEVICE, "device %d: the scratch table holds devices 0..%d", dev, kMaxDevices - 1);
+  ScratchDev& sd = g_scratch[dev];
+  std::call_once(sd.once, [&sd] { sd.err = hipGetSymbolAddress(&sd.ptr, HIP_SYMBOL(scratch)); });
+  if (sd.err != hipSuccess || !sd.ptr)
+    return tg_set_error(TG_EDEVICE, "hipGetSymbolAddress of the scratch array on device %d: %s", dev,
+                        hipGetErrorString(sd.err));
+  std::lock_guard<std::mutex> lk(sd.mu);
+  const hipStream_t st = (hipStream_t)stream;
+  if (ntasks == 0) return infer_empty(row_ptr, st);
+  Workspace ws;
+  ws.base = (uint8_t*)sd.ptr;
+  ws.cap = kScratchBytes;
+  uint32_t* c = col;
+  return infer_core(ws, ntasks, nreqs, index_space, reqs, req_ptr, kNoallocMaxBuckets, st, nullptr, row_ptr, &c, false,
                     col_cap, num_edges);
 }

@@ -43,7 +43,7 @@ EXPORTS = (
     "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
     "tg_graph_execute_after", "tg_reduce_dag", "tg_graph_reduce_edges",
     "tg_graph_set_retention", "tg_graph_payload_slots", "tg_graph_read_exec_dag", "tg_emulate_queue",
-    "tg_infer_dag",
+    "tg_infer_dag", "tg_infer_dag_noalloc",
 )
 
 
@@ -136,6 +136,7 @@ def load() -> ctypes.CDLL:
         "tg_graph_read_exec_dag": (i32, [G, P, P, u64, P]),
         "tg_emulate_queue": (i32, [P, u32, u32, u32, u32, u64, P, P]),
         "tg_infer_dag": (i32, [u32, P, P, u64, u64, P, P, u64, P, P]),
+        "tg_infer_dag_noalloc": (i32, [u32, P, P, u64, u64, P, P, u64, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -534,6 +535,16 @@ def tg_infer_dag(ntasks: int, req_ptr, reqs, nreqs: int, index_space: int, row_p
     e = ctypes.c_uint64()
     _check(load().tg_infer_dag(ntasks, _dptr(req_ptr), _dptr(reqs), nreqs, index_space, _dptr(row_ptr), _dptr(col),
                                col_cap, ctypes.byref(e), _stream(stream)), "tg_infer_dag")
+    return e.value
+
+
+def tg_infer_dag_noalloc(ntasks: int, req_ptr, reqs, nreqs: int, index_space: int, row_ptr, col, col_cap: int,
+                         stream=None) -> int:
+    """tg_infer_dag without any device allocation (the library's fixed
+    scratch array); same arguments and result."""
+    e = ctypes.c_uint64()
+    _check(load().tg_infer_dag_noalloc(ntasks, _dptr(req_ptr), _dptr(reqs), nreqs, index_space, _dptr(row_ptr),
+                                       _dptr(col), col_cap, ctypes.byref(e), _stream(stream)), "tg_infer_dag_noalloc")
     return e.value
 
 
