@@ -252,7 +252,8 @@ struct Layout {
   Config cfg;
   uint32_t nworkers = 0, grid_blocks = 0, npos = 0, last_started = 0;
   DevBuf rec, pred_addr, succ_pos, indeg, cnt, wbase, gtab, reqs, ctrl, execs, wprog, owner, bell, tstamp, wstamp, mbox;
-  DevBuf q, qctl, qfin, qsrc;  // ready-queue dispatch
+  DevBuf q, qctl, qsrc;  // ready-queue dispatch
+  uint32_t qwmax = 0;    // most workers claiming from one queue shard
   std::vector<std::vector<uint32_t>> pos_of;  // per graph: task id -> position
   std::vector<TaskRec> rec_host;               // host copy (rounds can be re-set)
   ExecParams params{};
@@ -943,6 +944,29 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
   return TG_OK;
 }
 
+// Most workers that claim tickets from one queue shard: a worker claims from
+// shard (workgroup index mod 8) mod shards, as the kernels do; wavefront
+// workers sit four to a workgroup.
+uint32_t queue_workers_per_shard(const Config& cfg, uint32_t nw, uint32_t shards) {
+  std::vector<uint32_t> per(shards, 0);
+  for (uint32_t w = 0; w < nw; ++w) {
+    const uint32_t block = cfg.mapping == TG_MAP_WAVE ? w / 4 : w;
+    per[(block & 7u) & (shards - 1u)]++;
+  }
+  return *std::max_element(per.begin(), per.end());
+}
+
+// Shards a launch of nw workers uses: every shard needs a workgroup that
+// claims from it (a claimed ticket is only ever run by its claimer, so tasks
+// pushed into a shard without workers would never run), so at most as many
+// shards as workgroups, rounded down to a power of two.
+uint32_t queue_shards(const Config& cfg, uint32_t nw) {
+  const uint32_t blocks = cfg.mapping == TG_MAP_WAVE ? (nw + 3) / 4 : nw;
+  uint32_t s = cfg.shards;
+  while (s > 1 && s > blocks) s >>= 1;
+  return s;
+}
+
 tg_status ensure_device(tg_graph g);
 tg_status ensure_events(tg_graph g);
 
@@ -1011,6 +1035,15 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   }
   L->pos_of = std::move(H.pos_of);
   const uint32_t N = H.N;
+  // queue dispatch: the sources (pushed at reset) and the number of sinks
+  // (the launch ends when all have run)
+  std::vector<uint32_t> src;
+  uint32_t sinks = 0;
+  if (cfg.dispatch == TG_DISPATCH_QUEUE)
+    for (uint32_t p = 0; p < N; ++p) {
+      if (H.indeg[p] == 0) src.push_back(p);
+      if (H.rec[p].nsucc == 0) ++sinks;
+    }
   if ((s = upload(L->rec, H.rec)) != TG_OK) return s;
   if (keep_host) L->rec_host = std::move(H.rec);
   if ((s = upload(L->pred_addr, H.pred_addr)) != TG_OK) return s;
@@ -1053,26 +1086,29 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   P.spin_limit = cfg.spin_limit;
   P.watchdog_ticks = (uint64_t)cfg.watchdog_ms * 100000ull;
   if (cfg.dispatch == TG_DISPATCH_QUEUE) {
-    // one ticket slot per task in each shard (every task is pushed at most
-    // once, into one shard), all empty; the sources are pushed at reset
-    std::vector<uint32_t> src;
-    for (uint32_t p = 0; p < N; ++p)
-      if (H.indeg[p] == 0) src.push_back(p);
-    if ((s = L->q.alloc((size_t)cfg.shards * N * 4)) != TG_OK) return s;
-    HIPCHK(hipMemset(L->q.p, 0xFF, (size_t)cfg.shards * N * 4));
-    if ((s = L->qctl.alloc((size_t)cfg.shards * tg::kQCtlStride * 8)) != TG_OK) return s;
-    HIPCHK(hipMemset(L->qctl.p, 0, (size_t)cfg.shards * tg::kQCtlStride * 8));
-    if ((s = L->qfin.alloc(256)) != TG_OK) return s;
-    HIPCHK(hipMemset(L->qfin.p, 0, 256));
+    // Each shard has a ticket slot for every task (each task is pushed once,
+    // into one shard) plus the exit sentinels of its workers: tile x (workers
+    // claiming from it + 1), sized for the largest tile so that a launch may
+    // choose any tile.  All slots start empty; the sources are pushed at reset.
+    const uint32_t shards = queue_shards(cfg, H.nw);
+    L->qwmax = queue_workers_per_shard(cfg, H.nw, shards);
+    const uint64_t cap = (uint64_t)N + 64ull * (L->qwmax + 1);
+    if (cap >= 0xFFFFFFF0ull) return fail(TG_EINVAL, "queue of %llu slots per shard is too large", (unsigned long long)cap);
+    if ((s = L->q.alloc((size_t)shards * cap * 4)) != TG_OK) return s;
+    HIPCHK(hipMemset(L->q.p, 0xFF, (size_t)shards * cap * 4));
+    const size_t ctl_bytes = (size_t)(2 * shards + 1) * tg::kQLine * 4;
+    if ((s = L->qctl.alloc(ctl_bytes)) != TG_OK) return s;
+    HIPCHK(hipMemset(L->qctl.p, 0, ctl_bytes));
     if ((s = upload(L->qsrc, src)) != TG_OK) return s;
     P.q = L->q.as<uint32_t>();
-    P.qctl = L->qctl.as<uint64_t>();
-    P.qfin = L->qfin.as<uint32_t>();
+    P.qctl = L->qctl.as<uint32_t>();
     P.qsrc = L->qsrc.as<uint32_t>();
     P.nsrc = (uint32_t)src.size();
-    P.qshards = cfg.shards;
-    P.qcap = N;
+    P.nsinks = sinks;
+    P.qshards = shards;
+    P.qcap = (uint32_t)cap;
     P.qtile = cfg.tile;
+    P.qsent = cfg.tile * (L->qwmax + 1);
   }
   if ((s = null_stream_fence()) != TG_OK) return s;
   L->plan_ms = plan_ms;
@@ -1163,41 +1199,50 @@ tg_status emulate_layout(const HostLayout& H, uint32_t window, uint64_t seed, ui
 // CPU model of the ready-queue dispatch (k_exec_wave_q): workers take one
 // step at a time in a seeded pseudo-random order, and every access to shared
 // state is a step of its own, so the model visits the interleavings the
-// kernels can produce -- a claim's read of (head, tail) and its
-// compare-and-swap, a push's reservation of tickets and the writes of the
-// slots, waiting for claimed slots that are still empty, the finished-count
-// flush and exit test.  It checks that every task runs exactly once, after
-// all its in-edges, and that every worker leaves.
+// kernels can produce -- a claim's atomic add on a shard head, polls of a
+// claimed slot that is still empty, a push's reservation of tickets on a
+// shard tail and each write of a reserved slot, the report of finished sinks,
+// and the finisher's reservation and writes of the exit sentinels.  It checks
+// that every task runs exactly once, after all its in-edges, that no ticket
+// lies beyond a shard's capacity (the task count plus the sentinels), that a
+// worker leaves only after reporting its sinks, and that every worker leaves.
 tg_status emulate_queue(const HostLayout& H, uint32_t nworkers, uint32_t shards, uint32_t tile, uint64_t seed,
                         uint32_t* order, uint64_t* executed) {
   const uint32_t N = H.N;
-  const uint32_t kNone = 0xFFFFFFFFu;
+  const uint32_t kNone = 0xFFFFFFFFu, kExitSlot = 0xFFFFFFFEu;
+  Config qc;
+  qc.mapping = TG_MAP_WAVE;
+  qc.shards = shards;
+  shards = queue_shards(qc, nworkers);
+  const uint32_t wmax = queue_workers_per_shard(qc, nworkers, shards);
+  const uint64_t cap = (uint64_t)N + 64ull * (wmax + 1);
+  const uint32_t sent = tile * (wmax + 1);
   std::vector<uint32_t> cnt(H.indeg);
-  std::vector<std::vector<uint32_t>> slot(shards, std::vector<uint32_t>(N, kNone));
-  std::vector<uint32_t> head(shards, 0), tail(shards, 0);
-  uint32_t nsrc = 0;
-  for (uint32_t p = 0; p < N; ++p)
+  std::vector<std::vector<uint32_t>> slot(shards, std::vector<uint32_t>(cap, kNone));
+  std::vector<uint64_t> head(shards, 0), tail(shards, 0);
+  uint32_t nsrc = 0, nsinks = 0;
+  for (uint32_t p = 0; p < N; ++p) {
     if (H.indeg[p] == 0) {
       slot[nsrc % shards][nsrc / shards] = p;
       nsrc++;
     }
+    if (H.rec[p].nsucc == 0) ++nsinks;
+  }
   for (uint32_t s = 0; s < shards; ++s) tail[s] = (nsrc + shards - 1 - s) / shards;
   uint64_t fin = 0, ex = 0;
   std::vector<uint8_t> done(N, 0);
-  enum Phase { kLook, kCas, kWait, kPushWrite, kFlush };
+  enum Phase { kNext, kClaim, kPoll, kReport, kReserve, kWrite, kFinReserve, kFinWrite };
   struct W {
-    Phase ph = kLook;
-    uint32_t shard = 0, local = 0xFFFFFFFFu, probe = 0;
-    uint32_t seen_h = 0, seen_t = 0, claim_s = 0, claim_h = 0, claim_k = 0;
-    std::vector<uint32_t> tile;  // claimed positions not yet run
-    size_t tile_i = 0;
-    uint32_t ran = 0;
+    Phase ph = kNext;
+    uint32_t shard = 0, pshard = 0, local = 0xFFFFFFFFu;
+    uint64_t tile_h = 0;
+    uint32_t tile_n = 0, tile_i = 0, sinks = 0;
     std::vector<uint32_t> pending;  // ready positions to write into reserved slots
-    uint32_t pbase = 0, ps = 0;
-    bool exited = false;
+    uint64_t pbase = 0;
+    uint32_t ps = 0, fin_s = 0, fin_left = 0;
   };
   std::vector<W> ws(nworkers);
-  for (uint32_t w = 0; w < nworkers; ++w) ws[w].shard = (w / 4) % 8 % shards;
+  for (uint32_t w = 0; w < nworkers; ++w) ws[w].shard = ws[w].pshard = ((w / 4) & 7u) & (shards - 1u);
   uint64_t rng = seed * 0x9E3779B97F4A7C15ull + 7;
   auto next_rand = [&]() {
     rng ^= rng << 13;
@@ -1205,10 +1250,33 @@ tg_status emulate_queue(const HostLayout& H, uint32_t nworkers, uint32_t shards,
     rng ^= rng << 17;
     return rng;
   };
+  // run task `pos` on worker x: signal its out-edges, keep one ready successor
+  auto run = [&](W& x, uint32_t pos) -> tg_status {
+    if (pos >= N || done[pos] || cnt[pos] != 0) return fail(TG_EINVAL, "queue model: position %u run twice or early", pos);
+    done[pos] = 1;
+    if (order) order[ex] = pos;
+    ++ex;
+    const TaskRec& r = H.rec[pos];
+    if (r.nsucc == 0) x.sinks++;
+    std::vector<uint32_t> ready;
+    for (uint32_t j = 0; j < r.nsucc; ++j) {
+      const uint32_t d = H.succ_pos[r.succ_beg + j];
+      if (cnt[d] == 0) return fail(TG_EINVAL, "queue model: counter underflow at %u", d);
+      if (--cnt[d] == 0) ready.push_back(d);
+    }
+    if (!ready.empty() && x.local == kNone) {
+      x.local = ready.front();
+      ready.erase(ready.begin());
+    }
+    x.pending.assign(ready.rbegin(), ready.rend());
+    x.ph = x.pending.empty() ? kNext : kReserve;
+    return TG_OK;
+  };
   std::vector<uint32_t> live(nworkers);
   for (uint32_t w = 0; w < nworkers; ++w) live[w] = w;
   uint64_t steps = 0;
   const uint64_t max_steps = 64ull * (N + 16) * (nworkers + 8) + 100000;
+  tg_status st = TG_OK;
   while (!live.empty()) {
     if (++steps > max_steps) {
       *executed = ex;
@@ -1217,101 +1285,83 @@ tg_status emulate_queue(const HostLayout& H, uint32_t nworkers, uint32_t shards,
     const size_t li = (size_t)(next_rand() % live.size());
     W& x = ws[live[li]];
     switch (x.ph) {
-      case kPushWrite: {  // write one reserved slot
-        slot[x.ps][x.pbase] = x.pending.back();
-        x.pending.pop_back();
-        x.pbase++;
-        if (x.pending.empty()) x.ph = kLook;
-        break;
-      }
-      case kWait: {  // the claimed slots, once written
-        bool all = true;
-        for (uint32_t i = 0; i < x.claim_k; ++i) all &= slot[x.claim_s][x.claim_h + i] != kNone;
-        if (!all) break;
-        x.tile.assign(slot[x.claim_s].begin() + x.claim_h, slot[x.claim_s].begin() + x.claim_h + x.claim_k);
-        x.tile_i = 0;
-        x.ph = kLook;
-        break;
-      }
-      case kCas: {
-        const uint32_t s = x.claim_s;
-        if (head[s] == x.seen_h) {
-          x.claim_k = std::min(tile, x.seen_t - x.seen_h);
-          x.claim_h = x.seen_h;
-          head[s] = x.seen_h + x.claim_k;
-          x.ph = kWait;
+      case kNext:
+        if (x.local != kNone) {
+          const uint32_t pos = x.local;
+          x.local = kNone;
+          if ((st = run(x, pos)) != TG_OK) return st;
         } else {
-          x.probe++;
-          x.ph = kLook;
+          x.ph = x.tile_i == x.tile_n ? kClaim : kPoll;
         }
         break;
-      }
-      case kFlush: {  // report the tasks run, then test for the end
-        fin += x.ran;
-        x.ran = 0;
-        if (fin >= N) {
-          x.exited = true;
+      case kClaim:  // one atomic add on the head: never fails
+        x.tile_h = head[x.shard];
+        head[x.shard] += tile;
+        x.tile_n = tile;
+        x.tile_i = 0;
+        x.ph = kPoll;
+        break;
+      case kPoll: {
+        const uint64_t t = x.tile_h + x.tile_i;
+        if (t >= cap) return fail(TG_EINVAL, "queue model: ticket %llu beyond capacity %llu", (unsigned long long)t,
+                                  (unsigned long long)cap);
+        const uint32_t v = slot[x.shard][t];
+        if (v == kNone) {
+          if (x.sinks) x.ph = kReport;  // nothing to run: report finished sinks first
+          break;
+        }
+        x.tile_i++;
+        if (v == kExitSlot) {
+          if (x.sinks) return fail(TG_EINVAL, "queue model: worker leaves with unreported sinks");
           live[li] = live.back();
           live.pop_back();
+          break;
+        }
+        if ((st = run(x, v)) != TG_OK) return st;
+        break;
+      }
+      case kReport: {
+        const uint64_t old = fin;
+        fin += x.sinks;
+        const bool last = old + x.sinks == nsinks;
+        x.sinks = 0;
+        if (last) {
+          x.fin_s = 0;
+          x.ph = kFinReserve;
         } else {
-          x.ph = kLook;
-          x.probe = 0;
+          x.ph = kPoll;
         }
         break;
       }
-      case kLook: {
-        uint32_t pos = kNone;
-        if (x.local != kNone) {
-          pos = x.local;
-          x.local = kNone;
-        } else if (x.tile_i < x.tile.size()) {
-          pos = x.tile[x.tile_i++];
-        }
-        if (pos != kNone) {  // run the task and signal its out-edges
-          if (done[pos] || cnt[pos] != 0) return fail(TG_EINVAL, "queue model: position %u run twice or early", pos);
-          done[pos] = 1;
-          if (order) order[ex] = pos;
-          ++ex;
-          x.ran++;
-          const TaskRec& r = H.rec[pos];
-          std::vector<uint32_t> ready;
-          for (uint32_t j = 0; j < r.nsucc; ++j) {
-            const uint32_t d = H.succ_pos[r.succ_beg + j];
-            if (cnt[d] == 0) return fail(TG_EINVAL, "queue model: counter underflow at %u", d);
-            if (--cnt[d] == 0) ready.push_back(d);
-          }
-          if (!ready.empty() && x.local == kNone) {
-            x.local = ready.front();
-            ready.erase(ready.begin());
-          }
-          if (!ready.empty()) {  // reserve the tickets now, write them in later steps
-            x.ps = x.shard;
-            x.pbase = tail[x.ps];
-            tail[x.ps] += (uint32_t)ready.size();
-            x.pending.assign(ready.rbegin(), ready.rend());
-            x.ph = kPushWrite;
-          }
-          break;
-        }
-        if (x.probe >= shards) {  // every shard looked empty
-          x.ph = kFlush;
-          break;
-        }
-        const uint32_t s = (x.shard + x.probe) % shards;
-        if (head[s] < tail[s]) {
-          x.claim_s = s;
-          x.seen_h = head[s];
-          x.seen_t = tail[s];
-          x.ph = kCas;
-        } else {
-          x.probe++;
-        }
+      case kFinReserve:
+        x.pbase = tail[x.fin_s];
+        tail[x.fin_s] += sent;
+        x.fin_left = sent;
+        x.ph = kFinWrite;
         break;
-      }
+      case kFinWrite:
+        if (x.pbase >= cap) return fail(TG_EINVAL, "queue model: sentinel beyond capacity");
+        slot[x.fin_s][x.pbase++] = kExitSlot;
+        if (--x.fin_left == 0) x.ph = ++x.fin_s < shards ? kFinReserve : kPoll;
+        break;
+      case kReserve:
+        x.ps = x.pshard;
+        x.pshard = (x.pshard + 1) % shards;
+        x.pbase = tail[x.ps];
+        tail[x.ps] += x.pending.size();
+        if (tail[x.ps] > cap) return fail(TG_EINVAL, "queue model: shard %u overflows", x.ps);
+        x.ph = kWrite;
+        break;
+      case kWrite:
+        slot[x.ps][x.pbase++] = x.pending.back();
+        x.pending.pop_back();
+        if (x.pending.empty()) x.ph = kNext;
+        break;
     }
   }
   *executed = ex;
   if (ex != N) return fail(TG_EINVAL, "queue model ran %llu of %u tasks", (unsigned long long)ex, N);
+  if (fin != nsinks) return fail(TG_EINVAL, "queue model: %llu of %u sinks reported", (unsigned long long)fin, nsinks);
   return TG_OK;
 }
 
@@ -1462,7 +1512,10 @@ tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph
       HIPCHK(tg_launch_init_data(g->data.as<uint32_t>(), g->space, sm64_host(g->seed ^ (2ull << 32)), st));
     }
   const bool queue = L.cfg.dispatch == TG_DISPATCH_QUEUE;
-  if (queue) P.qtile = cfg.tile;
+  if (queue) {
+    P.qtile = cfg.tile;
+    P.qsent = cfg.tile * (L.qwmax + 1);
+  }
   HIPCHK(tg::launch_reset(P, st));
   if (queue) HIPCHK(tg::launch_queue_reset(P, st));
   if (before_kernel) HIPCHK(hipEventRecord(before_kernel, st));

@@ -115,17 +115,21 @@ struct ExecParams {
   uint64_t progress_ticks;     // a worker publishes Ctrl::progress at most this often
   // ready-queue dispatch (kernels k_exec_wave_q / k_exec_block_q)
   uint32_t* q;                 // qshards x qcap ticket slots (kQEmpty when free)
-  uint64_t* qctl;              // per shard, at kQCtlStride u64: tail << 32 | head
-  uint32_t* qfin;              // tasks finished, flushed by idle workers
+  uint32_t* qctl;              // shard s: head at qctl[s * kQLine], tail at
+                               // qctl[(qshards + s) * kQLine]; sinks finished
+                               // at qctl[2 * qshards * kQLine]
   const uint32_t* qsrc;        // positions without in-edges (pushed at reset)
   uint32_t nsrc;
+  uint32_t nsinks;             // positions without out-edges
   uint32_t qshards;            // power of two, 1..8
-  uint32_t qcap;               // slots per shard (the task count)
+  uint32_t qcap;               // slots per shard: the task count plus the exit sentinels
   uint32_t qtile;              // tickets claimed per pop (1..64)
+  uint32_t qsent;              // exit sentinels pushed into every shard at the end
 };
 
 constexpr uint32_t kQEmpty = 0xFFFFFFFFu;
-constexpr uint32_t kQCtlStride = 16;  // u64 words between shard control words (128 bytes)
+constexpr uint32_t kQExit = 0xFFFFFFFEu;  // exit sentinel
+constexpr uint32_t kQLine = 32;           // u32 words between queue control words (128 bytes)
 
 constexpr uint32_t kBellStride = 32;  // u32 words between doorbells (128 bytes)
 // Gang mailbox, kMboxStride u32 per gang: [0] sequence number of the last

@@ -726,146 +726,145 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
 // vertex a COMPLETED_EDGE made ready), without per-worker lists.  The
 // decrement that empties a counter (old value 1) makes its task ready.  A
 // worker keeps the first task its own completion made ready as its next task
-// (so a chain causes no queue traffic) and pushes the others into the
-// ticket queue of its XCD: one ballot of the ready lanes, one atomic add on
-// the shard's tail for all of them, each lane's slot from the count of ready
-// lanes below it.  A worker without work claims up to qtile consecutive
-// tickets of its own shard with one compare-and-swap on the head -- only
-// tickets already taken by pushers, so a claim never waits for a push that
-// may not come -- waits until the claimed slots are written, and runs their
-// tasks one by one; when its shard is empty it tries the others.  Workers
-// count the tasks they ran and add the count to one global word when they
-// find no work; they leave once it reaches the task total.  No worker waits
-// for a particular other worker, so this dispatch needs no co-residency.
-
-__device__ __forceinline__ uint64_t ld_coherent64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// (a chain causes no queue traffic) and pushes the others into one ticket
+// queue shard (shards taken in turn): one ballot of the ready lanes, one
+// atomic add on the shard's tail for all of them, each lane's slot from the
+// count of ready lanes below it.  A worker that needs work claims a tile of
+// consecutive tickets of its own shard with one atomic add on the head --
+// a claim never fails and never retries -- and waits on each claimed slot in
+// turn until a pusher has written it; waiting workers poll distinct slots,
+// so no address is shared by the waiters.
+//
+// Termination needs no per-task counter: every task precedes some sink (a
+// task without out-edges), so the launch is over once every sink has run.
+// Workers count the sinks they finished and add the count to one word only
+// when they find their next slot empty; the addition that completes the sink
+// total pushes qsent exit sentinels into every shard.  A worker claims a new
+// tile only after consuming its previous one, so at most one tile per worker
+// (plus one straddling the last task ticket) reaches past the task tickets
+// of a shard: qsent = tile x (workers of the shard + 1) sentinels fill every
+// ticket ever claimed.  No worker waits for a particular other worker, so
+// this dispatch needs no co-residency.
 
 struct QueueState {
-  uint32_t worker, shard;
-  uint32_t local;   // ready task kept by this worker (kExit: none)
-  uint32_t tile_v;  // per lane: the position in claimed ticket `lane`
-  uint32_t tile_n, tile_i;
-  uint32_t ran;     // tasks run since the last flush to qfin
-  uint32_t spins;
-  uint64_t last, pub;
+  uint32_t worker, shard, pshard;  // claims from `shard`; next push into `pshard`
+  uint32_t local;                  // ready task kept by this worker (kExit: none)
+  uint32_t tile_h, tile_n, tile_i; // claimed tickets [tile_h, tile_h + tile_n), next tile_i
+  uint32_t sinks;                  // sinks finished since the last report
+  uint64_t pub;                    // time this worker last published Ctrl::progress
 };
+
+__device__ __forceinline__ uint32_t* q_head(const ExecParams& P, uint32_t s) { return P.qctl + s * kQLine; }
+__device__ __forceinline__ uint32_t* q_tail(const ExecParams& P, uint32_t s) {
+  return P.qctl + (P.qshards + s) * kQLine;
+}
+__device__ __forceinline__ uint32_t* q_sinks(const ExecParams& P) { return P.qctl + 2u * P.qshards * kQLine; }
 
 // Workgroups are dealt to the 8 XCDs round-robin by workgroup index.
 __device__ __forceinline__ void queue_init(QueueState& q, const ExecParams& P, uint32_t worker) {
   q.worker = worker;
   q.shard = blockIdx.x & 7u & (P.qshards - 1u);
+  q.pshard = q.shard;
   q.local = kExit;
-  q.tile_v = 0;
-  q.tile_n = q.tile_i = 0;
-  q.ran = 0;
-  q.spins = 0;
-  q.last = __builtin_amdgcn_s_memrealtime();
+  q.tile_h = q.tile_n = q.tile_i = 0;
+  q.sinks = 0;
   q.pub = 0;
 }
 
-__device__ __forceinline__ bool queue_idle(const ExecParams& P, QueueState& q, uint32_t lane) {
-  ++q.spins;
-  const uint32_t nap = q.spins < 64 ? 1u : P.idle_sleep;
-  for (uint32_t i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(2);
-  if ((q.spins & 63u) != 0u) return true;
-  if (uni(ld_coherent(&P.ctrl->abort)) != 0u) return false;
-  const uint64_t now = __builtin_amdgcn_s_memrealtime();
-  if (stalled(P, q.last, now) || (P.spin_limit != 0u && q.spins >= P.spin_limit)) {
-    if (lane == 0) {
-      const uint32_t prev = __hip_atomic_fetch_add(&P.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (prev == 0u) {
-        st_coherent(&P.ctrl->stuck_worker, q.worker);
-        st_coherent(&P.ctrl->stuck_pos, kExit);
-        st_coherent(&P.ctrl->stuck_cnt, ld_coherent(P.qfin));
-        st_coherent(&P.ctrl->stuck_h, q.shard);
-        st_coherent(&P.ctrl->stuck_wcnt, P.npos);
-      }
-    }
-    return false;
+// Raises the abort flag; the first abort records where it happened.
+__device__ void queue_abort(const ExecParams& P, const QueueState& q, uint32_t lane, uint32_t ticket) {
+  if (lane != 0) return;
+  const uint32_t prev = __hip_atomic_fetch_add(&P.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (prev == 0u) {
+    st_coherent(&P.ctrl->stuck_worker, q.worker);
+    st_coherent(&P.ctrl->stuck_pos, ticket);
+    st_coherent(&P.ctrl->stuck_cnt, ld_coherent(q_sinks(P)));
+    st_coherent(&P.ctrl->stuck_h, q.shard);
+    st_coherent(&P.ctrl->stuck_wcnt, P.npos);
   }
-  return true;
 }
 
-// Claims a tile of tickets from some shard (own shard first).  Returns
-// false when every shard looked empty (or the launch is being aborted).
-__device__ bool queue_claim(const ExecParams& P, QueueState& q, uint32_t lane) {
-  for (uint32_t i = 0; i < P.qshards; ++i) {
-    const uint32_t s = (q.shard + i) & (P.qshards - 1u);
-    uint64_t* ctl = P.qctl + (size_t)s * kQCtlStride;
-    const uint64_t w = uni64(ld_coherent64(ctl));
-    const uint32_t h = (uint32_t)w, t = (uint32_t)(w >> 32);
-    if (h >= t) continue;
-    const uint32_t k = (t - h) < P.qtile ? (t - h) : P.qtile;
-    uint32_t seen = h;
-    if (lane == 0)
-      __hip_atomic_compare_exchange_strong((uint32_t*)ctl, &seen, h + k, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    if (rl(seen, 0) != h) continue;  // another worker took these tickets
-    // tickets h .. h+k-1 are ours; their pushers have already reserved them
-    const uint32_t* slot = P.q + (size_t)s * P.qcap + h;
-    uint32_t v = kQEmpty;
+// The end of the launch: qsent exit sentinels into every shard.
+__device__ void queue_finish(const ExecParams& P, uint32_t lane) {
+  for (uint32_t s = 0; s < P.qshards; ++s) {
+    uint32_t base = 0;
+    if (lane == 0) base = __hip_atomic_fetch_add(q_tail(P, s), P.qsent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    base = rl(base, 0);
+    uint32_t* slot = P.q + (size_t)s * P.qcap;
+    for (uint32_t i = lane; i < P.qsent; i += 64u)
+      if (base + i < P.qcap) st_coherent(slot + base + i, kQExit);
+  }
+}
+
+// Reports the sinks this worker finished; the report that completes the
+// total ends the launch.
+__device__ __forceinline__ void queue_report(const ExecParams& P, QueueState& q, uint32_t lane) {
+  if (q.sinks == 0u) return;
+  uint32_t old = 0;
+  if (lane == 0) old = __hip_atomic_fetch_add(q_sinks(P), q.sinks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  old = rl(old, 0);
+  const bool last = old + q.sinks == P.nsinks;
+  q.sinks = 0;
+  if (last) queue_finish(P, lane);
+}
+
+__device__ __forceinline__ void queue_progress(const ExecParams& P, QueueState& q, uint32_t lane) {
+  const uint64_t now = __builtin_amdgcn_s_memrealtime();
+  if (now - q.pub < P.progress_ticks) return;
+  q.pub = now;
+  if (lane == 0) __hip_atomic_fetch_max(&P.ctrl->progress, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Position of the worker's next task, or kExit at the end of the launch (or
+// when it is being aborted).  Run by one whole wave.
+__device__ uint32_t queue_next(const ExecParams& P, QueueState& q, uint32_t lane) {
+  if (q.local != kExit) {
+    const uint32_t pos = q.local;
+    q.local = kExit;
+    queue_progress(P, q, lane);
+    return pos;
+  }
+  if (q.tile_i == q.tile_n) {
+    uint32_t h = 0;
+    if (lane == 0) h = __hip_atomic_fetch_add(q_head(P, q.shard), P.qtile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    q.tile_h = rl(h, 0);
+    q.tile_n = P.qtile;
+    q.tile_i = 0;
+  }
+  const uint32_t t = q.tile_h + q.tile_i;
+  if (t >= P.qcap) {  // beyond every sentinel: the protocol's bound was broken
+    queue_abort(P, q, lane, t);
+    return kExit;
+  }
+  const uint32_t* slot = P.q + (size_t)q.shard * P.qcap + t;
+  uint32_t v = uni(ld_coherent(slot));
+  if (v == kQEmpty) {
+    queue_report(P, q, lane);  // nothing to run now: report the finished sinks first
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     for (uint32_t spins = 1;; ++spins) {
-      if (lane < k && v == kQEmpty) v = ld_coherent(slot + lane);
-      if (uni64(__ballot(lane < k && v == kQEmpty)) == 0ull) break;
-      __builtin_amdgcn_s_sleep(1);
-      if ((spins & 1023u) == 0u) {
-        // a pusher stores right after reserving, so this wait is short; it
-        // is bounded all the same
-        if (uni(ld_coherent(&P.ctrl->abort)) != 0u) return false;
-        if (stalled(P, t0, __builtin_amdgcn_s_memrealtime())) {
-          if (lane == 0) __hip_atomic_fetch_add(&P.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          return false;
+      const uint32_t nap = spins < 64 ? 1u : P.idle_sleep;
+      for (uint32_t i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(2);
+      v = uni(ld_coherent(slot));
+      if (v != kQEmpty) break;
+      if ((spins & 63u) == 0u) {
+        if (uni(ld_coherent(&P.ctrl->abort)) != 0u) return kExit;
+        if (stalled(P, t0, __builtin_amdgcn_s_memrealtime()) || (P.spin_limit != 0u && spins >= P.spin_limit)) {
+          queue_abort(P, q, lane, t);
+          return kExit;
         }
       }
     }
-    q.tile_v = v;
-    q.tile_n = k;
-    q.tile_i = 0;
-    return true;
   }
-  return false;
-}
-
-// Position of the worker's next task, or kExit when every task of the
-// launch has finished (or the launch is being aborted).  Run by one wave.
-__device__ uint32_t queue_next(const ExecParams& P, QueueState& q, uint32_t lane) {
-  for (;;) {
-    uint32_t pos = kExit;
-    if (q.local != kExit) {
-      pos = q.local;
-      q.local = kExit;
-    } else if (q.tile_i < q.tile_n) {
-      pos = __builtin_amdgcn_readlane(q.tile_v, q.tile_i);
-      ++q.tile_i;
-    }
-    if (pos != kExit) {
-      q.spins = 0;
-      q.last = __builtin_amdgcn_s_memrealtime();
-      if (q.last - q.pub >= P.progress_ticks) {
-        q.pub = q.last;
-        if (lane == 0) __hip_atomic_fetch_max(&P.ctrl->progress, q.last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      ++q.ran;
-      return pos;
-    }
-    if (queue_claim(P, q, lane)) continue;
-    // no work: report the tasks run so far, leave once all have finished
-    if (q.ran) {
-      if (lane == 0) __hip_atomic_fetch_add(P.qfin, q.ran, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      q.ran = 0;
-    }
-    if (uni(ld_coherent(P.qfin)) >= P.npos) return kExit;
-    if (!queue_idle(P, q, lane)) return kExit;
-  }
+  ++q.tile_i;
+  if (v == kQExit) return kExit;
+  queue_progress(P, q, lane);
+  return v;
 }
 
 // One wave's part of a completion: `ready` marks the lanes whose decrement
 // emptied the counter of `dst`.  The scheduling wave (keep) holds on to the
 // first of them when it has no next task yet; the rest are pushed into the
-// wave's shard with one atomic on its tail.
+// next shard in turn with one atomic on its tail.
 __device__ __forceinline__ void queue_push(const ExecParams& P, QueueState& q, bool keep, uint32_t lane, bool ready,
                                            uint32_t dst) {
   uint64_t m = uni64(__ballot(ready));
@@ -877,16 +876,21 @@ __device__ __forceinline__ void queue_push(const ExecParams& P, QueueState& q, b
     if (lane == first) ready = false;
     if (!m) return;
   }
+  const uint32_t s = q.pshard;
+  q.pshard = (q.pshard + 1u) & (P.qshards - 1u);
   const uint32_t leader = (uint32_t)__builtin_ctzll(m);
   uint32_t base = 0;
-  uint32_t* tail = (uint32_t*)(P.qctl + (size_t)q.shard * kQCtlStride) + 1;
-  if (lane == leader) base = __hip_atomic_fetch_add(tail, (uint32_t)__builtin_popcountll(m), __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == leader)
+    base = __hip_atomic_fetch_add(q_tail(P, s), (uint32_t)__builtin_popcountll(m), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
   base = __builtin_amdgcn_readlane(base, leader);
   if (ready) {
-    const uint32_t below = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1ull));
-    st_coherent(P.q + (size_t)q.shard * P.qcap + base + below, dst);
+    const uint32_t idx = base + (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1ull));
+    if (idx < P.qcap) st_coherent(P.q + (size_t)s * P.qcap + idx, dst);
   }
+  // a shard holds at most every task once plus the sentinels, so a full
+  // shard means a broken protocol: stop the launch rather than lose a task
+  if (base + (uint32_t)__builtin_popcountll(m) > P.qcap) queue_abort(P, q, lane, base);
 }
 
 // COMPLETED_EDGE for every out-edge, then the pushes (one per wave with
@@ -923,6 +927,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     if (pos == kExit) break;
     Rec r;
     run_task(tm, P, pos, rec_dword(P, pos, lane), r);
+    if (r.nsucc == 0u) ++q.sinks;
     complete_edges_q(tm, P, r, q, true);
     if (P.tstamp && lane == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
   }
@@ -955,6 +960,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     if (pos == kExit) break;
     Rec r;
     run_task(tm, P, pos, v, r);
+    if (threadIdx.x < 64 && r.nsucc == 0u) ++q.sinks;
     complete_edges_q(tm, P, r, q, threadIdx.x < 64);
     if (P.tstamp && threadIdx.x == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
     __syncthreads();
@@ -966,23 +972,23 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
 __global__ __launch_bounds__(256) void k_queue_clear(ExecParams P) {
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t s = 0; s < P.qshards; ++s) {
-    uint32_t t = (uint32_t)(P.qctl[(size_t)s * kQCtlStride] >> 32);
+    uint32_t t = *q_tail(P, s);
     if (t > P.qcap) t = P.qcap;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < t; i += stride) P.q[(size_t)s * P.qcap + i] = kQEmpty;
   }
 }
 
-// Sources dealt round-robin over the shards; heads, tails and the finished
-// count reset.
+// Sources dealt round-robin over the shards; heads, tails and the sink count
+// reset.
 __global__ __launch_bounds__(256) void k_queue_seed(ExecParams P) {
   const uint32_t stride = gridDim.x * blockDim.x;
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   for (uint32_t i = gid; i < P.nsrc; i += stride) P.q[(size_t)(i % P.qshards) * P.qcap + i / P.qshards] = P.qsrc[i];
   if (gid < P.qshards) {
-    const uint64_t cnt = (P.nsrc + P.qshards - 1u - gid) / P.qshards;
-    P.qctl[(size_t)gid * kQCtlStride] = cnt << 32;
+    *q_head(P, gid) = 0u;
+    *q_tail(P, gid) = (P.nsrc + P.qshards - 1u - gid) / P.qshards;
   }
-  if (gid == 0) *P.qfin = 0u;
+  if (gid == 0) *q_sinks(P) = 0u;
 }
 
 // Residency probes: the executors' launch bounds and occupancy attributes

@@ -1,8 +1,10 @@
 """The ready-queue dispatch's protocol on the CPU model (tg_emulate_queue):
 every task runs exactly once and after all the edges the executor's
-counters follow, every worker leaves, for any number of workers, shards and
-ticket tile sizes, over single graphs, graphs with anti-dependence edges and
-batches of graphs."""
+counters follow, no ticket lies beyond a shard's capacity, every sink is
+reported and every worker leaves (on an exit sentinel), for any number of
+workers, shards and ticket tile sizes -- including fewer workgroups than
+shards -- over single graphs, graphs with anti-dependence edges and batches
+of graphs."""
 import numpy as np
 import pytest
 
@@ -29,7 +31,8 @@ def _check(graphs, nworkers, shards, tile, seed):
 
 
 @pytest.mark.parametrize("pattern", wl.PATTERNS)
-@pytest.mark.parametrize("nworkers,shards,tile", [(1, 1, 1), (3, 2, 1), (16, 8, 1), (16, 8, 4), (64, 4, 64)])
+@pytest.mark.parametrize("nworkers,shards,tile", [(1, 1, 1), (3, 2, 1), (16, 8, 1), (16, 8, 4), (64, 4, 64),
+                                                  (5, 8, 64), (37, 8, 3)])
 def test_patterns(tglib, pattern, nworkers, shards, tile):
     eg = wl.pattern_graph(pattern, 23, 9, seed=1, n=64)
     g = tg.graph_from_explicit(eg)
