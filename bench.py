@@ -126,22 +126,43 @@ def timed_execs(tg, g, cfg, stream, reps):
     return float(np.mean(tg.tg_graph_kernel_times(g.handle, reps)))
 
 
-# launch shapes timed for each graph alone (the best one is kept)
+# launch shapes timed for each graph alone at R = 0 (the best one is kept),
+# and the ready-queue dispatch beside them
 def alone_shapes(tg):
-    return [("wavefronts x resident, column", tg.make_config(mapping=1, schedule=tg.TG_SCHED_COLUMN)),
-            ("wavefronts x resident, level", tg.make_config(mapping=1, schedule=tg.TG_SCHED_LEVEL)),
-            ("wavefronts x 1024, level", tg.make_config(mapping=1, workers=1024, schedule=tg.TG_SCHED_LEVEL))]
+    return [("lists: wavefronts x resident, column", tg.make_config(mapping=1, schedule=tg.TG_SCHED_COLUMN)),
+            ("lists: wavefronts x resident, level", tg.make_config(mapping=1, schedule=tg.TG_SCHED_LEVEL)),
+            ("lists: wavefronts x 1024, level", tg.make_config(mapping=1, workers=1024, schedule=tg.TG_SCHED_LEVEL))]
+
+
+def queue_shape(tg):
+    return ("queue: wavefronts x 2048, tile 1", tg.make_config(mapping=1, workers=2048, dispatch=tg.TG_DISPATCH_QUEUE,
+                                                               tile=1))
+
+
+# shapes of the mix-round sweep (the faster one at each R is kept): one
+# wavefront or one 4-wave workgroup per task, as many workers as tasks can be
+# ready at once (the width; every task of the dependence-free graph)
+def sweep_shapes(tg, dependent):
+    w = 1024 if dependent else 0
+    return [("lists: wavefronts, level", tg.make_config(mapping=1, workers=w, schedule=tg.TG_SCHED_LEVEL)),
+            ("lists: 4-wave workgroups, level", tg.make_config(mapping=2, wg_waves=4, workers=w,
+                                                               schedule=tg.TG_SCHED_LEVEL))]
 
 
 def leg_patterns(tg, wl, egs, gs, probes, stream):
     """Each C2 graph alone: best of three launch shapes at R = 0 (tasks/s,
-    HBM and latency fractions, per-task overhead), then its own mix-round
-    sweep in that shape (efficiency against the measured mix rate) and
-    METG(50)."""
+    HBM and latency fractions, per-task overhead) and the ready-queue
+    dispatch beside it, then its own mix-round sweep (the faster of two
+    shapes at each R; efficiency against the measured mix rate) and
+    METG(50).  Task slots (for granularity and per-task overhead) are the
+    workers a launch runs, capped at the tasks that can be ready at once:
+    the width W for the dependent patterns, every task without them."""
     pi = probes["mix_word_rounds_per_s"]
     hop_ns = probes.get("handoff_ns")
     out = {}
     for p, eg, g in zip(wl.PATTERNS, egs, gs):
+        dependent = p != "none"
+        conc = W if dependent else eg.N
         best = None
         for name, cfg in alone_shapes(tg):
             ms = timed_execs(tg, g, cfg, stream, 3)
@@ -149,30 +170,43 @@ def leg_patterns(tg, wl, egs, gs, probes, stream):
             if best is None or ms < best[1]:
                 best = (name, ms, cfg, workers)
         name, ms, cfg, workers = best
-        levels = T if p != "none" else 1
-        rec = {"launch": name, "workers": workers, "kernel_ms": ms, "tasks_per_s": eg.N / (ms * 1e-3),
-               "algorithmic_bytes": algorithmic_bytes(eg),
+        qname, qcfg = queue_shape(tg)
+        qms = timed_execs(tg, g, qcfg, stream, 3)
+        slots = min(workers, conc)
+        levels = T if dependent else 1
+        rec = {"launch": name, "workers": workers, "task_slots": slots, "kernel_ms": ms,
+               "tasks_per_s": eg.N / (ms * 1e-3), "algorithmic_bytes": algorithmic_bytes(eg),
                "hbm_frac": algorithmic_bytes(eg) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
                "edges": eg.E, "levels": levels,
-               "per_task_overhead_ns": ms * 1e6 * workers / eg.N,
-               "throughput_ns_per_task": ms * 1e6 / eg.N}
+               "per_task_overhead_ns": ms * 1e6 * slots / eg.N,
+               "throughput_ns_per_task": ms * 1e6 / eg.N,
+               "queue": {"launch": qname, "kernel_ms": qms, "lists_over_queue": ms / qms}}
         if hop_ns:
             rec["latency_floor_ms"] = levels * hop_ns * 1e-6
             rec["latency_frac"] = levels * hop_ns * 1e-6 / ms
         rows = []
         for R in SWEEP_ROUNDS:
             tg.tg_graph_set_rounds(g.handle, R)
-            rms = timed_execs(tg, g, cfg, stream, 2 if R >= 1024 else 3) if R else ms
+            if R == 0:
+                rows.append({"rounds": 0, "ms": ms, "efficiency": 0.0, "granularity_us": ms * 1e3 * slots / eg.N,
+                             "launch": name})
+                continue
+            cand = []
+            for sname, scfg in sweep_shapes(tg, dependent):
+                sms = timed_execs(tg, g, scfg, stream, 2 if R >= 1024 else 3)
+                sw, _ = tg.tg_graph_exec_info(g.handle)
+                cand.append((sms, sname, min(sw, conc)))
+            rms, sname, sslots = min(cand)
             U = eg.N * eg.n * R
-            rows.append({"rounds": R, "ms": rms, "efficiency": (U / (rms * 1e-3)) / pi if R else 0.0,
-                         "granularity_us": rms * 1e3 * workers / eg.N})
+            rows.append({"rounds": R, "ms": rms, "efficiency": (U / (rms * 1e-3)) / pi,
+                         "granularity_us": rms * 1e3 * sslots / eg.N, "launch": sname})
         tg.tg_graph_set_rounds(g.handle, 0)
         rec["sweep"] = rows
         rec["metg50_us"] = metg50([r["granularity_us"] for r in rows if r["rounds"]],
                                   [r["efficiency"] for r in rows if r["rounds"]])
         out[p] = rec
         log(f"alone {p}: {ms:.3f} ms ({name}), {rec['tasks_per_s'] / 1e6:.0f} M tasks/s, hbm {rec['hbm_frac']:.3f}, "
-            f"latency frac {rec.get('latency_frac', 0):.3f}, METG(50) {rec['metg50_us']}")
+            f"latency frac {rec.get('latency_frac', 0):.3f}, queue {qms:.3f} ms, METG(50) {rec['metg50_us']}")
     return out
 
 
@@ -246,6 +280,9 @@ def main():
     ap.add_argument("--requests", type=int, default=4000, help="serving: measured requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: arrivals per second")
     ap.add_argument("--slots", type=int, default=4, help="serving: launch slots (streams) of the server, 1..4")
+    ap.add_argument("--max-batch", type=int, default=64, help="serving: most requests per launch")
+    ap.add_argument("--server-dispatch", default="queue", choices=["queue", "lists"],
+                    help="serving: ready queue with device-built records (default) or host-planned lists")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the executor runs on one GPU only (it is single-device); use --gpus 1",
@@ -335,6 +372,23 @@ def main():
     achieved_gbs = bytes_per_step / (kernel_ms_per_step * 1e-3) / 1e9
     log(f"step {ms_per_step:.3f} ms (wall {wall * 1e3 / args.steps:.3f} ms); kernel {kernel_ms_per_step:.3f} ms")
     leg_s["step"] = time.time() - t0
+
+    # the same step with the ready-queue dispatch (timing only; the parity of
+    # that dispatch is in the test-suite)
+    step_queue = None
+    if "patterns" not in skip:
+        qb = tg.tg_batch_create([g.handle for g in gs], tg.make_config(mapping=1, workers=4096,
+                                                                         dispatch=tg.TG_DISPATCH_QUEUE, tile=1))
+        tg.tg_batch_execute(qb, stream)
+        tg.tg_batch_wait(qb)
+        for _ in range(3):
+            tg.tg_batch_execute(qb, stream)
+        tg.tg_batch_wait(qb)
+        step_queue = {"launch": "queue: wavefronts x 4096, tile 1",
+                      "kernel_ms": float(np.mean(tg.tg_batch_kernel_times(qb, 3))),
+                      "lists_kernel_ms": kernel_ms_per_step}
+        tg.tg_batch_destroy(qb)
+        log(f"step with the ready queue: {step_queue['kernel_ms']:.3f} ms")
 
     # -------------------------------------------- oracle: parity and baseline
     parity = None
@@ -511,6 +565,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "patterns": patterns,
+        "step_with_queue": step_queue,
         "rounds_sweep": sweep,
         "small_stencil": small,
         "comparators": comps,

@@ -23,10 +23,13 @@ from paper_2508_16522_amd import workloads as wl
 
 METRIC = "tasks/sec + per-task overhead (ns) + min effective task granularity, 1 GPU"
 ROOT = os.path.dirname(os.path.abspath(__file__))
-# integer-VALU peak of the task body: 256 CUs x 64 lanes x 2.4 GHz, 8 VALU
-# instructions per word-round (3 shifts, 3 xors, one 32-bit multiply, one
-# add in the compiled loop)
-ALU_PEAK_WORD_ROUNDS = 256 * 64 * 2.4e9 / 8
+# integer-VALU peak of the task body from the unit counts: the published
+# fp32 vector peak (157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 lanes x 2 flops
+# per fused multiply-add) gives 128 32-bit lanes per clock per CU; the
+# compiled mix is 8 VALU instructions per word-round (3 shifts, 3 xors, one
+# 32-bit multiply, one add), so 256 x 2.4e9 x 128 / 8 word-rounds/s.  (64
+# lanes per clock would give half this, which the measured mix rate exceeds.)
+ALU_PEAK_WORD_ROUNDS = 256 * 2.4e9 * 128 / 8
 
 
 def log(msg):
@@ -104,6 +107,7 @@ def run_implicit(args, stream, probes=None):
 # ------------------------------------------------------------------ batch
 
 BATCH_CFG = dict(mapping=1, workers=4096, schedule=tg.TG_SCHED_BALANCED)
+BATCH_QUEUE_CFG = dict(mapping=1, dispatch=tg.TG_DISPATCH_QUEUE, tile=1)
 # oracle cost cap of the parity sample, in word-rounds (about 5 s per graph
 # on one core)
 BATCH_COST_CAP = 1.5e9
@@ -186,6 +190,15 @@ def run_batch(args, stream, probes=None):
     ms = float(np.mean(kt))
     log(f"batch: one launch {ms:.1f} ms")
     tg.tg_batch_destroy(b)
+    # the same graphs with the ready-queue dispatch (timing only)
+    qb = tg.tg_batch_create([g.handle for g in gs], tg.make_config(**BATCH_QUEUE_CFG))
+    tg.tg_batch_execute(qb, stream)
+    tg.tg_batch_wait(qb)
+    tg.tg_batch_execute(qb, stream)
+    tg.tg_batch_wait(qb)
+    qms = float(np.mean(tg.tg_batch_kernel_times(qb, 1)))
+    tg.tg_batch_destroy(qb)
+    log(f"batch: one launch with the ready queue {qms:.1f} ms")
     # parity: stratified sample against the oracle in parallel processes
     sample = stratified_batch_sample(specs)
     tp = time.perf_counter()
@@ -228,6 +241,7 @@ def run_batch(args, stream, probes=None):
         "frac_of_measured_mix_rate": U / (ms * 1e-3) / probes["mix_word_rounds_per_s"] if probes else None,
         "frac_of_alu_peak": U / (ms * 1e-3) / ALU_PEAK_WORD_ROUNDS,
         "payload_bytes": payload_bytes, "host_build_s": build_s, "layout_s": layout_s, "layout_ms": btimes,
+        "queue": {"launch": "queue: wavefronts x resident, tile 1", "exec_ms": qms, "lists_over_queue": ms / qms},
         "parity": {"ok": not bad, "graphs": len(sample), "failed": bad, "oracle_processes": workers,
                    "sample": "per (pattern, payload) cell the highest-R graph and one random graph, plus the 14 "
                              f"highest-R graphs, all under {BATCH_COST_CAP:.1e} word-rounds (seed 7)"},
@@ -259,7 +273,9 @@ def run_serving(args, stream, probes=None):
         handles.append(tg.graph_from_implicit(x) if isinstance(x, wl.ImplicitGraph) else tg.graph_from_explicit(x))
         if i % 1000 == 0:
             log(f"serving: built {i} requests, {time.perf_counter() - t0:.0f} s")
-    srv = tg.tg_server_create(64 << 30, slots=args.slots, max_batch=64)
+    srv = tg.tg_server_create(64 << 30, slots=args.slots, max_batch=args.max_batch)
+    if getattr(args, "server_dispatch", "queue") == "lists":
+        tg.tg_server_configure(srv, tg.make_config(dispatch=tg.TG_DISPATCH_LISTS))
     tickets = [None] * len(reqs)
 
     def client():
@@ -273,11 +289,13 @@ def run_serving(args, stream, probes=None):
     th = threading.Thread(target=client)
     th.start()
     th.join()
-    lat, done = [], []
+    lat, wait, serv, done = [], [], [], []
     for i, t in enumerate(tickets):
         s_ns, a_ns, d_ns = tg.tg_server_wait(srv, t)
         if i >= warm:
             lat.append((d_ns - s_ns) * 1e-6)
+            wait.append((a_ns - s_ns) * 1e-6)
+            serv.append((d_ns - a_ns) * 1e-6)
             done.append((s_ns, d_ns, graphs[i].N))
     stats = tg.tg_server_stats(srv)
     tg.tg_server_destroy(srv)
@@ -303,6 +321,11 @@ def run_serving(args, stream, probes=None):
         "tasks": tasks, "span_s": span_s, "tasks_per_s": tasks / span_s,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
+        # submission to admission (waiting for a slot and memory), and
+        # admission to completion (layout, launch, the graph's own execution)
+        "admission_wait_ms": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
+        "service_ms": {"p50": float(np.percentile(serv, 50)), "p99": float(np.percentile(serv, 99))},
+        "server_config": getattr(args, "server_dispatch", "queue"),
         "offered_req_per_s": args.rate, "server": stats,
         "parity": {"ok": not bad, "requests": len(pick), "failed": bad,
                    "sample": "64 requests drawn with seed 1 from all submitted"},

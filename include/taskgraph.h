@@ -459,6 +459,18 @@ tg_status tg_probe(uint32_t kind, double* value);
  * and tg_graph_checksum keep working) and its device memory is released.
  * A request larger than the whole budget fails with TG_ENOMEM. */
 tg_status tg_server_create(tg_server* out, uint64_t budget_bytes, uint32_t slots, uint32_t max_batch);
+/* Launch configuration of the batches a server issues from now on (Section
+ * 4.1: compiled graphs issued dynamically).  Default: TG_DISPATCH_QUEUE with
+ * one wavefront per task, tile 1, 8 shards and the co-resident workers
+ * divided over the slots.  With the ready queue a batch needs no host
+ * schedule: each graph's compiled form (its predecessor and successor
+ * lists, counter reset values, rounds, requirements and sources, packed at
+ * finalize) is uploaded once when the graph is admitted, and one device
+ * kernel builds the batch's task records from them; the slot keeps its
+ * buffers for the next batch.  TG_DISPATCH_LISTS plans per-worker lists and
+ * builds the records on the host for every batch (mapping, workers,
+ * schedule and window apply).  Gangs are refused (TG_EINVAL). */
+tg_status tg_server_configure(tg_server srv, const tg_exec_config* cfg);
 /* Non-blocking.  g must be compiled (finalised) and not executing; the caller
  * keeps ownership and must not touch g until the ticket is waited for.  A
  * graph whose request has not finished cannot be submitted again: TG_EBUSY. */

@@ -135,6 +135,17 @@ struct DevBuf {
   }
   template <class T>
   T* as() const { return (T*)p; }
+  // Takes over o's memory (o is left empty).
+  void take(DevBuf& o) {
+    release();
+    p = o.p;
+    bytes = o.bytes;
+    fa = o.fa;
+    ff = o.ff;
+    ctx = o.ctx;
+    o.p = nullptr;
+    o.bytes = 0;
+  }
 };
 
 // Host-to-device copies and memsets here run on the NULL stream (except the
@@ -251,9 +262,20 @@ static void ledger_forget(const void* key);
 struct Layout {
   Config cfg;
   uint32_t nworkers = 0, grid_blocks = 0, npos = 0, last_started = 0;
-  DevBuf rec, pred_addr, succ_pos, indeg, cnt, wbase, gtab, reqs, ctrl, execs, wprog, owner, bell, tstamp, wstamp, mbox;
+  DevBuf rec, pred_addr, succ_pos, indeg, cnt, wbase, gtab, ctrl, execs, wprog, owner, bell, tstamp, wstamp, mbox;
   DevBuf q, qctl, qsrc;  // ready-queue dispatch
   uint32_t qwmax = 0;    // most workers claiming from one queue shard
+  // layouts built on the device (build_layout_device): the graph tables, the
+  // graphs' blobs (staged in pinned host memory, one copy per launch), and
+  // per-graph completion (sink counts on the device, flags in host memory)
+  DevBuf gsrc, blobs, gdone;
+  std::vector<GraphEnt> gtab_host;
+  std::vector<tg::GraphSrc> gsrc_host;
+  uint32_t* pin = nullptr;
+  size_t pin_bytes = 0;
+  uint32_t* gflag = nullptr;  // pinned, device-visible
+  size_t gflag_n = 0;
+  uint32_t gseq = 0;
   std::vector<std::vector<uint32_t>> pos_of;  // per graph: task id -> position
   std::vector<TaskRec> rec_host;               // host copy (rounds can be re-set)
   ExecParams params{};
@@ -269,6 +291,8 @@ struct Layout {
   ~Layout() {
     ledger_forget(this);
     if (ev_done) (void)hipEventDestroy(ev_done);
+    if (pin) (void)hipHostFree(pin);
+    if (gflag) (void)hipHostFree(gflag);
   }
 };
 
@@ -326,7 +350,19 @@ struct tg_graph_s {
   std::vector<uint32_t> topo;
   std::vector<uint32_t> xindeg;      // in-degree over the executed edges (counter reset values)
   std::vector<uint32_t> rw_base;  // implicit: per requirement, ordinal of its first written element
-  DevBuf payload, data, digest;
+  // The compiled graph in one block of u32 words (built on the host at
+  // finalize, uploaded once to `dblob` when the graph first runs): what a
+  // launch needs to build task records on the device, and the implicit
+  // requirements the records point into (section offsets in words).
+  struct BlobOff {
+    uint64_t pred_ptr = 0, preds = 0, succ_ptr = 0, succ = 0, indeg = 0, rounds = 0, slot = 0, req_ptr = 0,
+             reqs = 0, src = 0, words = 0;
+    uint32_t nsrc = 0, nsinks = 0;
+    bool has_slot = false;
+  } bo;
+  std::vector<uint32_t> blob;
+  uint64_t blob_gen = 0, dblob_gen = ~0ull;  // host version; version on the device
+  DevBuf payload, data, digest, dblob;
   std::unique_ptr<Layout> solo;
   std::shared_ptr<PlanCache> plans;  // schedules of this graph alone, by (workers, schedule)
   // execution state
@@ -435,7 +471,6 @@ struct HostLayout {
   std::vector<uint32_t> succ_pos;
   std::vector<uint32_t> indeg;
   std::vector<GraphEnt> gtab;
-  std::vector<ReqDev> reqs;
   std::vector<std::vector<uint32_t>> pos_of;
 };
 
@@ -784,6 +819,20 @@ tg_status schedule_list(const std::vector<tg_graph>& gs, uint32_t N, uint32_t nw
 // order it is to run them.
 // A schedule: per-worker list lengths and, worker by worker, the tasks of
 // each list in order as (graph << 32) | id.
+uint64_t req_addr(tg_graph g, uint32_t v);
+
+// Per-graph constants of the graph table.
+void graph_entry(tg_graph g, GraphEnt& e) {
+  memset(&e, 0, sizeof(e));
+  e.key1 = sm64_host(g->seed ^ (1ull << 32));
+  e.key2 = sm64_host(g->seed ^ (2ull << 32));
+  e.digest = g->digest.as<uint32_t>();
+  e.data = g->data.as<uint32_t>();
+  e.n = g->n;
+  e.mode = g->mode;
+  e.nsinks = g->bo.nsinks;
+}
+
 struct Plan {
   std::vector<uint32_t> wlen;
   std::vector<uint64_t> seq;
@@ -839,14 +888,6 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
   H.pred_addr.resize(npred_tot);
   H.succ_pos.resize(nsucc_tot);
   H.indeg.resize(N);
-  std::vector<uint64_t> req_base(gs.size(), 0);
-  {
-    uint64_t rb = 0;
-    for (uint32_t gi = 0; gi < gs.size(); ++gi) {
-      req_base[gi] = rb;
-      if (gs[gi]->mode == TG_IMPLICIT) rb += gs[gi]->reqs.size();
-    }
-  }
   // records in graph order (each graph's arrays are read sequentially); a
   // record is stored at its task's position, and its predecessor and
   // successor lists are slices of pred_addr / succ_pos in graph order.
@@ -890,7 +931,7 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
             H.pred_addr[pb + j] = addr;
           }
         } else {
-          r.out = req_base[gi] + g->req_ptr[v];
+          r.out = req_addr(g, v);
           r.nreq = (uint32_t)(g->req_ptr[v + 1] - g->req_ptr[v]);
         }
         const uint64_t s0 = g->succ_ptr[v], s1 = g->succ_ptr[v + 1];
@@ -918,29 +959,7 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
     for (auto& th : pool) th.join();
   }
   H.gtab.assign(gs.size(), GraphEnt());
-  H.reqs.clear();
-  H.reqs.reserve(nreq_tot);
-  for (uint32_t gi = 0; gi < gs.size(); ++gi) {
-    const tg_graph g = gs[gi];
-    GraphEnt& e = H.gtab[gi];
-    memset(&e, 0, sizeof(e));
-    e.key1 = sm64_host(g->seed ^ (1ull << 32));
-    e.key2 = sm64_host(g->seed ^ (2ull << 32));
-    e.digest = g->digest.as<uint32_t>();
-    e.data = g->data.as<uint32_t>();
-    e.n = g->n;
-    e.mode = g->mode;
-    if (g->mode == TG_IMPLICIT)
-      for (size_t i = 0; i < g->reqs.size(); ++i) {
-        ReqDev q;
-        memset(&q, 0, sizeof(q));
-        q.lo = g->reqs[i].lo;
-        q.hi = g->reqs[i].hi;
-        q.priv = g->reqs[i].priv;
-        q.rw_base = g->rw_base[i];
-        H.reqs.push_back(q);
-      }
-  }
+  for (uint32_t gi = 0; gi < gs.size(); ++gi) graph_entry(gs[gi], H.gtab[gi]);
   return TG_OK;
 }
 
@@ -967,7 +986,7 @@ uint32_t queue_shards(const Config& cfg, uint32_t nw) {
   return s;
 }
 
-tg_status ensure_device(tg_graph g);
+tg_status ensure_device(tg_graph g, bool upload_blob = true);
 tg_status ensure_events(tg_graph g);
 
 // Schedule and upload the layout of a set of finalised graphs.
@@ -1052,7 +1071,6 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   if ((s = L->cnt.alloc((size_t)N * 4)) != TG_OK) return s;
   if ((s = upload(L->wbase, H.wbase)) != TG_OK) return s;
   if ((s = upload(L->gtab, H.gtab)) != TG_OK) return s;
-  if ((s = upload(L->reqs, H.reqs)) != TG_OK) return s;
   if ((s = L->ctrl.alloc(sizeof(tg::Ctrl))) != TG_OK) return s;
   HIPCHK(hipMemset(L->ctrl.p, 0, sizeof(tg::Ctrl)));
   {
@@ -1071,7 +1089,6 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   P.cnt = L->cnt.as<uint32_t>();
   P.wbase = L->wbase.as<uint32_t>();
   P.gtab = L->gtab.as<GraphEnt>();
-  P.reqs = L->reqs.as<ReqDev>();
   P.ctrl = L->ctrl.as<tg::Ctrl>();
   P.owner = L->owner.as<uint32_t>();
   P.bell = L->bell.as<uint32_t>();
@@ -1114,6 +1131,209 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   L->plan_ms = plan_ms;
   L->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_build).count();
   out = std::move(L);
+  return TG_OK;
+}
+
+// Grows a reusable device buffer to at least `bytes` (by half again, so a
+// serving slot reallocates rarely); returns true in *grown when it did.
+tg_status grow(DevBuf& b, size_t bytes, bool* grown = nullptr) {
+  if (grown) *grown = false;
+  if (b.p && b.bytes >= bytes) return TG_OK;
+  if (grown) *grown = true;
+  return b.alloc(std::max(bytes, b.bytes + b.bytes / 2));
+}
+
+// A ready-queue layout whose task records are built on the device from the
+// graphs' compiled blobs (k_build_records), for launches that cannot afford
+// host planning (serving): the host work is one table entry per graph.
+// Positions follow graph order, task ids ascending.  L is reused from launch
+// to launch on one stream: its buffers only grow, and the queue slots the
+// previous launch filled are emptied first.  Every step runs on `st`.
+// Pinned host memory of at least `bytes`, kept and grown (by half again);
+// `coherent` asks for fine-grained memory that device stores reach while a
+// kernel runs.
+tg_status grow_pinned(uint32_t*& p, size_t& have, size_t bytes, bool coherent = false) {
+  if (p && have >= bytes) return TG_OK;
+  const size_t want = std::max(bytes, have + have / 2);
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  have = 0;
+  HIPCHK(hipHostMalloc((void**)&p, want, coherent ? (hipHostMallocCoherent | hipHostMallocMapped) : hipHostMallocDefault));
+  have = want;
+  return TG_OK;
+}
+
+tg_status build_layout_device(const std::vector<tg_graph>& gs, const Config& cfg, Layout& L, hipStream_t st,
+                              bool report) {
+  const auto t_build = std::chrono::steady_clock::now();
+  tg_status s = check_config(cfg);
+  if (s != TG_OK) return s;
+  if (cfg.dispatch != TG_DISPATCH_QUEUE || cfg.mapping == TG_MAP_GANG)
+    return fail(TG_EINVAL, "device-built layouts use the ready queue with wavefront or workgroup workers");
+  {
+    // the graphs' buffers are cleared and their blobs uploaded on `st` too
+    const hipStream_t prev = t_copy_stream;
+    t_copy_stream = st;
+    for (auto g : gs)
+      if ((s = ensure_device(g, false)) != TG_OK) break;
+    t_copy_stream = prev;
+    if (s != TG_OK) return s;
+  }
+  // the graphs' blobs, packed one after the other (256-byte aligned) into
+  // the pinned staging buffer and copied to the device arena in one go; the
+  // staging buffer is free again once this layout's previous launch, which
+  // is ordered after its copy, has finished
+  std::vector<uint64_t> boff(gs.size(), 0);
+  uint64_t bwords = 0;
+  for (size_t gi = 0; gi < gs.size(); ++gi) {
+    boff[gi] = bwords;
+    bwords += (gs[gi]->blob.size() + 63) & ~63ull;
+  }
+  if ((s = grow_pinned(L.pin, L.pin_bytes, std::max<uint64_t>(bwords, 64) * 4)) != TG_OK) return s;
+  if ((s = grow(L.blobs, std::max<uint64_t>(bwords, 64) * 4)) != TG_OK) return s;
+  {
+    const uint64_t t0 = steady_ns();
+    for (size_t gi = 0; gi < gs.size(); ++gi)
+      if (!gs[gi]->blob.empty()) memcpy(L.pin + boff[gi], gs[gi]->blob.data(), gs[gi]->blob.size() * 4);
+    if (bwords) HIPCHK(hipMemcpyAsync(L.blobs.p, L.pin, bwords * 4, hipMemcpyHostToDevice, st));
+    t_copy_ns += steady_ns() - t0;
+  }
+  uint32_t cap32 = 0;
+  if ((s = resident_workers(cfg.mapping, cfg.wg_waves, &cap32)) != TG_OK) return s;
+  uint32_t nw = cfg.workers ? std::min(cfg.workers, cap32) : cap32;
+  const uint32_t G = (uint32_t)gs.size();
+  L.gtab_host.assign(G, GraphEnt());
+  L.gsrc_host.assign(G, tg::GraphSrc());
+  uint64_t N = 0, Pn = 0, E = 0, nsrc = 0, nsinks = 0;
+  for (uint32_t gi = 0; gi < G; ++gi) {
+    const tg_graph g = gs[gi];
+    graph_entry(g, L.gtab_host[gi]);
+    tg::GraphSrc& t = L.gsrc_host[gi];
+    memset(&t, 0, sizeof(t));
+    const uint32_t* b = L.blobs.as<uint32_t>() + boff[gi];
+    const tg_graph_s::BlobOff& o = g->bo;
+    const bool expl = g->mode == TG_EXPLICIT;
+    t.pred_ptr = expl ? b + o.pred_ptr : nullptr;
+    t.preds = expl ? b + o.preds : nullptr;
+    t.succ_ptr = b + o.succ_ptr;
+    t.succ = b + o.succ;
+    t.indeg = b + o.indeg;
+    t.rounds = b + o.rounds;
+    t.slot = o.has_slot ? b + o.slot : nullptr;
+    t.req_ptr = expl ? nullptr : b + o.req_ptr;
+    t.reqs = expl ? nullptr : (const ReqDev*)(b + o.reqs);
+    t.src = b + o.src;
+    t.payload = (uint64_t)g->payload.p;
+    t.pos_base = (uint32_t)N;
+    t.pred_base = (uint32_t)Pn;
+    t.succ_base = (uint32_t)E;
+    t.src_base = (uint32_t)nsrc;
+    t.n = g->n;
+    t.mode = g->mode;
+    N += g->N();
+    Pn += expl ? g->dpred.size() : 0;
+    E += g->succ.size();
+    nsrc += o.nsrc;
+    nsinks += o.nsinks;
+  }
+  if (N >= 0xFFFFFFF0ull || Pn >= 0xFFFFFFFFull || E >= 0xFFFFFFFFull)
+    return fail(TG_EINVAL, "layout too large: %llu tasks, %llu edges", (unsigned long long)N, (unsigned long long)E);
+  if (nw > N) nw = N ? (uint32_t)N : 1;
+  const uint32_t shards = queue_shards(cfg, nw);
+  const uint32_t qwmax = queue_workers_per_shard(cfg, nw, shards);
+  const uint64_t cap = N + 64ull * (qwmax + 1);
+  // The queue slots the previous launch on this layout filled are emptied
+  // (with that launch's geometry) only when the queue buffer is kept: a
+  // buffer about to be replaced goes back to the allocator at once, which
+  // does not know about work still queued on `st`, so no kernel may be
+  // queued against it; its replacement is filled afresh.
+  if (L.q.p && L.params.q && L.q.bytes >= (size_t)shards * cap * 4) HIPCHK(tg::launch_queue_clear(L.params, st));
+  bool grown = false;
+  if ((s = grow(L.rec, N * sizeof(TaskRec))) != TG_OK) return s;
+  if ((s = grow(L.pred_addr, Pn * 8)) != TG_OK) return s;
+  if ((s = grow(L.succ_pos, E * 4)) != TG_OK) return s;
+  if ((s = grow(L.indeg, N * 4)) != TG_OK) return s;
+  if ((s = grow(L.cnt, N * 4)) != TG_OK) return s;
+  if ((s = grow(L.gtab, G * sizeof(GraphEnt))) != TG_OK) return s;
+  if ((s = grow(L.gsrc, G * sizeof(tg::GraphSrc))) != TG_OK) return s;
+  if ((s = grow(L.qsrc, nsrc * 4)) != TG_OK) return s;
+  if ((s = grow(L.bell, (size_t)nw * tg::kBellStride * 4)) != TG_OK) return s;
+  if ((s = grow(L.ctrl, sizeof(tg::Ctrl), &grown)) != TG_OK) return s;
+  if (grown) HIPCHK(tg::launch_fill(L.ctrl.as<uint32_t>(), sizeof(tg::Ctrl) / 4, 0, st));
+  if ((s = grow(L.q, (size_t)shards * cap * 4, &grown)) != TG_OK) return s;
+  if (grown) HIPCHK(tg::launch_fill(L.q.as<uint32_t>(), L.q.bytes / 4, tg::kQEmpty, st));
+  const size_t ctl_words = (size_t)(2 * 8 + 1) * tg::kQLine;
+  if ((s = grow(L.qctl, ctl_words * 4)) != TG_OK) return s;
+  HIPCHK(tg::launch_fill(L.qctl.as<uint32_t>(), ctl_words, 0, st));  // this launch's clear finds nothing to do
+  if (G) {
+    HIPCHK(hipMemcpyAsync(L.gtab.p, L.gtab_host.data(), G * sizeof(GraphEnt), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(L.gsrc.p, L.gsrc_host.data(), G * sizeof(tg::GraphSrc), hipMemcpyHostToDevice, st));
+  }
+  if (N || nsrc)
+    HIPCHK(tg::launch_build_records(L.gsrc.as<tg::GraphSrc>(), G, (uint32_t)N, (uint32_t)nsrc, L.rec.as<TaskRec>(),
+                                    L.pred_addr.as<uint64_t>(), L.succ_pos.as<uint32_t>(), L.indeg.as<uint32_t>(),
+                                    L.qsrc.as<uint32_t>(), st));
+  L.cfg = cfg;
+  L.npos = (uint32_t)N;
+  L.nworkers = nw;
+  L.grid_blocks = cfg.mapping == TG_MAP_WAVE ? (nw + 3) / 4 : nw;
+  L.qwmax = qwmax;
+  L.pos_of.clear();
+  L.rec_host.clear();
+  {
+    DevInfo di;
+    if ((s = device_info(di)) != TG_OK) return s;
+    L.dev = di.dev;
+    L.variant = (cfg.mapping == TG_MAP_WAVE ? tg::flight_variant(TG_MAP_WAVE, 1, 1)
+                                            : tg::flight_variant(cfg.mapping, cfg.wg_waves, 1)) |
+                ((uint64_t)cfg.dispatch << 60);
+    L.units = nw;
+    L.capacity = cap32;
+    if (!L.ev_done) HIPCHK(hipEventCreateWithFlags(&L.ev_done, hipEventDisableTiming));
+  }
+  ExecParams& P = L.params;
+  memset(&P, 0, sizeof(P));
+  P.rec = L.rec.as<TaskRec>();
+  P.pred_addr = L.pred_addr.as<uint64_t>();
+  P.succ_pos = L.succ_pos.as<uint32_t>();
+  P.indeg = L.indeg.as<uint32_t>();
+  P.cnt = L.cnt.as<uint32_t>();
+  P.gtab = L.gtab.as<GraphEnt>();
+  P.ctrl = L.ctrl.as<tg::Ctrl>();
+  P.bell = L.bell.as<uint32_t>();
+  P.gang = 1;
+  P.npos = (uint32_t)N;
+  P.nworkers = nw;
+  P.window = cfg.window;
+  P.q = L.q.as<uint32_t>();
+  P.qctl = L.qctl.as<uint32_t>();
+  P.qsrc = L.qsrc.as<uint32_t>();
+  P.nsrc = (uint32_t)nsrc;
+  P.nsinks = (uint32_t)nsinks;
+  P.qshards = shards;
+  P.qcap = (uint32_t)cap;
+  P.qtile = cfg.tile;
+  P.qsent = cfg.tile * (qwmax + 1);
+  if (report && G) {
+    // per-graph completion: counts cleared on the stream, flags compared
+    // with this launch's sequence number (never cleared)
+    if ((s = grow(L.gdone, G * 4)) != TG_OK) return s;
+    if (L.gflag_n < G) {
+      size_t have = L.gflag_n * 4;
+      if ((s = grow_pinned(L.gflag, have, G * 4, true)) != TG_OK) return s;
+      L.gflag_n = have / 4;
+      memset(L.gflag, 0, L.gflag_n * 4);
+      L.gseq = 0;
+    }
+    HIPCHK(tg::launch_fill(L.gdone.as<uint32_t>(), G, 0, st));
+    P.gdone = L.gdone.as<uint32_t>();
+    void* dflag = nullptr;
+    HIPCHK(hipHostGetDevicePointer(&dflag, L.gflag, 0));
+    P.gflag = (uint32_t*)dflag;
+    P.gseq = ++L.gseq;
+  }
+  L.plan_ms = 0;
+  L.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_build).count();
   return TG_OK;
 }
 
@@ -1684,9 +1904,98 @@ tg_status finalize_explicit(tg_graph g) {
   return TG_OK;
 }
 
+// Packs the compiled graph into g->blob (see tg_graph_s::BlobOff): rows of
+// distinct predecessors (explicit) and of executed successors as u32
+// offsets, counter reset values, mix rounds, payload slots, requirement rows
+// and requirements (implicit, 32-byte ReqDev records), and the sources.
+// Called whenever any of these change after finalize.
+tg_status build_blob(tg_graph g) {
+  const uint32_t N = g->N();
+  const bool expl = g->mode == TG_EXPLICIT;
+  const uint64_t P = expl ? g->dpred.size() : 0, E = g->succ.size(), M = expl ? 0 : g->reqs.size();
+  if (P >= 0xFFFFFFFFull || E >= 0xFFFFFFFFull || M >= 0xFFFFFFFFull)
+    return fail(TG_EINVAL, "graph too large for 32-bit edge offsets");
+  tg_graph_s::BlobOff o;
+  uint64_t w = 0;
+  auto take = [&](uint64_t words) {  // sections start on 32-byte boundaries
+    const uint64_t at = w;
+    w += (words + 7) & ~7ull;
+    return at;
+  };
+  for (uint32_t v = 0; v < N; ++v) {
+    if (g->xindeg[v] == 0) o.nsrc++;
+    if (g->succ_ptr[v + 1] == g->succ_ptr[v]) o.nsinks++;
+  }
+  o.has_slot = expl && !g->slot_of.empty();
+  if (expl) {
+    o.pred_ptr = take((uint64_t)N + 1);
+    o.preds = take(P);
+  } else {
+    o.req_ptr = take((uint64_t)N + 1);
+    o.reqs = take(M * (sizeof(ReqDev) / 4));
+  }
+  o.succ_ptr = take((uint64_t)N + 1);
+  o.succ = take(E);
+  o.indeg = take(N);
+  o.rounds = take(N);
+  if (o.has_slot) o.slot = take(N);
+  o.src = take(o.nsrc);
+  o.words = w;
+  std::vector<uint32_t>& b = g->blob;
+  b.assign(w, 0);
+  if (expl) {
+    for (uint32_t v = 0; v <= N; ++v) b[o.pred_ptr + v] = (uint32_t)g->dpred_ptr[v];
+    std::copy(g->dpred.begin(), g->dpred.end(), b.begin() + o.preds);
+  } else {
+    for (uint32_t v = 0; v <= N; ++v) b[o.req_ptr + v] = (uint32_t)g->req_ptr[v];
+    for (uint64_t i = 0; i < M; ++i) {
+      ReqDev q;
+      memset(&q, 0, sizeof(q));
+      q.lo = g->reqs[i].lo;
+      q.hi = g->reqs[i].hi;
+      q.priv = g->reqs[i].priv;
+      q.rw_base = g->rw_base[i];
+      memcpy(b.data() + o.reqs + i * (sizeof(ReqDev) / 4), &q, sizeof(q));
+    }
+  }
+  for (uint32_t v = 0; v <= N; ++v) b[o.succ_ptr + v] = (uint32_t)g->succ_ptr[v];
+  std::copy(g->succ.begin(), g->succ.end(), b.begin() + o.succ);
+  std::copy(g->xindeg.begin(), g->xindeg.end(), b.begin() + o.indeg);
+  std::copy(g->rounds.begin(), g->rounds.end(), b.begin() + o.rounds);
+  if (o.has_slot) std::copy(g->slot_of.begin(), g->slot_of.end(), b.begin() + o.slot);
+  for (uint32_t v = 0, k = 0; v < N; ++v)
+    if (g->xindeg[v] == 0) b[o.src + k++] = v;
+  g->bo = o;
+  g->blob_gen++;
+  return TG_OK;
+}
+
+// Uploads the compiled graph's blob if the device copy is missing or stale
+// (on `st`; the null stream when st is null).
+tg_status ensure_blob(tg_graph g, hipStream_t st) {
+  if (g->dblob.p && g->dblob_gen == g->blob_gen) return TG_OK;
+  tg_status s;
+  const size_t bytes = std::max<size_t>(g->blob.size(), 8) * 4;
+  if (g->dblob.p && g->dblob.bytes < bytes) g->dblob.release();
+  if (!g->dblob.p) {
+    if ((s = g->dblob.alloc(bytes)) != TG_OK) return s;
+    g->dev_gen++;  // layouts hold addresses inside it
+  }
+  const uint64_t t0 = steady_ns();
+  if (!g->blob.empty()) HIPCHK(hipMemcpyAsync(g->dblob.p, g->blob.data(), g->blob.size() * 4, hipMemcpyHostToDevice, st));
+  t_copy_ns += steady_ns() - t0;
+  g->dblob_gen = g->blob_gen;
+  return TG_OK;
+}
+
+// Device address of task v's first requirement (implicit graphs).
+uint64_t req_addr(tg_graph g, uint32_t v) {
+  return (uint64_t)g->dblob.p + (g->bo.reqs + (uint64_t)g->blob[g->bo.req_ptr + v] * (sizeof(ReqDev) / 4)) * 4;
+}
+
 // Device buffers of a graph are allocated on first use, so graphs can be
 // built and compiled on a machine without a GPU.
-tg_status ensure_device(tg_graph g) {
+tg_status ensure_device(tg_graph g, bool upload_blob) {
   const uint32_t N = g->N();
   tg_status s;
   g->released = false;
@@ -1699,8 +2008,9 @@ tg_status ensure_device(tg_graph g) {
   }
   if (!g->digest.p) {
     if ((s = g->digest.alloc((size_t)N * 4)) != TG_OK) return s;
-    HIPCHK(hipMemsetAsync(g->digest.p, 0, (size_t)N * 4, nullptr));
+    HIPCHK(hipMemsetAsync(g->digest.p, 0, (size_t)N * 4, t_copy_stream));
   }
+  if (upload_blob && (s = ensure_blob(g, t_copy_stream)) != TG_OK) return s;
   return TG_OK;  // the caller fences the null stream once for all its graphs
 }
 
@@ -1907,6 +2217,7 @@ tg_status tg_graph_finalize(tg_graph g) {
   auto t0 = std::chrono::steady_clock::now();
   tg_status s = g->mode == TG_EXPLICIT ? finalize_explicit(g) : tg_finalize_implicit(g);
   if (s != TG_OK) return s;
+  if ((s = build_blob(g)) != TG_OK) return s;
   g->finalized = true;
   g->compile_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() - g->infer_ms;
   return TG_OK;
@@ -2114,6 +2425,7 @@ tg_status tg_graph_reduce_edges(tg_graph g, uint64_t* removed) {
   g->dpred_ptr.swap(pp);
   g->dpred.swap(pr);
   for (uint32_t k = 0; k < N; ++k) g->xindeg[k] = (uint32_t)(g->dpred_ptr[k + 1] - g->dpred_ptr[k]);
+  if ((s = build_blob(g)) != TG_OK) return s;
   g->reduced = true;
   // layouts and schedules were built on the full edge set
   drop_solo(g);
@@ -2224,6 +2536,10 @@ tg_status tg_graph_set_rounds(tg_graph g, uint32_t uniform_rounds) {
   tg_status s = graph_wait(g);
   if (s != TG_OK) return s;
   std::fill(g->rounds.begin(), g->rounds.end(), uniform_rounds);
+  if (g->finalized) {
+    std::fill(g->blob.begin() + g->bo.rounds, g->blob.begin() + g->bo.rounds + g->N(), uniform_rounds);
+    g->blob_gen++;
+  }
   if (g->solo) {
     Layout& L = *g->solo;
     for (auto& r : L.rec_host) r.rounds = uniform_rounds;
@@ -2783,6 +3099,9 @@ struct tg_server_s {
     uint64_t t_submit = 0, t_admit = 0, t_done = 0;
     tg_status status = TG_OK;
     bool done = false;
+    // the record lives until both its slot let go of it (a request can
+    // finish while its launch still runs) and its waiter read it
+    bool in_slot = false, waited = false;
   };
   // A launch slot: one stream, one layout at a time, and a builder thread
   // that compiles and launches the batch assigned to it, so that up to one
@@ -2795,11 +3114,18 @@ struct tg_server_s {
     hipEvent_t ev = nullptr, ev0 = nullptr;  // end of the launch; its start (timing)
     State state = kIdle;
     bool assigned = false;  // a batch waits for the builder
+    bool reports = false;   // the launch reports graphs as they finish (flags in the layout)
+    // device memory of requests completed while their launch still runs,
+    // freed when it ends
+    std::vector<std::unique_ptr<DevBuf>> keep;
     std::condition_variable cv;
     std::thread th;
   };
   uint64_t budget = 0, in_use = 0, next_ticket = 1;
   uint32_t workers = 0, max_batch = 64;
+  // launch configuration of every batch: the ready queue with records built
+  // on the device (no host schedule), unless lists are chosen
+  Config cfg;
   std::vector<std::unique_ptr<Slot>> slots;
   std::deque<Req*> pending;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
@@ -2826,20 +3152,31 @@ uint64_t now_ns() {
 // Device bytes a compiled graph occupies while admitted: its payloads (or
 // array) and digests plus its share of a layout.
 uint64_t graph_device_bytes(tg_graph g) {
-  const uint64_t N = g->N(), E = g->succ.size();
+  const uint64_t N = g->N(), E = g->succ.size(), P = g->dpred.size();
   uint64_t b = N * 4;  // digests
   b += g->mode == TG_EXPLICIT ? (uint64_t)g->nslots * g->n * 4ull : g->space * 4ull;
-  b += N * (sizeof(TaskRec) + 4 + 4 + 4 + 4) + E * (8 + 4);
+  b += g->blob.size() * 4;  // the compiled graph on the device
+  // its share of a launch: records, counters and reset values, successor
+  // positions, predecessor addresses, a slot in each of 8 queue shards
+  b += N * (sizeof(TaskRec) + 4 + 4 + 8 * 4) + E * 4 + P * 8;
   return b + 4096;
 }
 
-void release_graph_device(tg_graph g) {
+// Copies a served graph's digests to the host and releases its device
+// memory -- or, with `keep`, hands the memory to the caller (a launch that
+// still runs may hold addresses inside it), leaving the graph free to be
+// submitted again.
+void release_graph_device(tg_graph g, std::vector<std::unique_ptr<DevBuf>>* keep = nullptr) {
   const uint32_t N = g->N();
   g->host_digest.assign(N, 0);
   if (N && g->digest.p) (void)hipMemcpy(g->host_digest.data(), g->digest.p, (size_t)N * 4, hipMemcpyDeviceToHost);
-  g->payload.release();
-  g->data.release();
-  g->digest.release();
+  for (DevBuf* b : {&g->payload, &g->data, &g->digest, &g->dblob}) {
+    if (keep && b->p) {
+      keep->push_back(std::make_unique<DevBuf>());
+      keep->back()->take(*b);
+    }
+    b->release();
+  }
   drop_solo(g);
   g->inflight = false;
   g->released = true;
@@ -2854,6 +3191,13 @@ void finish_req(tg_server srv, tg_server_s::Req* r, tg_status st, uint64_t t) {
   srv->live.erase(r->g);
 }
 
+// A slot lets go of a request record (the server's lock is held): freed now
+// if its waiter has already read it, else by the waiter.
+void leave_slot(tg_server srv, tg_server_s::Req* r) {
+  r->in_slot = false;
+  if (r->waited) srv->reqs.erase(r->ticket);
+}
+
 // Builder thread of one slot: compile the assigned batch into a layout and
 // launch it on the slot's stream.
 void slot_builder(tg_server srv, tg_server_s::Slot* sl) {
@@ -2863,15 +3207,22 @@ void slot_builder(tg_server srv, tg_server_s::Slot* sl) {
     if (!sl->assigned) return;  // stopping
     sl->assigned = false;
     const std::vector<tg_server_s::Req*> batch = sl->reqs;
+    const Config cfg = srv->cfg;
     lk.unlock();
     std::vector<tg_graph> gs;
     for (auto* r : batch) gs.push_back(r->g);
-    Config cfg;
-    cfg.workers = srv->workers;
+    const bool device_built = cfg.dispatch == TG_DISPATCH_QUEUE;
     const uint64_t h0 = t_hook_ns, c0 = t_copy_ns;
     const uint64_t t0 = now_ns();
     t_copy_stream = sl->st;
-    tg_status st = build_layout(gs, cfg, sl->lay, nullptr, false);
+    tg_status st;
+    sl->reports = device_built;
+    if (device_built) {
+      if (!sl->lay) sl->lay = std::make_unique<Layout>();
+      st = build_layout_device(gs, cfg, *sl->lay, sl->st, true);
+    } else {
+      st = build_layout(gs, cfg, sl->lay, nullptr, false);
+    }
     t_copy_stream = nullptr;
     const uint64_t t1 = now_ns();
     if (st == TG_OK && hipEventRecord(sl->ev0, sl->st) != hipSuccess) st = TG_EDEVICE;
@@ -2890,6 +3241,7 @@ void slot_builder(tg_server srv, tg_server_s::Slot* sl) {
       for (auto* r : batch) {
         srv->in_use -= r->bytes;
         finish_req(srv, r, st, now_ns());
+        leave_slot(srv, r);
       }
       sl->lay.reset();
       sl->reqs.clear();
@@ -2909,6 +3261,24 @@ void server_loop(tg_server srv) {
   std::unique_lock<std::mutex> lk(srv->mu);
   while (!srv->stop) {
     bool progressed = false, running = false;
+    // requests whose graphs finished inside launches that still run
+    for (auto& slp : srv->slots) {
+      tg_server_s::Slot& sl = *slp;
+      if (sl.state != tg_server_s::Slot::kRunning || !sl.reports || !sl.lay || !sl.lay->gflag) continue;
+      const uint32_t seq = sl.lay->gseq;
+      for (size_t i = 0; i < sl.reqs.size() && i < sl.lay->gflag_n; ++i) {
+        tg_server_s::Req* r = sl.reqs[i];
+        if (r->done || __atomic_load_n(sl.lay->gflag + i, __ATOMIC_ACQUIRE) != seq) continue;
+        const uint64_t t = now_ns();
+        lk.unlock();
+        release_graph_device(r->g, &sl.keep);
+        lk.lock();
+        srv->tasks_done += r->g->N();
+        finish_req(srv, r, TG_OK, t);
+        progressed = true;
+        srv->cv_done.notify_all();
+      }
+    }
     // retire finished launches
     for (auto& slp : srv->slots) {
       tg_server_s::Slot& sl = *slp;
@@ -2922,13 +3292,19 @@ void server_loop(tg_server srv) {
       std::vector<tg_server_s::Req*> done;
       done.swap(sl.reqs);
       lk.unlock();
-      for (auto* r : done) release_graph_device(r->g);
-      sl.lay.reset();
+      for (auto* r : done)
+        if (!r->done) release_graph_device(r->g);
+      sl.keep.clear();
+      // a device-built layout keeps its buffers for the slot's next batch
+      if (sl.lay && sl.lay->cfg.dispatch != TG_DISPATCH_QUEUE) sl.lay.reset();
       lk.lock();
       for (auto* r : done) {
         srv->in_use -= r->bytes;
-        srv->tasks_done += r->g->N();
-        finish_req(srv, r, st, t);
+        if (!r->done) {  // else reported while the launch ran
+          srv->tasks_done += r->g->N();
+          finish_req(srv, r, st, t);
+        }
+        leave_slot(srv, r);
       }
       sl.state = tg_server_s::Slot::kIdle;
       srv->retire_ms += (now_ns() - t) * 1e-6;
@@ -2960,7 +3336,10 @@ void server_loop(tg_server srv) {
       srv->in_use += add;
       if (srv->in_use > srv->peak_in_use) srv->peak_in_use = srv->in_use;
       const uint64_t t = now_ns();
-      for (auto* r : batch) r->t_admit = t;
+      for (auto* r : batch) {
+        r->t_admit = t;
+        r->in_slot = true;
+      }
       sl.reqs = batch;
       sl.state = tg_server_s::Slot::kBuilding;
       sl.assigned = true;
@@ -2994,6 +3373,8 @@ tg_status tg_server_create(tg_server* out, uint64_t budget_bytes, uint32_t slots
   auto srv = std::make_unique<tg_server_s>();
   srv->budget = budget_bytes;
   srv->workers = resident / slots;  // concurrent launches stay co-resident together
+  srv->cfg.workers = srv->workers;
+  srv->cfg.dispatch = TG_DISPATCH_QUEUE;
   srv->max_batch = max_batch ? max_batch : 64;
   for (uint32_t i = 0; i < slots; ++i) {
     auto sl = std::make_unique<tg_server_s::Slot>();
@@ -3006,6 +3387,19 @@ tg_status tg_server_create(tg_server* out, uint64_t budget_bytes, uint32_t slots
   for (auto& sl : srvp->slots) sl->th = std::thread(slot_builder, srvp, sl.get());
   srvp->th = std::thread(server_loop, srvp);
   *out = srvp;
+  return TG_OK;
+}
+
+tg_status tg_server_configure(tg_server srv, const tg_exec_config* cfgp) {
+  if (!srv || !cfgp) return fail(TG_EINVAL, "NULL argument");
+  Config c = resolve(cfgp);
+  if (!cfgp->dispatch) c.dispatch = TG_DISPATCH_QUEUE;
+  if (!cfgp->workers) c.workers = srv->workers;
+  tg_status s = check_config(c);
+  if (s != TG_OK) return s;
+  if (c.mapping == TG_MAP_GANG) return fail(TG_EINVAL, "the server runs wavefront or workgroup workers");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->cfg = c;
   return TG_OK;
 }
 
@@ -3038,7 +3432,8 @@ tg_status tg_server_wait(tg_server srv, uint64_t ticket, uint64_t* submit_ns, ui
   if (admit_ns) *admit_ns = r->t_admit;
   if (done_ns) *done_ns = r->t_done;
   const tg_status st = r->status;
-  srv->reqs.erase(it);
+  if (r->in_slot) r->waited = true;  // the slot's retirement frees it
+  else srv->reqs.erase(it);
   if (st != TG_OK) return fail(st, "request %llu failed", (unsigned long long)ticket);
   return TG_OK;
 }

@@ -22,7 +22,8 @@ struct GraphEnt {
   uint32_t* data;    // implicit: shared array A (index space words)
   uint32_t n;        // explicit: payload words per task (power of two)
   uint32_t mode;     // 1 explicit, 2 implicit
-  uint32_t pad[2];
+  uint32_t nsinks;   // tasks without out-edges (per-graph completion)
+  uint32_t pad;
 };
 
 constexpr uint32_t kInPred = 6;  // predecessor payload addresses held in the record
@@ -35,7 +36,7 @@ constexpr uint32_t kInSucc = 8;  // successor positions held in the record
 // record) and its edge signals on none after the payload store.
 struct alignas(128) TaskRec {
   uint64_t out;            // dw 0-1  explicit: device address of this task's payload
-                           //         implicit: index of its first region requirement
+                           //         implicit: device address of its first region requirement
   uint32_t tid;            // dw 2    task id inside its graph (creation index)
   uint32_t graph;          // dw 3    index into the graph table
   uint32_t pred_beg;       // dw 4    explicit: all predecessors at pred_addr[pred_beg ..]
@@ -93,7 +94,6 @@ struct ExecParams {
   uint32_t* cnt;               // pending in-edge counters
   const uint32_t* wbase;       // worker w owns positions [wbase[w], wbase[w+1])
   const GraphEnt* gtab;
-  const ReqDev* reqs;
   Ctrl* ctrl;
   const uint32_t* owner;       // worker of every position
   uint32_t* bell;              // per-worker doorbell, one per 128-byte line
@@ -125,6 +125,36 @@ struct ExecParams {
   uint32_t qcap;               // slots per shard: the task count plus the exit sentinels
   uint32_t qtile;              // tickets claimed per pop (1..64)
   uint32_t qsent;              // exit sentinels pushed into every shard at the end
+  // per-graph completion (queue kernels; null gdone: not reported)
+  uint32_t* gdone;             // sinks finished per graph of the layout
+  uint32_t* gflag;             // per graph, in host memory: gseq once it finished
+  uint32_t gseq;
+};
+
+// One graph of a layout whose task records are built on the device
+// (k_build_records) from the graph's compiled blob: row offsets and id lists
+// of its distinct predecessors (explicit) and executed successors, counter
+// reset values, mix rounds, payload slots (or null), requirement rows and
+// requirements (implicit), and sources.
+struct alignas(16) GraphSrc {
+  const uint32_t* pred_ptr;
+  const uint32_t* preds;
+  const uint32_t* succ_ptr;
+  const uint32_t* succ;
+  const uint32_t* indeg;
+  const uint32_t* rounds;
+  const uint32_t* slot;
+  const uint32_t* req_ptr;
+  const ReqDev* reqs;
+  const uint32_t* src;
+  uint64_t payload;     // explicit: payload base address; slot or task v at payload + 4n v
+  uint32_t pos_base;    // first position of the graph in the layout
+  uint32_t pred_base;   // first entry of its predecessor addresses in pred_addr
+  uint32_t succ_base;   // first entry of its successor positions in succ_pos
+  uint32_t src_base;    // first entry of its sources in the launch's source list
+  uint32_t n;           // payload words (explicit)
+  uint32_t mode;
+  uint32_t pad[2];
 };
 
 constexpr uint32_t kQEmpty = 0xFFFFFFFFu;
@@ -147,8 +177,19 @@ hipError_t launch_exec(const ExecParams& p, uint32_t mapping, uint32_t wg_waves,
 // Ready-queue dispatch: clear the slots used by the previous launch, then
 // seed the queue with the sources (after launch_reset, before the executor).
 hipError_t launch_queue_reset(const ExecParams& p, hipStream_t s);
+// Only the clearing half: empties the slots the last launch of p filled.
+hipError_t launch_queue_clear(const ExecParams& p, hipStream_t s);
 hipError_t launch_exec_queue(const ExecParams& p, uint32_t mapping, uint32_t wg_waves, uint32_t grid_blocks,
                              hipStream_t s);
+// Task records, predecessor addresses, successor positions, counter reset
+// values and the source list of a layout, built on the device from the
+// graphs' blobs: ng graphs (table gsrc, ascending pos_base and src_base),
+// npos positions, nsrc sources.
+hipError_t launch_build_records(const GraphSrc* gsrc, uint32_t ng, uint32_t npos, uint32_t nsrc, TaskRec* rec,
+                                uint64_t* pred_addr, uint32_t* succ_pos, uint32_t* indeg, uint32_t* src,
+                                hipStream_t s);
+// Clears n words to v with a kernel (stream-ordered, no memset node).
+hipError_t launch_fill(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 // Occupancy: blocks per CU for the executor kernel of this mapping.
 int exec_blocks_per_cu(uint32_t mapping, uint32_t wg_waves);
 // One task per launch (comparator): runs position `pos` with no counters.

@@ -306,7 +306,7 @@ __device__ __forceinline__ u32x4 load4(const uint32_t* p, uint32_t t, uint32_t S
 template <class Team>
 __device__ __forceinline__ uint32_t body_implicit(const Team& tm, const ExecParams& P, const Rec& r,
                                                   const GraphEnt& G) {
-  const cptr<ReqDev> rq = as_const(P.reqs) + r.out;
+  const cptr<ReqDev> rq = as_const((const ReqDev*)r.out);
   uint32_t* A = G.data;
   // read-only elements: their wrap sum c
   uint32_t part = 0;
@@ -362,7 +362,9 @@ __device__ __forceinline__ uint32_t run_body(const Team& tm, const ExecParams& P
 template <class Team>
 __device__ __forceinline__ void run_task(const Team& tm, const ExecParams& P, uint32_t pos, uint32_t v, Rec& r) {
   const uint32_t d = run_body(tm, P, pos, v, r);
-  if (tm.leader()) r.digest[r.tid] = d;
+  // device-coherent, so it is in memory once the team's stores are drained
+  // (a graph's digests may be read while its launch still runs)
+  if (tm.leader()) st_coherent(r.digest + r.tid, d);
 }
 
 // Signal every out-edge of a finished task (COMPLETED_EDGE).
@@ -699,7 +701,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
       if (ok) {
         uint32_t total = d;
         for (uint32_t m = 1; m < G; ++m) total += ld_coherent(mb + 16 + m);
-        r.digest[r.tid] = total;
+        st_coherent(r.digest + r.tid, total);
       }
     }
     __syncthreads();
@@ -914,6 +916,19 @@ __device__ __forceinline__ void complete_edges_q(const Team& tm, const ExecParam
   }
 }
 
+// Per-graph completion (launches that report graphs as they finish): a
+// finished sink adds one to its graph's count; the addition that completes
+// it stores the launch's sequence number into the graph's flag in host
+// memory.  Every task of the graph precedes one of its sinks, and every
+// sink's stores were drained before its addition, so the graph's results are
+// in memory when the flag is seen.
+__device__ __forceinline__ void graph_sink_done(const ExecParams& P, uint32_t graph, bool lead) {
+  if (!P.gdone || !lead) return;
+  const uint32_t old = __hip_atomic_fetch_add(P.gdone + graph, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (old + 1u == as_const(P.gtab)[graph].nsinks)
+    __hip_atomic_store(P.gflag + graph, P.gseq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exec_wave_q(ExecParams P) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t worker = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -929,6 +944,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     run_task(tm, P, pos, rec_dword(P, pos, lane), r);
     if (r.nsucc == 0u) ++q.sinks;
     complete_edges_q(tm, P, r, q, true);
+    if (r.nsucc == 0u) graph_sink_done(P, r.graph, lane == 0);
     if (P.tstamp && lane == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
   }
 }
@@ -962,6 +978,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
     run_task(tm, P, pos, v, r);
     if (threadIdx.x < 64 && r.nsucc == 0u) ++q.sinks;
     complete_edges_q(tm, P, r, q, threadIdx.x < 64);
+    if (r.nsucc == 0u) graph_sink_done(P, r.graph, threadIdx.x == 0);
     if (P.tstamp && threadIdx.x == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
     __syncthreads();
   }
@@ -1039,7 +1056,100 @@ __global__ __launch_bounds__(64) void k_one_task(ExecParams P, uint32_t pos) {
   run_task(tm, P, pos, rec_dword(P, pos, threadIdx.x), r);
 }
 
+// -------------------------------------------- records built on the device
+
+// Last graph whose `field` is <= x (the table ascends in it; graphs without
+// tasks share their successor's base, so the last such graph is the one that
+// holds x).
+template <uint32_t GraphSrc::*F>
+__device__ __forceinline__ uint32_t graph_of(const GraphSrc* g, uint32_t ng, uint32_t x) {
+  uint32_t lo = 0, hi = ng;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (g[mid].*F <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One thread per position: the record of the task at that position (layout
+// order = graph order, task ids ascending), its slices of the predecessor
+// address and successor position arrays, and its counter reset value; then
+// one thread per source: the launch's source list.
+__global__ __launch_bounds__(256) void k_build_records(const GraphSrc* gsrc, uint32_t ng, uint32_t npos, uint32_t nsrc,
+                                                       TaskRec* rec, uint64_t* pred_addr, uint32_t* succ_pos,
+                                                       uint32_t* indeg, uint32_t* src) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npos; p += stride) {
+    const uint32_t gi = graph_of<&GraphSrc::pos_base>(gsrc, ng, p);
+    const GraphSrc& g = gsrc[gi];
+    const uint32_t v = p - g.pos_base;
+    TaskRec r;
+    memset(&r, 0, sizeof(r));
+    r.tid = v;
+    r.graph = gi;
+    r.rounds = g.rounds[v];
+    const uint64_t wbytes = (uint64_t)g.n * 4u;
+    if (g.mode == 1) {
+      r.out = g.payload + (uint64_t)(g.slot ? g.slot[v] : v) * wbytes;
+      const uint32_t d0 = g.pred_ptr[v], d1 = g.pred_ptr[v + 1];
+      r.npred = d1 - d0;
+      r.pred_beg = g.pred_base + d0;
+      for (uint32_t j = d0; j < d1; ++j) {
+        const uint32_t q = g.preds[j];
+        const uint64_t addr = g.payload + (uint64_t)(g.slot ? g.slot[q] : q) * wbytes;
+        if (j - d0 < kInPred) r.pred[j - d0] = addr;
+        pred_addr[g.pred_base + j] = addr;
+      }
+    } else {
+      const uint32_t a0 = g.req_ptr[v];
+      r.out = (uint64_t)(g.reqs + a0);
+      r.nreq = g.req_ptr[v + 1] - a0;
+    }
+    const uint32_t s0 = g.succ_ptr[v], s1 = g.succ_ptr[v + 1];
+    r.nsucc = s1 - s0;
+    r.succ_beg = g.succ_base + s0;
+    for (uint32_t j = s0; j < s1; ++j) {
+      const uint32_t sp = g.pos_base + g.succ[j];
+      if (j - s0 < kInSucc) r.succ[j - s0] = sp;
+      succ_pos[g.succ_base + j] = sp;
+    }
+    rec[p] = r;
+    indeg[p] = g.indeg[v];
+  }
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nsrc; i += stride) {
+    const GraphSrc& g = gsrc[graph_of<&GraphSrc::src_base>(gsrc, ng, i)];
+    src[i] = g.pos_base + g.src[i - g.src_base];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill(uint32_t* p, uint64_t n, uint32_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
 // ---------------------------------------------------------------- launchers
+
+hipError_t launch_build_records(const GraphSrc* gsrc, uint32_t ng, uint32_t npos, uint32_t nsrc, TaskRec* rec,
+                                uint64_t* pred_addr, uint32_t* succ_pos, uint32_t* indeg, uint32_t* src,
+                                hipStream_t s) {
+  const uint32_t n = npos > nsrc ? npos : nsrc;
+  uint32_t blocks = (n + 255u) / 256u;
+  if (blocks > 8192u) blocks = 8192u;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_build_records, dim3(blocks), dim3(256), 0, s, gsrc, ng, npos, nsrc, rec, pred_addr, succ_pos,
+                     indeg, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_reset(const ExecParams& p, hipStream_t s) {
   uint32_t blocks = (p.npos + 255u) / 256u;
@@ -1061,6 +1171,14 @@ hipError_t launch_exec(const ExecParams& p, uint32_t mapping, uint32_t wg_waves,
   } else {
     hipLaunchKernelGGL(k_exec_gang, dim3(grid_blocks), dim3(wg_waves * 64u), 0, s, p);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_clear(const ExecParams& p, hipStream_t s) {
+  uint32_t blocks = (p.qcap + 255u) / 256u;
+  if (blocks > 4096u) blocks = 4096u;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_queue_clear, dim3(blocks), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 

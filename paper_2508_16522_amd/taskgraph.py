@@ -43,7 +43,7 @@ EXPORTS = (
     "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
     "tg_graph_execute_after", "tg_reduce_dag", "tg_graph_reduce_edges",
     "tg_graph_set_retention", "tg_graph_payload_slots", "tg_graph_read_exec_dag", "tg_emulate_queue",
-    "tg_infer_dag", "tg_infer_dag_noalloc",
+    "tg_infer_dag", "tg_infer_dag_noalloc", "tg_server_configure",
 )
 
 
@@ -124,6 +124,7 @@ def load() -> ctypes.CDLL:
         "tg_server_wait": (i32, [G, u64, P, P, P]),
         "tg_server_stats": (i32, [G, P, P, P, P]),
         "tg_server_destroy": (i32, [G]),
+        "tg_server_configure": (i32, [G, P]),
         "tg_batch_kernel_times": (i32, [G, P, u32, P]),
         "tg_batch_set_rounds": (i32, [G, u32]),
         "tg_batch_info": (i32, [G, P, P, P, P]),
@@ -620,6 +621,10 @@ def tg_server_create(budget_bytes: int, slots: int = 4, max_batch: int = 64):
     srv = ctypes.c_void_p()
     _check(load().tg_server_create(ctypes.byref(srv), budget_bytes, slots, max_batch), "tg_server_create")
     return srv
+
+
+def tg_server_configure(srv, cfg: tg_exec_config):
+    _check(load().tg_server_configure(srv, ctypes.byref(cfg)), "tg_server_configure")
 
 
 def tg_server_submit(srv, g) -> int:

@@ -36,11 +36,21 @@ def _build(reqs):
     return graphs, handles
 
 
+SERVER_CONFIGS = {
+    "queue": None,  # the default: ready queue, records built on the device
+    "queue-wg4-tile4": tg.make_config(mapping=2, wg_waves=4, dispatch=tg.TG_DISPATCH_QUEUE, tile=4, shards=2),
+    "lists": tg.make_config(dispatch=tg.TG_DISPATCH_LISTS),
+}
+
+
+@pytest.mark.parametrize("config", list(SERVER_CONFIGS))
 @pytest.mark.parametrize("slots,max_batch", [(4, 8), (1, 1), (2, 64)])
-def test_mix_equals_alone_and_oracle(gpu, slots, max_batch):
+def test_mix_equals_alone_and_oracle(gpu, slots, max_batch, config):
     reqs = _small_requests(40, seed=slots)
     graphs, handles = _build(reqs)
     srv = tg.tg_server_create(8 << 30, slots=slots, max_batch=max_batch)
+    if SERVER_CONFIGS[config] is not None:
+        tg.tg_server_configure(srv, SERVER_CONFIGS[config])
     try:
         # submit following the arrival times, from another thread
         tickets = [None] * len(reqs)
@@ -143,3 +153,33 @@ def test_hipgraph_comparator_after_serving(gpu):
     tg.tg_graph_wait(h.handle)
     assert np.array_equal(tg.tg_graph_read_digests(h.handle), ref["digest"])
     assert tg.tg_graph_checksum(h.handle) == ref["checksum"]
+
+
+def test_configure_refuses_gangs(gpu):
+    srv = tg.tg_server_create(1 << 30, slots=1, max_batch=1)
+    try:
+        with pytest.raises(tg.TaskGraphError) as ei:
+            tg.tg_server_configure(srv, tg.make_config(mapping=3, gang=2))
+        assert ei.value.status == tg.TG_EINVAL
+    finally:
+        tg.tg_server_destroy(srv)
+
+
+def test_slot_layout_reused_across_batch_sizes(gpu):
+    """One slot serves batches that grow and shrink (its device-built layout
+    keeps and grows its buffers, and empties the queue slots of the previous
+    batch): every request of every batch equals the oracle."""
+    sizes = [(8, 4), (64, 40), (16, 8), (128, 60), (8, 2)]
+    srv = tg.tg_server_create(8 << 30, slots=1, max_batch=64)
+    try:
+        for k, (W, T) in enumerate(sizes):
+            egs = [wl.pattern_graph(p, W, T, seed=10 * k + i, n=64, rounds=3) for i, p in enumerate(wl.PATTERNS)]
+            hs = [tg.graph_from_explicit(eg) for eg in egs]
+            for t in [tg.tg_server_submit(srv, h.handle) for h in hs]:
+                tg.tg_server_wait(srv, t)
+            for eg, h in zip(egs, hs):
+                ref = _ref(eg)
+                assert np.array_equal(tg.tg_graph_read_digests(h.handle), ref["digest"]), (W, T, eg.N)
+                assert tg.tg_graph_checksum(h.handle) == ref["checksum"]
+    finally:
+        tg.tg_server_destroy(srv)
