@@ -267,10 +267,20 @@ def run_serving(args, stream, probes=None):
     reqs = wl.serving_manifest(warm + args.requests, rate=args.rate, seed=0)
     t0 = time.perf_counter()
     graphs, handles = [], []
+    edges_full, edges_run = 0, 0
     for i, r in enumerate(reqs):
         x = wl.build_request(r)
         graphs.append(x)
-        handles.append(tg.graph_from_implicit(x) if isinstance(x, wl.ImplicitGraph) else tg.graph_from_explicit(x))
+        if isinstance(x, wl.ImplicitGraph):
+            h = tg.graph_from_implicit(x)
+            e = tg.tg_graph_num_edges(h.handle)  # the full inferred DAG
+            edges_full += e
+            edges_run += e
+        else:
+            h = tg.graph_from_explicit(x)
+            edges_full += x.E
+            edges_run += x.E
+        handles.append(h)
         if i % 1000 == 0:
             log(f"serving: built {i} requests, {time.perf_counter() - t0:.0f} s")
     srv = tg.tg_server_create(64 << 30, slots=args.slots, max_batch=args.max_batch)
@@ -327,6 +337,7 @@ def run_serving(args, stream, probes=None):
         "service_ms": {"p50": float(np.percentile(serv, 50)), "p99": float(np.percentile(serv, 99))},
         "server_config": getattr(args, "server_dispatch", "queue"),
         "offered_req_per_s": args.rate, "server": stats,
+        "edges": edges_run,
         "parity": {"ok": not bad, "requests": len(pick), "failed": bad,
                    "sample": "64 requests drawn with seed 1 from all submitted"},
     }

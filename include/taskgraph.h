@@ -457,7 +457,12 @@ tg_status tg_probe(uint32_t kind, double* value);
  * others run are admitted as soon as a slot and memory free up.  On
  * completion a request's digests are copied to the host (tg_graph_read_digests
  * and tg_graph_checksum keep working) and its device memory is released.
- * A request larger than the whole budget fails with TG_ENOMEM. */
+ * A request larger than the whole budget fails with TG_ENOMEM.  With more than
+ * one slot, requests of 65,536 tasks or more run in slot 0 only (which also
+ * takes smaller ones while no large one waits), so small requests do not share
+ * a launch with graphs that keep it busy for long.  With the ready queue
+ * (tg_server_configure) a request completes as soon as its graph has, while
+ * its launch may still run other graphs. */
 tg_status tg_server_create(tg_server* out, uint64_t budget_bytes, uint32_t slots, uint32_t max_batch);
 /* Launch configuration of the batches a server issues from now on (Section
  * 4.1: compiled graphs issued dynamically).  Default: TG_DISPATCH_QUEUE with
@@ -479,13 +484,15 @@ tg_status tg_server_submit(tg_server srv, tg_graph g, uint64_t* ticket);
  * times (ns) of submission, admission and completion.  Each ticket is waited
  * for once. */
 tg_status tg_server_wait(tg_server srv, uint64_t ticket, uint64_t* submit_ns, uint64_t* admit_ns, uint64_t* done_ns);
-/* Totals so far: tasks finished, launches, peak admitted bytes; phase_ms (7
- * doubles, may be NULL): host time of the serving thread building layouts
+/* Totals so far: tasks finished, launches, peak admitted bytes; phase_ms (9
+ * doubles, may be NULL): host time of the serving threads building layouts
  * (device buffers, schedule, upload), issuing launches and retiring finished
  * launches (results copied back, buffers released); the device time of all
  * launches (HIP events around each); and, inside the host time, the time
  * spent planning schedules and records, in the device-memory allocator
- * (hooks or hipMalloc/hipFree) and in host-device copies. */
+ * (hooks or hipMalloc/hipFree), in host-device copies, and (records built on
+ * the device) preparing the admitted graphs' device buffers and setting up
+ * the layout's buffers, tables and kernels. */
 tg_status tg_server_stats(tg_server srv, uint64_t* tasks_done, uint64_t* launches, uint64_t* peak_bytes,
                           double* phase_ms);
 /* Finishes all submitted work, then stops the server thread. */

@@ -81,6 +81,9 @@ void* g_ctx = nullptr;
 std::atomic<long> g_live{0};
 // host time this thread spent in allocator hooks and in host-device copies
 thread_local uint64_t t_hook_ns = 0, t_copy_ns = 0;
+// device-built layouts: preparing the graphs' device buffers, and the rest
+// of the layout (buffers, tables, kernels) after the blobs were staged
+thread_local uint64_t t_setup_ns = 0, t_tables_ns = 0;
 
 uint64_t steady_ns() {
   return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -1170,6 +1173,7 @@ tg_status build_layout_device(const std::vector<tg_graph>& gs, const Config& cfg
   if (s != TG_OK) return s;
   if (cfg.dispatch != TG_DISPATCH_QUEUE || cfg.mapping == TG_MAP_GANG)
     return fail(TG_EINVAL, "device-built layouts use the ready queue with wavefront or workgroup workers");
+  const uint64_t t_setup0 = steady_ns();
   {
     // the graphs' buffers are cleared and their blobs uploaded on `st` too
     const hipStream_t prev = t_copy_stream;
@@ -1192,12 +1196,36 @@ tg_status build_layout_device(const std::vector<tg_graph>& gs, const Config& cfg
   if ((s = grow_pinned(L.pin, L.pin_bytes, std::max<uint64_t>(bwords, 64) * 4)) != TG_OK) return s;
   if ((s = grow(L.blobs, std::max<uint64_t>(bwords, 64) * 4)) != TG_OK) return s;
   {
-    const uint64_t t0 = steady_ns();
-    for (size_t gi = 0; gi < gs.size(); ++gi)
-      if (!gs[gi]->blob.empty()) memcpy(L.pin + boff[gi], gs[gi]->blob.data(), gs[gi]->blob.size() * 4);
+    // large batches stage on several threads (the blobs are read from
+    // memory the cache no longer holds)
+    auto stage = [&](size_t g0, size_t g1) {
+      for (size_t gi = g0; gi < g1; ++gi)
+        if (!gs[gi]->blob.empty()) memcpy(L.pin + boff[gi], gs[gi]->blob.data(), gs[gi]->blob.size() * 4);
+    };
+    const size_t nth = bwords * 4 >= (8u << 20) ? std::min<size_t>(gs.size(), 6) : 1;
+    if (nth <= 1) {
+      stage(0, gs.size());
+    } else {
+      // split the graphs into nth runs of about equal words
+      std::vector<std::thread> pool;
+      size_t g0 = 0;
+      for (size_t t = 0; t < nth && g0 < gs.size(); ++t) {
+        const uint64_t until = bwords * (t + 1) / nth;
+        size_t g1 = g0;
+        while (g1 < gs.size() && (t + 1 == nth || boff[g1] < until)) ++g1;
+        if (g1 == g0) g1 = g0 + 1;
+        pool.emplace_back(stage, g0, g1);
+        g0 = g1;
+      }
+      for (auto& th : pool) th.join();
+      if (g0 < gs.size()) stage(g0, gs.size());
+    }
+    const uint64_t t0 = steady_ns();  // staging counts as set-up, the copy call as copying
     if (bwords) HIPCHK(hipMemcpyAsync(L.blobs.p, L.pin, bwords * 4, hipMemcpyHostToDevice, st));
     t_copy_ns += steady_ns() - t0;
+    t_setup_ns += t0 - t_setup0;
   }
+  const uint64_t t_tables0 = steady_ns();
   uint32_t cap32 = 0;
   if ((s = resident_workers(cfg.mapping, cfg.wg_waves, &cap32)) != TG_OK) return s;
   uint32_t nw = cfg.workers ? std::min(cfg.workers, cap32) : cap32;
@@ -1334,6 +1362,7 @@ tg_status build_layout_device(const std::vector<tg_graph>& gs, const Config& cfg
   }
   L.plan_ms = 0;
   L.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_build).count();
+  t_tables_ns += steady_ns() - t_tables0;
   return TG_OK;
 }
 
@@ -3121,6 +3150,7 @@ struct tg_server_s {
     std::condition_variable cv;
     std::thread th;
   };
+  static constexpr uint32_t kLargeTasks = 1u << 16;  // size class served by slot 0 alone
   uint64_t budget = 0, in_use = 0, next_ticket = 1;
   uint32_t workers = 0, max_batch = 64;
   // launch configuration of every batch: the ready queue with records built
@@ -3137,8 +3167,9 @@ struct tg_server_s {
   uint64_t tasks_done = 0, launches = 0, peak_in_use = 0;
   // host time of the serving thread by phase, and executor time on the device
   double build_ms = 0, launch_ms = 0, retire_ms = 0, gpu_ms = 0;
-  // parts of it: schedules and records, allocator hooks, host-device copies
-  double plan_ms = 0, hook_ms = 0, copy_ms = 0;
+  // parts of it: schedules and records, allocator hooks, host-device copies;
+  // device-built layouts: the graphs' buffers, the layout's tables and kernels
+  double plan_ms = 0, hook_ms = 0, copy_ms = 0, setup_ms = 0, tables_ms = 0;
 };
 
 namespace {
@@ -3212,7 +3243,7 @@ void slot_builder(tg_server srv, tg_server_s::Slot* sl) {
     std::vector<tg_graph> gs;
     for (auto* r : batch) gs.push_back(r->g);
     const bool device_built = cfg.dispatch == TG_DISPATCH_QUEUE;
-    const uint64_t h0 = t_hook_ns, c0 = t_copy_ns;
+    const uint64_t h0 = t_hook_ns, c0 = t_copy_ns, s0 = t_setup_ns, b0 = t_tables_ns;
     const uint64_t t0 = now_ns();
     t_copy_stream = sl->st;
     tg_status st;
@@ -3237,6 +3268,8 @@ void slot_builder(tg_server srv, tg_server_s::Slot* sl) {
     if (sl->lay) srv->plan_ms += sl->lay->plan_ms;
     srv->hook_ms += (t_hook_ns - h0) * 1e-6;
     srv->copy_ms += (t_copy_ns - c0) * 1e-6;
+    srv->setup_ms += (t_setup_ns - s0) * 1e-6;
+    srv->tables_ms += (t_tables_ns - b0) * 1e-6;
     if (st != TG_OK) {
       for (auto* r : batch) {
         srv->in_use -= r->bytes;
@@ -3313,26 +3346,43 @@ void server_loop(tg_server srv) {
       progressed = true;
       srv->cv_done.notify_all();
     }
-    // admit waiting requests into idle slots
-    for (auto& slp : srv->slots) {
-      tg_server_s::Slot& sl = *slp;
+    // requests that can never fit the budget fail at once
+    for (auto it = srv->pending.begin(); it != srv->pending.end();) {
+      if ((*it)->bytes > srv->budget) {
+        finish_req(srv, *it, TG_ENOMEM, now_ns());
+        srv->cv_done.notify_all();
+        it = srv->pending.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    // admit waiting requests into idle slots, in arrival order and while
+    // the budget holds them.  With several slots, requests of at least
+    // kLargeTasks tasks go to slot 0 only (which takes small ones when no
+    // large one waits): a small request then never shares a launch -- and
+    // its ready queue -- with a graph that keeps the launch busy for long.
+    for (size_t si = 0; si < srv->slots.size(); ++si) {
+      tg_server_s::Slot& sl = *srv->slots[si];
       if (sl.state != tg_server_s::Slot::kIdle || srv->pending.empty()) continue;
+      const bool sized = srv->slots.size() > 1;
+      auto large = [](const tg_server_s::Req* r) { return r->g->N() >= tg_server_s::kLargeTasks; };
+      bool want_large = false;
+      if (sized && si == 0)
+        for (auto* r : srv->pending) want_large |= large(r);
       std::vector<tg_server_s::Req*> batch;
       uint64_t add = 0;
-      while (!srv->pending.empty() && batch.size() < srv->max_batch) {
-        auto* r = srv->pending.front();
-        if (r->bytes > srv->budget) {  // can never fit
-          srv->pending.pop_front();
-          finish_req(srv, r, TG_ENOMEM, now_ns());
-          srv->cv_done.notify_all();
+      for (auto it = srv->pending.begin(); it != srv->pending.end() && batch.size() < srv->max_batch;) {
+        tg_server_s::Req* r = *it;
+        if (sized && large(r) != want_large) {
+          ++it;
           continue;
         }
         if (srv->in_use + add + r->bytes > srv->budget) break;
         batch.push_back(r);
         add += r->bytes;
-        srv->pending.pop_front();
+        it = srv->pending.erase(it);
       }
-      if (batch.empty()) break;
+      if (batch.empty()) continue;
       srv->in_use += add;
       if (srv->in_use > srv->peak_in_use) srv->peak_in_use = srv->in_use;
       const uint64_t t = now_ns();
@@ -3453,6 +3503,8 @@ tg_status tg_server_stats(tg_server srv, uint64_t* tasks_done, uint64_t* launche
     phase_ms[4] = srv->plan_ms;
     phase_ms[5] = srv->hook_ms;
     phase_ms[6] = srv->copy_ms;
+    phase_ms[7] = srv->setup_ms;
+    phase_ms[8] = srv->tables_ms;
   }
   return TG_OK;
 }

@@ -641,11 +641,12 @@ def tg_server_wait(srv, ticket: int):
 
 def tg_server_stats(srv):
     a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
-    ph = (ctypes.c_double * 7)()
+    ph = (ctypes.c_double * 9)()
     _check(load().tg_server_stats(srv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ph), "tg_server_stats")
     return {"tasks_done": a.value, "launches": b.value, "peak_bytes": c.value,
             "host_build_ms": ph[0], "host_launch_ms": ph[1], "host_retire_ms": ph[2], "device_ms": ph[3],
-            "host_plan_ms": ph[4], "host_alloc_ms": ph[5], "host_copy_ms": ph[6]}
+            "host_plan_ms": ph[4], "host_alloc_ms": ph[5], "host_copy_ms": ph[6], "host_setup_ms": ph[7],
+            "host_tables_ms": ph[8]}
 
 
 def tg_server_destroy(srv):
