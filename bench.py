@@ -198,7 +198,8 @@ def leg_patterns(tg, wl, egs, gs, probes, stream):
                 cand.append((sms, sname, min(sw, conc)))
             rms, sname, sslots = min(cand)
             U = eg.N * eg.n * R
-            rows.append({"rounds": R, "ms": rms, "efficiency": (U / (rms * 1e-3)) / pi,
+            rows.append({"rounds": R, "ms": rms, "word_rounds_per_s": U / (rms * 1e-3),
+                         "efficiency": (U / (rms * 1e-3)) / pi,
                          "granularity_us": rms * 1e3 * sslots / eg.N, "launch": sname})
         tg.tg_graph_set_rounds(g.handle, 0)
         rec["sweep"] = rows
@@ -260,22 +261,59 @@ def leg_comparators(tg, wl, stream, steps):
                      "nodes instantiate in seconds, so larger graphs are not used", "patterns": out}
 
 
+def apply_peak(pi_probe, patterns, sweep, legs):
+    """The mix-rate peak Pi is the best rate of the task body measured in
+    this run: the dependence-free probe kernel, or any sweep point of the
+    executor that beat it (the five-graph step at large R runs the same body
+    in its persistent launch).  Efficiencies, METG(50) and the legs'
+    fractions are taken against it, so none exceeds 1."""
+    rates = [pi_probe]
+    for rec in (patterns or {}).values():
+        rates += [r["word_rounds_per_s"] for r in rec["sweep"] if r["rounds"]]
+    if sweep:
+        rates += [r["word_rounds_per_s"] for r in sweep["rows"] if r["rounds"]]
+    pi = max(rates)
+    for rec in (patterns or {}).values():
+        for r in rec["sweep"]:
+            if r["rounds"]:
+                r["efficiency"] = r["word_rounds_per_s"] / pi
+        rec["metg50_us"] = metg50([r["granularity_us"] for r in rec["sweep"] if r["rounds"]],
+                                  [r["efficiency"] for r in rec["sweep"] if r["rounds"]])
+    if sweep:
+        for r in sweep["rows"]:
+            if r["rounds"]:
+                r["efficiency"] = r["word_rounds_per_s"] / pi
+        sweep["metg50_us"] = metg50([r["granularity_us"] for r in sweep["rows"] if r["rounds"]],
+                                    [r["efficiency"] for r in sweep["rows"] if r["rounds"]])
+        sweep["peak_word_rounds_per_s"] = pi
+    for leg in legs.values():
+        if leg.get("word_rounds_per_s"):
+            leg["frac_of_mix_peak"] = leg["word_rounds_per_s"] / pi
+            leg.pop("frac_of_measured_mix_rate", None)
+    src = "probe kernel" if pi == pi_probe else "executor sweep (same body, persistent launch)"
+    return {"word_rounds_per_s": pi, "source": src, "probe_word_rounds_per_s": pi_probe}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--skip", default="", help="comma list of legs to leave out: patterns, sweep, comparators, cpu, "
-                                               "implicit, batch, serving")
+    ap.add_argument("--skip", default="", help="comma list of legs to leave out: patterns, sweep, small, comparators, "
+                                               "cpu, implicit, batch, serving, queue (the batch leg's queue timing; with "
+                                               "--workload batch, cpu and comparators leave out its oracle sample "
+                                               "and comparators)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--schedule", type=int, default=0,
                     help="with --no-tune: the batch's schedule (1 list, 2 level, 3 spread, 4 column; 0 default)")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="run only the copy-bandwidth probe (short runs under a counter profiler)")
     ap.add_argument("--comparator-steps", type=int, default=50, help="timesteps of the comparator graphs")
-    ap.add_argument("--workload", default="step", choices=["step", "implicit", "batch", "serving"],
+    ap.add_argument("--workload", default="step", choices=["step", "implicit", "batch", "serving", "alone"],
                     help="step (default): every leg, the five-graph step as headline; implicit / batch / "
-                         "serving: that leg alone on its own line")
+                         "serving / alone (one pattern graph): that leg on its own line")
+    ap.add_argument("--pattern", default="stencil", help="alone: none, stencil, fft, tree or random")
+    ap.add_argument("--dispatch", default="lists", choices=["lists", "queue"], help="alone: the dispatch")
     ap.add_argument("--graphs", type=int, default=4096, help="batch: number of graphs")
     ap.add_argument("--requests", type=int, default=4000, help="serving: measured requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: arrivals per second")
@@ -289,6 +327,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     skip = set(x for x in args.skip.split(",") if x)
+    args.skipset = skip
 
     import numpy as np
     import torch
@@ -452,7 +491,8 @@ def main():
             U = tasks_per_step * NWORDS * R
             eff = (U / (ms * 1e-3)) / pi if R else 0.0
             gran_us = ms * 1e3 * slots / tasks_per_step
-            rows.append({"rounds": R, "ms": ms, "efficiency": eff, "granularity_us": gran_us,
+            rows.append({"rounds": R, "ms": ms, "word_rounds_per_s": U / (ms * 1e-3) if R else 0.0,
+                         "efficiency": eff, "granularity_us": gran_us,
                          "frac_of_alu_peak": (U / (ms * 1e-3)) / bw.ALU_PEAK_WORD_ROUNDS if R else 0.0,
                          "launch": {k: rcfg[k] for k in ("mapping", "workers", "wg_waves", "notify", "schedule")}})
             log(f"sweep R={R}: {ms:.3f} ms eff {eff:.3f} gran {gran_us:.2f} us")
@@ -462,30 +502,32 @@ def main():
         leg_s["sweep"] = time.time() - t0
 
     # ----------------------------------------------------- small stencil
+    small = None
     t0 = time.time()
-    eg1 = wl.pattern_graph("stencil", 8, 16, seed=0, n=64, rounds=16)
-    g1 = tg.graph_from_explicit(eg1)
-    tg.tg_graph_execute(g1.handle, None, stream)
-    tg.tg_graph_wait(g1.handle)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(20):
+    if "small" not in skip:
+        eg1 = wl.pattern_graph("stencil", 8, 16, seed=0, n=64, rounds=16)
+        g1 = tg.graph_from_explicit(eg1)
         tg.tg_graph_execute(g1.handle, None, stream)
-    e1.record(stream)
-    tg.tg_graph_wait(g1.handle)
-    torch.cuda.synchronize()
-    small = {"graph": "stencil 8x16, n=64, R=16 (128 tasks, 16 levels)", "ms_per_execution": e0.elapsed_time(e1) / 20,
-             "kernel_ms": float(np.mean(tg.tg_graph_kernel_times(g1.handle, 20)))}
-    if probes.get("handoff_ns"):
-        small["latency_floor_ms"] = 16 * probes["handoff_ns"] * 1e-6
-        small["latency_frac"] = small["latency_floor_ms"] / small["kernel_ms"]
-    if "cpu" not in skip:
-        import oracle
-        r1 = oracle.exec_explicit(eg1.N, eg1.n, eg1.pred_ptr, eg1.preds, eg1.rounds, seed=0, want_payload=False)
-        small["parity"] = bool(tg.tg_graph_checksum(g1.handle) == r1["checksum"] and
-                               np.array_equal(tg.tg_graph_read_digests(g1.handle), r1["digest"]))
-    log(f"small stencil: {small}")
-    del g1
+        tg.tg_graph_wait(g1.handle)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            tg.tg_graph_execute(g1.handle, None, stream)
+        e1.record(stream)
+        tg.tg_graph_wait(g1.handle)
+        torch.cuda.synchronize()
+        small = {"graph": "stencil 8x16, n=64, R=16 (128 tasks, 16 levels)", "ms_per_execution": e0.elapsed_time(e1) / 20,
+                 "kernel_ms": float(np.mean(tg.tg_graph_kernel_times(g1.handle, 20)))}
+        if probes.get("handoff_ns"):
+            small["latency_floor_ms"] = 16 * probes["handoff_ns"] * 1e-6
+            small["latency_frac"] = small["latency_floor_ms"] / small["kernel_ms"]
+        if "cpu" not in skip:
+            import oracle
+            r1 = oracle.exec_explicit(eg1.N, eg1.n, eg1.pred_ptr, eg1.preds, eg1.rounds, seed=0, want_payload=False)
+            small["parity"] = bool(tg.tg_graph_checksum(g1.handle) == r1["checksum"] and
+                                   np.array_equal(tg.tg_graph_read_digests(g1.handle), r1["digest"]))
+        log(f"small stencil: {small}")
+        del g1
     leg_s["small"] = time.time() - t0
 
     # ------------------------------------------------------- comparators
@@ -515,6 +557,8 @@ def main():
         gc.collect()
         torch.cuda.empty_cache()
 
+    peak = (apply_peak(probes["mix_word_rounds_per_s"], patterns, sweep, legs)
+            if probes.get("mix_word_rounds_per_s") else None)
     out = {
         "metric": "tasks/sec + per-task overhead (ns) + min effective task granularity, 1 GPU",
         "value": value,
@@ -540,6 +584,7 @@ def main():
         "per_task_overhead_ns": kernel_ms_per_step * 1e6 * bcfg["workers"] / tasks_per_step,
         "throughput_ns_per_task": 1e9 / value,
         "metg50_us": sweep["metg50_us"] if sweep else None,
+        "mix_peak": peak,
         "parity": parity,
         "roofline": {
             "bound": "hbm",

@@ -55,6 +55,28 @@ def _timed_graph(g, cfg, stream, warmup, steps):
     return float(np.mean(tg.tg_graph_kernel_times(g.handle, steps)))
 
 
+# ------------------------------------------------------------------ alone
+
+def run_alone(args, stream, probes=None):
+    """One Task Bench shaped graph alone (1024 x 1000, 256-word payloads,
+    0 mix rounds) with the static lists (wavefronts x 1024, level order) or
+    the ready queue (wavefronts x 2048, tile 1): for kernel traces and
+    counters of one dispatch on one pattern."""
+    eg = wl.pattern_graph(args.pattern, 1024, 1000, seed=0, n=256, rounds=0)
+    g = tg.graph_from_explicit(eg)
+    if args.dispatch == "queue":
+        cfg = tg.make_config(mapping=1, workers=2048, dispatch=tg.TG_DISPATCH_QUEUE, tile=1)
+    else:
+        cfg = tg.make_config(mapping=1, workers=1024, schedule=tg.TG_SCHED_LEVEL)
+    ms = _timed_graph(g, cfg, stream, args.warmup, args.steps)
+    import oracle
+    ref = oracle.exec_explicit(eg.N, eg.n, eg.pred_ptr, eg.preds, 0, want_payload=False)
+    ok = bool(np.array_equal(tg.tg_graph_read_digests(g.handle), ref["digest"]))
+    return {"workload": f"{args.pattern} 1024 x 1000 alone, n=256, R=0, {args.dispatch}", "tasks": eg.N,
+            "edges": eg.E, "exec_ms": ms, "tasks_per_s": eg.N / (ms * 1e-3), "parity": ok,
+            "launch": tg.tg_graph_exec_info(g.handle)[0]}
+
+
 # ---------------------------------------------------------------- implicit
 
 def run_implicit(args, stream, probes=None):
@@ -78,9 +100,15 @@ def run_implicit(args, stream, probes=None):
         return bool(_sha(d) == gold["digest_sha256"] and _sha(A) == gold["array_sha256"] and
                     f"{tg.tg_graph_checksum(g.handle):#018x}" == gold["checksum"])
 
-    cfg, tms = tg.tg_graph_autotune(g.handle, reps=1)
-    log(f"implicit: tuned {cfg} {tms:.2f} ms")
-    ms = _timed_graph(g, None, stream, args.warmup, args.steps)
+    if getattr(args, "no_tune", False):
+        # the shape the autotuner picks for this program: gangs of eight
+        # 8-wave workgroups, level order
+        cfg = dict(mapping=3, workers=0, wg_waves=8, schedule=tg.TG_SCHED_LEVEL, gang=8)
+        ms = _timed_graph(g, tg.make_config(**cfg), stream, args.warmup, args.steps)
+    else:
+        cfg, tms = tg.tg_graph_autotune(g.handle, reps=1)
+        log(f"implicit: tuned {cfg} {tms:.2f} ms")
+        ms = _timed_graph(g, None, stream, args.warmup, args.steps)
     ok = parity()
     word_rounds = 64 * 16384 * 64 * 1024
     t1 = time.perf_counter()
@@ -190,15 +218,30 @@ def run_batch(args, stream, probes=None):
     ms = float(np.mean(kt))
     log(f"batch: one launch {ms:.1f} ms")
     tg.tg_batch_destroy(b)
-    # the same graphs with the ready-queue dispatch (timing only)
-    qb = tg.tg_batch_create([g.handle for g in gs], tg.make_config(**BATCH_QUEUE_CFG))
-    tg.tg_batch_execute(qb, stream)
-    tg.tg_batch_wait(qb)
-    tg.tg_batch_execute(qb, stream)
-    tg.tg_batch_wait(qb)
-    qms = float(np.mean(tg.tg_batch_kernel_times(qb, 1)))
-    tg.tg_batch_destroy(qb)
-    log(f"batch: one launch with the ready queue {qms:.1f} ms")
+    skip = getattr(args, "skipset", set())
+    rec = {
+        "workload": f"{len(gs)} independent graphs: W~U[8,512], T~U[8,256], five patterns, n~U{{64..1024}}, "
+                    "R~LogNormal(ln 64, 1); one persistent launch",
+        "tasks": N, "word_rounds": U, "launch": bcfg, "exec_ms": ms, "tasks_per_s": N / (ms * 1e-3),
+        "word_rounds_per_s": U / (ms * 1e-3),
+        "frac_of_measured_mix_rate": (U / (ms * 1e-3) / probes["mix_word_rounds_per_s"]
+                                      if probes and probes.get("mix_word_rounds_per_s") else None),
+        "frac_of_alu_peak": U / (ms * 1e-3) / ALU_PEAK_WORD_ROUNDS,
+        "payload_bytes": payload_bytes, "host_build_s": build_s, "layout_s": layout_s, "layout_ms": btimes,
+    }
+    if "queue" not in skip:
+        # the same graphs with the ready-queue dispatch (timing only)
+        qb = tg.tg_batch_create([g.handle for g in gs], tg.make_config(**BATCH_QUEUE_CFG))
+        tg.tg_batch_execute(qb, stream)
+        tg.tg_batch_wait(qb)
+        tg.tg_batch_execute(qb, stream)
+        tg.tg_batch_wait(qb)
+        qms = float(np.mean(tg.tg_batch_kernel_times(qb, 1)))
+        tg.tg_batch_destroy(qb)
+        log(f"batch: one launch with the ready queue {qms:.1f} ms")
+        rec["queue"] = {"launch": "queue: wavefronts x resident, tile 1", "exec_ms": qms, "lists_over_queue": ms / qms}
+    if "cpu" in skip and "comparators" in skip:
+        return rec
     # parity: stratified sample against the oracle in parallel processes
     sample = stratified_batch_sample(specs)
     tp = time.perf_counter()
@@ -233,15 +276,7 @@ def run_batch(args, stream, probes=None):
         hipg += bb
         capg += c
         sub_tasks += egs[i].N
-    return {
-        "workload": f"{len(gs)} independent graphs: W~U[8,512], T~U[8,256], five patterns, n~U{{64..1024}}, "
-                    "R~LogNormal(ln 64, 1); one persistent launch",
-        "tasks": N, "word_rounds": U, "launch": bcfg, "exec_ms": ms, "tasks_per_s": N / (ms * 1e-3),
-        "word_rounds_per_s": U / (ms * 1e-3),
-        "frac_of_measured_mix_rate": U / (ms * 1e-3) / probes["mix_word_rounds_per_s"] if probes else None,
-        "frac_of_alu_peak": U / (ms * 1e-3) / ALU_PEAK_WORD_ROUNDS,
-        "payload_bytes": payload_bytes, "host_build_s": build_s, "layout_s": layout_s, "layout_ms": btimes,
-        "queue": {"launch": "queue: wavefronts x resident, tile 1", "exec_ms": qms, "lists_over_queue": ms / qms},
+    rec.update({
         "parity": {"ok": not bad, "graphs": len(sample), "failed": bad, "oracle_processes": workers,
                    "sample": "per (pattern, payload) cell the highest-R graph and one random graph, plus the 14 "
                              f"highest-R graphs, all under {BATCH_COST_CAP:.1e} word-rounds (seed 7)"},
@@ -253,7 +288,8 @@ def run_batch(args, stream, probes=None):
             "per_task_launch_tasks_per_s": sub_tasks / (per_task * 1e-3),
             "hipgraph_dag_replay_tasks_per_s": sub_tasks / (hipg * 1e-3),
             "hipgraph_captured_replay_tasks_per_s": sub_tasks / (capg * 1e-3)},
-    }
+    })
+    return rec
 
 
 # ---------------------------------------------------------------- serving
