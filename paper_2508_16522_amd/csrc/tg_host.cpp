@@ -2645,29 +2645,41 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
     }
   }
   cand.push_back(mk(TG_MAP_WAVE, rw, 0, 1));
-  // ready-queue dispatch
-  for (uint32_t tile : {1u, 4u}) {
-    for (uint32_t w : {rw, rw / 2}) {
-      tg_exec_config c = mk(TG_MAP_WAVE, w, 0, 0);
+  // ready-queue dispatch, unless the DAG is dense (an inferred conflict DAG
+  // links each task to every later task of its region: every completion
+  // then pays a ballot and a push round over tens of out-edges, and the
+  // queue has been measured several times slower than the lists there)
+  if (g->succ.size() <= 16ull * g->N())
+    for (uint32_t tile : {1u, 4u}) {
+      for (uint32_t w : {rw, rw / 2}) {
+        tg_exec_config c = mk(TG_MAP_WAVE, w, 0, 0);
+        c.dispatch = TG_DISPATCH_QUEUE;
+        c.tile = tile;
+        cand.push_back(c);
+      }
+      tg_exec_config c = mk(TG_MAP_WORKGROUP, rg4, 4, 0);
       c.dispatch = TG_DISPATCH_QUEUE;
       c.tile = tile;
       cand.push_back(c);
     }
-    tg_exec_config c = mk(TG_MAP_WORKGROUP, rg4, 4, 0);
-    c.dispatch = TG_DISPATCH_QUEUE;
-    c.tile = tile;
-    cand.push_back(c);
-  }
   double best_t = 1e300;
   tg_exec_config best_c = cand[0];
   for (const auto& c : cand) {
     double tot = 0;
+    uint32_t timed = 0;
     for (uint32_t r = 0; r <= reps; ++r) {  // first run warms up
       if ((s = tg_graph_execute(g, &c, nullptr)) != TG_OK) return s;
       if ((s = graph_wait(g)) != TG_OK) return s;
-      if (r) tot += g->kernel_ms;
+      // a candidate whose warm-up took several times the best mean so far
+      // cannot win: its timed runs are skipped
+      if (r == 0 && g->kernel_ms > 4.0 * best_t) break;
+      if (r) {
+        tot += g->kernel_ms;
+        ++timed;
+      }
     }
-    const double mean = tot / reps;
+    if (!timed) continue;
+    const double mean = tot / timed;
     if (mean < best_t) {
       best_t = mean;
       best_c = c;
@@ -2871,16 +2883,21 @@ tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, dou
     b->lay.reset();
     if ((s = build_layout(b->graphs, c, b->lay, b->plans.get())) != TG_OK) return s;
     double tot = 0;
+    uint32_t timed = 0;
     for (uint32_t r = 0; r <= reps; ++r) {
       if ((s = tg_batch_execute(b, nullptr)) != TG_OK) return s;
       if ((s = tg_batch_wait(b)) != TG_OK) return s;
       float ms = 0;
       const uint32_t slot = (uint32_t)((b->launches - 1) % tg_batch_s::kRing);
       HIPCHK(hipEventElapsedTime(&ms, b->rk0[slot], b->rk1[slot]));
-      if (r) tot += ms;
+      if (r == 0 && ms > 4.0 * best_t) break;  // cannot win: skip the timed runs
+      if (r) {
+        tot += ms;
+        ++timed;
+      }
     }
-    if (tot / reps < best_t) {
-      best_t = tot / reps;
+    if (timed && tot / timed < best_t) {
+      best_t = tot / timed;
       best_c = c;
     }
   }

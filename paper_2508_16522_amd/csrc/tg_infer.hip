@@ -574,8 +574,16 @@ tg_status tg_infer_dag_host(uint32_t N, const uint64_t* req_ptr, const void* req
   if (e != hipSuccess) return tg_set_error(TG_EDEVICE, "hipStreamCreateWithFlags: %s", hipGetErrorString(e));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   tg_status s = TG_OK;
-  {
+  // The device memory of the finalize-time inferences is one region kept
+  // from call to call (under the lock above) and regrown, by half again,
+  // when an inference does not fit: allocating and freeing it per call cost
+  // more than the inference kernels.
+  static void* region = nullptr;
+  static size_t region_bytes = 0;
+  for (int attempt = 0;; ++attempt) {
     Workspace ws;
+    ws.base = (uint8_t*)region;
+    ws.cap = region_bytes;
     tg_region_req* d_rq = nullptr;
     uint64_t *d_req = nullptr, *d_row = nullptr;
     uint32_t* d_col = nullptr;
@@ -587,9 +595,27 @@ tg_status tg_infer_dag_host(uint32_t N, const uint64_t* req_ptr, const void* req
         (M && (e = hipMemcpyAsync(d_rq, reqs, M * sizeof(tg_region_req), hipMemcpyHostToDevice, st)) != hipSuccess) ||
         (e = hipMemcpyAsync(d_req, req_ptr, ((size_t)N + 1) * 8, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipEventRecord(e0, st)) != hipSuccess) {
-      s = tg_set_error(TG_EDEVICE, "dependence inference set-up: %s", hipGetErrorString(e));
+      s = ws.missing ? TG_ENOMEM : tg_set_error(TG_EDEVICE, "dependence inference set-up: %s", hipGetErrorString(e));
     } else {
       s = infer_core(ws, N, M, space, d_rq, d_req, 1ull << 26, st, pinned, d_row, &d_col, true, 0, &E);
+    }
+    if (s == TG_ENOMEM && ws.missing && attempt < 8) {
+      // the region was too small: wait for the stream, regrow, start again
+      (void)hipStreamSynchronize(st);
+      const size_t want = std::max<size_t>(ws.used + (size_t(64) << 20), region_bytes + region_bytes / 2);
+      if (region) (void)hipFree(region);
+      region = nullptr;
+      region_bytes = 0;
+      if ((e = hipMalloc(&region, want)) != hipSuccess) {
+        region = nullptr;
+        s = tg_set_error(TG_ENOMEM, "dependence inference: hipMalloc(%zu): %s", want, hipGetErrorString(e));
+        break;
+      }
+      region_bytes = want;
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      e0 = e1 = nullptr;
+      continue;
     }
     if (s == TG_OK) {
       res.col.resize(E);
@@ -604,6 +630,7 @@ tg_status tg_infer_dag_host(uint32_t N, const uint64_t* req_ptr, const void* req
       }
     }
     (void)hipStreamSynchronize(st);
+    break;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
