@@ -61,23 +61,30 @@ def _halo_rows_job(spec):
     return j0, counts, (np.concatenate(cols) if cols else np.zeros(0, np.uint32))
 
 
-def _pool(workers):
-    return mp.get_context("spawn").Pool(processes=workers)
+def _map(fn, jobs, workers):
+    """fn over jobs in `workers` spawned processes; the workers have exited
+    when it returns (closed and joined, not terminated)."""
+    p = mp.get_context("spawn").Pool(processes=workers)
+    try:
+        out = p.map(fn, list(jobs), chunksize=1)
+        p.close()
+        p.join()
+        return out
+    except BaseException:
+        p.terminate()
+        p.join()
+        raise
 
 
 def explicit_many(specs, workers=None):
     """specs: (pattern, W, T, seed, n, rounds) tuples.  Returns, in order,
     (digest array, checksum, oracle seconds) per spec."""
-    workers = workers or default_workers()
-    with _pool(workers) as p:
-        return p.map(_explicit_job, list(specs), chunksize=1)
+    return _map(_explicit_job, specs, workers or default_workers())
 
 
 def implicit_many(specs, workers=None):
     """specs: (P, S, iters, seed, rounds) halo programs."""
-    workers = workers or default_workers()
-    with _pool(workers) as p:
-        return p.map(_implicit_job, list(specs), chunksize=1)
+    return _map(_implicit_job, specs, workers or default_workers())
 
 
 def halo_conflict_dag(P, S, iters, seed=0, workers=None, chunk=2048):
@@ -87,8 +94,7 @@ def halo_conflict_dag(P, S, iters, seed=0, workers=None, chunk=2048):
     N = P * iters
     workers = workers or default_workers()
     jobs = [(P, S, iters, seed, j0, min(N, j0 + chunk)) for j0 in range(0, N, chunk)]
-    with _pool(workers) as p:
-        parts = p.map(_halo_rows_job, jobs, chunksize=1)
+    parts = _map(_halo_rows_job, jobs, workers)
     parts.sort(key=lambda x: x[0])
     row_ptr = np.zeros(N + 1, np.uint64)
     row_ptr[1:] = np.cumsum(np.concatenate([c for _, c, _ in parts]))
