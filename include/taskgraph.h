@@ -284,15 +284,35 @@ tg_status tg_graph_read_exec_dag(tg_graph g, uint64_t* row_ptr, uint32_t* col, u
  * out_col: capacity row_ptr[n]; rows come out ascending; *out_e = edges kept.
  * Host memory only; cost grows with the sum over edges i -> k of i's
  * in-degree.  TG_EINVAL for an edge that does not go forward.
- * tg_graph_reduce_edges: apply it to a finalised implicit graph's inferred
- * DAG for execution (fewer counter decrements, identical results: an
- * implicit task's inputs come from the shared array, not from its
- * predecessors); tg_graph_read_dag keeps returning the full inferred DAG.
+ * tg_graph_reduce_edges: execute a finalised implicit graph on the two-hop
+ * reduction of its last-user DAG (tg_last_user_dag below), which orders the
+ * tasks as the inferred DAG does (fewer counter decrements, identical
+ * results: an implicit task's inputs come from the shared array, not from
+ * its predecessors); tg_graph_read_dag keeps returning the full inferred DAG.
  * *removed (may be NULL) = edges dropped.  TG_EINVAL for explicit graphs,
  * whose predecessor sets are task inputs. */
 tg_status tg_reduce_dag(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, uint64_t* out_row_ptr,
                         uint32_t* out_col, uint64_t* out_e);
 tg_status tg_graph_reduce_edges(tg_graph g, uint64_t* removed);
+/* Last-user dependences of an implicit program (Section 5: the runtime must
+ * order conflicting tasks as sequential program order does, and need not
+ * record every conflicting pair).  Tasks are visited in program order; each
+ * element's history is its last writer and the tasks that read it since.  A
+ * task reading an element depends on its last writer; a task writing it
+ * depends on the last writer and every reader since.  Every edge joins two
+ * conflicting tasks, and every conflicting pair is joined by a path, so the
+ * DAG orders the tasks exactly as the inferred conflict DAG does, with a few
+ * edges per task instead of one per conflicting pair.
+ *   n        : tasks; req_ptr (host, n + 1 u64, req_ptr[0] = 0, ascending)
+ *              and reqs (host, req_ptr[n] records) as for
+ *              tg_task_add_regions_many.
+ *   out_row_ptr : host, n + 1 u64, written: out-edge CSR, rows ascending.
+ *   out_col  : host, cap_e u32, written.
+ *   *out_e   : edges of the DAG (also on TG_ENOMEM, when it exceeds cap_e).
+ * TG_EINVAL for NULL arguments, lo > hi or an unknown privilege.
+ * tg_graph_reduce_edges executes the two-hop reduction of this DAG. */
+tg_status tg_last_user_dag(uint32_t n, const uint64_t* req_ptr, const tg_region_req* reqs, uint64_t* out_row_ptr,
+                           uint32_t* out_col, uint64_t cap_e, uint64_t* out_e);
 
 /* Dependence inference on device-resident requirements (Section 2: tasks
  * declare the data they access and the runtime discovers the dependences;

@@ -2420,6 +2420,101 @@ tg_status tg_graph_read_exec_dag(tg_graph g, uint64_t* row_ptr, uint32_t* col, u
   return TG_OK;
 }
 
+// Last-user dependences of an implicit program (Section 5: dependences only
+// have to order conflicting tasks as program order does).  Walks the tasks in
+// program order over a map of element runs that share one history: the last
+// task that wrote the run and the tasks that read it since.  A task that
+// reads a run depends on its last writer; a task that writes it depends on
+// the last writer and every reader since, and becomes the run's only user.
+// Every edge joins two conflicting tasks, and every conflicting pair j < k is
+// joined by a path through the writers of a shared element between them, so
+// the order imposed is the conflict DAG's.  Out-edge CSR, rows ascending.
+static void last_user_dag(uint32_t N, const uint64_t* req_ptr, const tg_region_req* reqs,
+                          std::vector<uint64_t>& rp, std::vector<uint32_t>& cl) {
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  struct Run {
+    uint64_t hi;
+    uint32_t writer;
+    std::vector<uint32_t> readers;  // ascending, no repeats
+  };
+  std::map<uint64_t, Run> runs;  // key: first element of the run
+  runs.emplace(0, Run{UINT64_MAX, kNone, {}});
+  auto split = [&](uint64_t x) {  // make x the start of a run
+    auto it = std::prev(runs.upper_bound(x));
+    if (it->first == x) return;
+    Run tail{it->second.hi, it->second.writer, it->second.readers};
+    it->second.hi = x;
+    runs.emplace_hint(std::next(it), x, std::move(tail));
+  };
+  std::vector<uint64_t> pp(N + 1, 0);
+  std::vector<uint32_t> pr, preds;
+  for (uint32_t k = 0; k < N; ++k) {
+    preds.clear();
+    for (uint64_t a = req_ptr[k]; a < req_ptr[k + 1]; ++a) {
+      const tg_region_req& q = reqs[a];
+      if (q.lo >= q.hi) continue;
+      split(q.lo);
+      if (q.hi != UINT64_MAX) split(q.hi);
+      auto it = runs.find(q.lo);
+      if (q.priv == TG_RW) {
+        for (auto jt = it; jt != runs.end() && jt->first < q.hi; ++jt) {
+          if (jt->second.writer != kNone) preds.push_back(jt->second.writer);
+          preds.insert(preds.end(), jt->second.readers.begin(), jt->second.readers.end());
+        }
+        // the written interval becomes one run whose only user is k
+        const uint64_t hi = q.hi;
+        auto end = runs.lower_bound(hi);
+        runs.erase(it, end);
+        runs.emplace(q.lo, Run{hi, k, {}});
+      } else {
+        for (auto jt = it; jt != runs.end() && jt->first < q.hi; ++jt) {
+          if (jt->second.writer != kNone) preds.push_back(jt->second.writer);
+          std::vector<uint32_t>& rd = jt->second.readers;
+          if (rd.empty() || rd.back() != k) rd.push_back(k);
+        }
+      }
+    }
+    std::sort(preds.begin(), preds.end());
+    preds.erase(std::unique(preds.begin(), preds.end()), preds.end());
+    while (!preds.empty() && preds.back() == k) preds.pop_back();  // its own earlier interval
+    pr.insert(pr.end(), preds.begin(), preds.end());
+    pp[k + 1] = pr.size();
+  }
+  // predecessor rows -> successor rows (ascending: k is visited in order)
+  rp.assign(N + 1, 0);
+  for (uint32_t j : pr) rp[j + 1]++;
+  for (uint32_t j = 0; j < N; ++j) rp[j + 1] += rp[j];
+  cl.resize(pr.size());
+  std::vector<uint64_t> fill(rp.begin(), rp.end() - 1);
+  for (uint32_t k = 0; k < N; ++k)
+    for (uint64_t x = pp[k]; x < pp[k + 1]; ++x) cl[fill[pr[x]]++] = k;
+}
+
+tg_status tg_last_user_dag(uint32_t n, const uint64_t* req_ptr, const tg_region_req* reqs, uint64_t* out_row_ptr,
+                           uint32_t* out_col, uint64_t cap_e, uint64_t* out_e) {
+  if (!req_ptr || !out_row_ptr || !out_e) return fail(TG_EINVAL, "NULL argument");
+  if (req_ptr[0] != 0) return fail(TG_EINVAL, "req_ptr[0] = %llu, not 0", (unsigned long long)req_ptr[0]);
+  for (uint32_t k = 0; k < n; ++k)
+    if (req_ptr[k + 1] < req_ptr[k]) return fail(TG_EINVAL, "req_ptr not ascending at %u", k);
+  if (req_ptr[n] && !reqs) return fail(TG_EINVAL, "reqs is NULL");
+  for (uint64_t a = 0; a < req_ptr[n]; ++a) {
+    if (reqs[a].lo > reqs[a].hi) return fail(TG_EINVAL, "requirement %llu: lo > hi", (unsigned long long)a);
+    if (reqs[a].priv != TG_RO && reqs[a].priv != TG_RW)
+      return fail(TG_EINVAL, "requirement %llu: unknown privilege %u", (unsigned long long)a, reqs[a].priv);
+  }
+  std::vector<uint64_t> rp;
+  std::vector<uint32_t> cl;
+  last_user_dag(n, req_ptr, reqs, rp, cl);
+  *out_e = cl.size();
+  if (cl.size() > cap_e) return fail(TG_ENOMEM, "col capacity %llu < %zu edges", (unsigned long long)cap_e, cl.size());
+  memcpy(out_row_ptr, rp.data(), (n + 1) * sizeof(uint64_t));
+  if (!cl.empty()) {
+    if (!out_col) return fail(TG_EINVAL, "out_col is NULL");
+    memcpy(out_col, cl.data(), cl.size() * 4);
+  }
+  return TG_OK;
+}
+
 tg_status tg_graph_reduce_edges(tg_graph g, uint64_t* removed) {
   if (!g) return fail(TG_EINVAL, "graph is NULL");
   if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
@@ -2432,10 +2527,15 @@ tg_status tg_graph_reduce_edges(tg_graph g, uint64_t* removed) {
     return TG_OK;
   }
   const uint32_t N = g->N();
+  // the last-user DAG orders the tasks as the inferred DAG does with a few
+  // edges per task; the two-hop pass then drops what paths imply
+  std::vector<uint64_t> lrp;
+  std::vector<uint32_t> lcl;
+  last_user_dag(N, g->req_ptr.data(), g->reqs.data(), lrp, lcl);
   std::vector<uint64_t> rp(N + 1);
-  std::vector<uint32_t> cl(g->succ.size());
+  std::vector<uint32_t> cl(lcl.size());
   uint64_t e = 0;
-  if ((s = tg_reduce_dag(N, g->succ_ptr.data(), g->succ.data(), rp.data(), cl.data(), &e)) != TG_OK) return s;
+  if ((s = tg_reduce_dag(N, lrp.data(), lcl.data(), rp.data(), cl.data(), &e)) != TG_OK) return s;
   cl.resize(e);
   g->full_succ_ptr.swap(g->succ_ptr);
   g->full_succ.swap(g->succ);

@@ -41,7 +41,7 @@ EXPORTS = (
     "tg_graph_kernel_ms", "tg_graph_autotune", "tg_probe", "tg_graph_kernel_times", "tg_graph_set_rounds",
     "tg_server_create", "tg_server_submit", "tg_server_wait", "tg_server_stats", "tg_server_destroy",
     "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
-    "tg_graph_execute_after", "tg_reduce_dag", "tg_graph_reduce_edges",
+    "tg_graph_execute_after", "tg_reduce_dag", "tg_last_user_dag", "tg_graph_reduce_edges",
     "tg_graph_set_retention", "tg_graph_payload_slots", "tg_graph_read_exec_dag", "tg_emulate_queue",
     "tg_infer_dag", "tg_infer_dag_noalloc", "tg_server_configure",
 )
@@ -131,6 +131,7 @@ def load() -> ctypes.CDLL:
         "tg_batch_autotune": (i32, [G, u32, P, P]),
         "tg_graph_execute_after": (i32, [G, P, P, P, u32, P]),
         "tg_reduce_dag": (i32, [u32, P, P, P, P, P]),
+        "tg_last_user_dag": (i32, [u32, P, P, P, P, u64, P]),
         "tg_graph_reduce_edges": (i32, [G, P]),
         "tg_graph_set_retention": (i32, [G, u32]),
         "tg_graph_payload_slots": (i32, [G, P, P, P]),
@@ -520,9 +521,30 @@ def tg_reduce_dag(row_ptr, col):
     return orp, ocl[:e.value]
 
 
+def tg_last_user_dag(req_ptr, reqs: np.ndarray):
+    """Last-user dependences of an implicit program given as requirement rows
+    (host): returns the out-edge CSR (row_ptr, col)."""
+    rp = np.ascontiguousarray(req_ptr, dtype=np.uint64)
+    r = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    n = rp.size - 1
+    orp = np.zeros(n + 1, np.uint64)
+    e = ctypes.c_uint64()
+    cap = max(int(r.size) * 4, 16)
+    while True:
+        ocl = np.zeros(cap, np.uint32)
+        st = load().tg_last_user_dag(n, _ptr(rp), _ptr(r) if r.size else None, _ptr(orp), _ptr(ocl), cap,
+                                     ctypes.byref(e))
+        if st == TG_ENOMEM and e.value > cap:
+            cap = int(e.value)
+            continue
+        _check(st, "tg_last_user_dag")
+        return orp, ocl[:e.value]
+
+
 def tg_graph_reduce_edges(g) -> int:
-    """Execute an implicit graph on its two-hop-reduced inferred DAG; returns
-    the number of edges dropped (tg_graph_read_dag still returns all)."""
+    """Execute an implicit graph on its reduced DAG (the two-hop reduction of
+    its last-user DAG); returns the number of inferred edges not executed
+    (tg_graph_read_dag still returns all)."""
     removed = ctypes.c_uint64()
     _check(load().tg_graph_reduce_edges(g, ctypes.byref(removed)), "tg_graph_reduce_edges")
     return removed.value

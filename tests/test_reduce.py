@@ -75,3 +75,59 @@ def test_chain_with_shortcuts_and_errors(tglib):
     # empty graph
     orp, ocl = tg.tg_reduce_dag(np.zeros(4, np.uint64), np.zeros(0, np.uint32))
     assert orp.tolist() == [0, 0, 0, 0] and ocl.size == 0
+
+
+def _lu(ig):
+    return tg.tg_last_user_dag(ig.req_ptr, tg.reqs_array(ig.lo, ig.hi, ig.priv))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_last_user_dag_orders_like_the_conflict_dag(tglib, seed):
+    """Every last-user edge joins two conflicting tasks (it is an edge of the
+    brute-force conflict DAG) and the two DAGs have the same reachability."""
+    rng = np.random.default_rng(100 + seed)
+    N, space = (120, 200) if seed % 2 else (90, 60)  # a small space: many overlaps
+    ig = wl.random_regions(N, space, 1 + seed % 4, 10 + 5 * seed, rng, seed=seed)
+    rp, cl = _dag(ig)
+    lrp, lcl = _lu(ig)
+    full, lu = _edges(rp, cl), _edges(lrp, lcl)
+    assert lu <= full
+    assert (_closure(ig.N, rp, cl) == _closure(ig.N, lrp, lcl)).all()
+    assert len(lu) < len(full)
+    for j in range(ig.N):  # rows ascending, no repeats
+        row = lcl[int(lrp[j]):int(lrp[j + 1])]
+        assert np.all(np.diff(row.astype(np.int64)) > 0)
+
+
+@pytest.mark.parametrize("P,S,iters", [(8, 128, 6), (16, 256, 5), (64, 256, 8)])
+def test_last_user_dag_of_halo_program(tglib, P, S, iters):
+    """On the halo programs the two-hop reduction of the last-user DAG is the
+    exact transitive reduction of the conflict DAG, (P-1)(2 iters - 1) edges."""
+    ig = wl.halo_graph(P, S, iters, seed=3)
+    rp, cl = _dag(ig)
+    lrp, lcl = _lu(ig)
+    assert _edges(lrp, lcl) <= _edges(rp, cl)
+    orp, ocl = tg.tg_reduce_dag(lrp, lcl)
+    assert _edges(orp, ocl) == _exact_tr(ig.N, rp, cl)
+    assert len(ocl) == (P - 1) * (2 * iters - 1)
+
+
+def test_last_user_dag_small_cases_and_errors(tglib):
+    RO, RW = tg.TG_RO, tg.TG_RW
+    # t0 writes [0,10); t1, t2 read parts of it; t3 writes [5,6): depends on
+    # the last writer t0 and on the readers since that touch element 5 (t1);
+    # t4 reads [0,10): last writers t0 (elements 0..4, 6..9) and t3 (5); an
+    # empty interval touches nothing
+    reqs = tg.reqs_array([0, 0, 7, 5, 0, 3], [10, 6, 9, 6, 10, 3], [RW, RO, RO, RW, RO, RW])
+    req_ptr = np.array([0, 1, 2, 3, 4, 5, 6], np.uint64)
+    rp, cl = tg.tg_last_user_dag(req_ptr, reqs)
+    assert _edges(rp, cl) == {(0, 1), (0, 2), (0, 3), (1, 3), (0, 4), (3, 4)}
+    # no tasks, and tasks without requirements
+    rp, cl = tg.tg_last_user_dag(np.zeros(1, np.uint64), np.zeros(0, tg.REQ_DTYPE))
+    assert rp.tolist() == [0] and cl.size == 0
+    rp, cl = tg.tg_last_user_dag(np.zeros(4, np.uint64), np.zeros(0, tg.REQ_DTYPE))
+    assert rp.tolist() == [0, 0, 0, 0] and cl.size == 0
+    with pytest.raises(tg.TaskGraphError):
+        tg.tg_last_user_dag(np.array([0, 1], np.uint64), tg.reqs_array([5], [4], [RO]))
+    with pytest.raises(tg.TaskGraphError):
+        tg.tg_last_user_dag(np.array([0, 1], np.uint64), tg.reqs_array([0], [4], [7]))
