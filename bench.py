@@ -321,6 +321,11 @@ def main():
     ap.add_argument("--max-batch", type=int, default=64, help="serving: most requests per launch")
     ap.add_argument("--server-dispatch", default="queue", choices=["queue", "lists"],
                     help="serving: ready queue with device-built records (default) or host-planned lists")
+    ap.add_argument("--full-dags", action="store_true",
+                    help="serving: implicit requests execute their full inferred DAG instead of the reduced one")
+    ap.add_argument("--retention", default="sinks", choices=["all", "sinks"],
+                    help="batch and serving: explicit graphs keep every payload (all) or reuse payload memory "
+                         "once read, keeping the sinks' payloads (sinks, default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the executor runs on one GPU only (it is single-device); use --gpus 1",

@@ -79,6 +79,26 @@ def run_alone(args, stream, probes=None):
 
 # ---------------------------------------------------------------- implicit
 
+RETENTION = {"all": tg.TG_KEEP_ALL, "sinks": tg.TG_KEEP_SINKS}
+
+
+def request_graph(x, retention="sinks", reduce_implicit=True):
+    """A graph of the batch or serving workloads in the form the benchmark
+    runs it: explicit graphs reuse payload memory once every reader has run
+    (keeping the sinks' payloads) unless retention is "all"; implicit graphs
+    execute the two-hop reduction of their last-user DAG unless
+    reduce_implicit is false (the inferred DAG is kept for reading)."""
+    if isinstance(x, wl.ImplicitGraph):
+        h = tg.graph_from_implicit(x)
+        h.inferred_edges = tg.tg_graph_num_edges(h.handle)
+        if reduce_implicit:
+            tg.tg_graph_reduce_edges(h.handle)
+        return h
+    h = tg.graph_from_explicit(x, retention=RETENTION[retention])
+    h.inferred_edges = x.E
+    return h
+
+
 def run_implicit(args, stream, probes=None):
     """2^16 tasks over 2^24 elements in 1024 subregions, halos 1..64, R = 64:
     device inference (timed), then execution (autotuned launch shape), on
@@ -195,17 +215,19 @@ def run_batch(args, stream, probes=None):
     with a stratified oracle sample and the plain comparators."""
     from oracle import parallel as opar
     specs = wl.batch_manifest(args.graphs, seed=0)
+    retention = getattr(args, "retention", "sinks")
     t0 = time.perf_counter()
     egs, gs = [], []
     for i, sp in enumerate(specs):
         eg = wl.pattern_graph(sp.pattern, sp.W, sp.T, seed=sp.seed, n=sp.n, rounds=sp.rounds)
         egs.append(eg)
-        gs.append(tg.graph_from_explicit(eg))
+        gs.append(request_graph(eg, retention))
         if i % 1024 == 0:
             log(f"batch: built {i} graphs, {time.perf_counter() - t0:.0f} s")
     N = sum(eg.N for eg in egs)
     U = sum(eg.N * eg.n * eg.rounds for eg in egs)
-    payload_bytes = sum(eg.N * eg.n * 4 for eg in egs)
+    payload_bytes_all = sum(eg.N * eg.n * 4 for eg in egs)
+    payload_bytes = sum(tg.tg_graph_payload_slots(g.handle)[2] for g in gs)
     build_s = time.perf_counter() - t0
     log(f"batch: {len(gs)} graphs, {N} tasks, {U:.3e} word-rounds; host build {build_s:.0f} s")
     t1 = time.perf_counter()
@@ -232,7 +254,8 @@ def run_batch(args, stream, probes=None):
         "frac_of_measured_mix_rate": (U / (ms * 1e-3) / probes["mix_word_rounds_per_s"]
                                       if probes and probes.get("mix_word_rounds_per_s") else None),
         "frac_of_alu_peak": U / (ms * 1e-3) / ALU_PEAK_WORD_ROUNDS,
-        "payload_bytes": payload_bytes, "host_build_s": build_s, "layout_s": layout_s, "layout_ms": btimes,
+        "retention": retention, "payload_bytes": payload_bytes, "payload_bytes_keep_all": payload_bytes_all,
+        "host_build_s": build_s, "layout_s": layout_s, "layout_ms": btimes,
     }
     if "queue" not in skip:
         # the same graphs with the ready-queue dispatch (timing only)
@@ -309,18 +332,20 @@ def run_serving(args, stream, probes=None):
     t0 = time.perf_counter()
     graphs, handles = [], []
     edges_full, edges_run = 0, 0
+    # implicit requests execute the two-hop reduction of their last-user DAG
+    # (same order, a few edges per task) unless asked to run the full DAG
+    reduce_implicit = not getattr(args, "full_dags", False)
+    retention = getattr(args, "retention", "sinks")
+    payload_run, payload_all = 0, 0
     for i, r in enumerate(reqs):
         x = wl.build_request(r)
         graphs.append(x)
-        if isinstance(x, wl.ImplicitGraph):
-            h = tg.graph_from_implicit(x)
-            e = tg.tg_graph_num_edges(h.handle)  # the full inferred DAG
-            edges_full += e
-            edges_run += e
-        else:
-            h = tg.graph_from_explicit(x)
-            edges_full += x.E
-            edges_run += x.E
+        h = request_graph(x, retention, reduce_implicit)
+        edges_run += tg.tg_graph_num_edges(h.handle)
+        edges_full += h.inferred_edges
+        if not isinstance(x, wl.ImplicitGraph):
+            payload_run += tg.tg_graph_payload_slots(h.handle)[2]
+            payload_all += x.N * x.n * 4
         handles.append(h)
         if i % 1000 == 0:
             log(f"serving: built {i} requests, {time.perf_counter() - t0:.0f} s")
@@ -378,7 +403,9 @@ def run_serving(args, stream, probes=None):
         "service_ms": {"p50": float(np.percentile(serv, 50)), "p99": float(np.percentile(serv, 99))},
         "server_config": getattr(args, "server_dispatch", "queue"),
         "offered_req_per_s": args.rate, "server": stats,
-        "edges": edges_run,
+        "edges": edges_run, "edges_inferred": edges_full, "retention": retention,
+        "explicit_payload_bytes": payload_run, "explicit_payload_bytes_keep_all": payload_all,
+        "implicit_dag": "reduced (last-user, two-hop)" if reduce_implicit else "full inferred DAG",
         "parity": {"ok": not bad, "requests": len(pick), "failed": bad,
                    "sample": "64 requests drawn with seed 1 from all submitted"},
     }

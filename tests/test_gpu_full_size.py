@@ -22,7 +22,7 @@ import time
 import numpy as np
 import pytest
 
-from bench_workloads import BATCH_CFG, stratified_batch_sample
+from bench_workloads import BATCH_CFG, request_graph, stratified_batch_sample
 from oracle import parallel as opar
 from paper_2508_16522_amd import taskgraph as tg
 from paper_2508_16522_amd import workloads as wl
@@ -90,8 +90,8 @@ def test_batch_4096_graphs_stratified(gpu):
     sample = stratified_batch_sample(specs)
     cells = {(specs[i].pattern, specs[i].n) for i in sample}
     assert len(sample) >= 64 and len(cells) == 25
-    gs = [tg.graph_from_explicit(wl.pattern_graph(s.pattern, s.W, s.T, seed=s.seed, n=s.n, rounds=s.rounds))
-          for s in specs]
+    # as the benchmark runs them: payload memory reused once read
+    gs = [request_graph(wl.pattern_graph(s.pattern, s.W, s.T, seed=s.seed, n=s.n, rounds=s.rounds)) for s in specs]
     b = tg.tg_batch_create([g.handle for g in gs], tg.make_config(**BATCH_CFG))
     try:
         tg.tg_batch_execute(b)
@@ -115,8 +115,9 @@ def test_serving_real_size_distribution(gpu):
     every request's digests and checksum equal the oracle's."""
     reqs = wl.serving_manifest(256, rate=2000.0, seed=3, max_tasks=1 << 15)
     graphs = [wl.build_request(r) for r in reqs]
-    handles = [tg.graph_from_implicit(x) if isinstance(x, wl.ImplicitGraph) else tg.graph_from_explicit(x)
-               for x in graphs]
+    # as the benchmark serves them: explicit requests reuse payload memory,
+    # implicit requests execute their reduced DAG
+    handles = [request_graph(x) for x in graphs]
     srv = tg.tg_server_create(64 << 30, slots=4, max_batch=64)
     tickets = [None] * len(reqs)
     try:

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+from bench_workloads import request_graph
 from paper_2508_16522_amd import taskgraph as tg
 from paper_2508_16522_amd import workloads as wl
 
@@ -29,10 +30,16 @@ def _small_requests(num, seed=0):
     return reqs
 
 
-def _build(reqs):
+def _build(reqs, form="plain"):
+    """plain: every payload kept, implicit graphs on their full inferred DAG;
+    compact: the benchmark's form (payload memory reused once read, keeping
+    the sinks'; implicit graphs on their reduced DAG)."""
     graphs = [wl.build_request(r) for r in reqs]
-    handles = [tg.graph_from_implicit(x) if isinstance(x, wl.ImplicitGraph) else tg.graph_from_explicit(x)
-               for x in graphs]
+    if form == "compact":
+        handles = [request_graph(x) for x in graphs]
+    else:
+        handles = [tg.graph_from_implicit(x) if isinstance(x, wl.ImplicitGraph) else tg.graph_from_explicit(x)
+                   for x in graphs]
     return graphs, handles
 
 
@@ -44,10 +51,11 @@ SERVER_CONFIGS = {
 
 
 @pytest.mark.parametrize("config", list(SERVER_CONFIGS))
-@pytest.mark.parametrize("slots,max_batch", [(4, 8), (1, 1), (2, 64)])
-def test_mix_equals_alone_and_oracle(gpu, slots, max_batch, config):
-    reqs = _small_requests(40, seed=slots)
-    graphs, handles = _build(reqs)
+@pytest.mark.parametrize("slots,max_batch,form", [(4, 8, "plain"), (1, 1, "plain"), (2, 64, "plain"),
+                                                  (4, 8, "compact"), (2, 64, "compact")])
+def test_mix_equals_alone_and_oracle(gpu, slots, max_batch, form, config):
+    reqs = _small_requests(40, seed=slots + (10 if form == "compact" else 0))
+    graphs, handles = _build(reqs, form)
     srv = tg.tg_server_create(8 << 30, slots=slots, max_batch=max_batch)
     if SERVER_CONFIGS[config] is not None:
         tg.tg_server_configure(srv, SERVER_CONFIGS[config])
