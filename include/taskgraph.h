@@ -71,6 +71,7 @@ enum {
 typedef struct tg_graph_s* tg_graph;
 typedef struct tg_batch_s* tg_batch;
 typedef struct tg_server_s* tg_server;
+typedef struct tg_flag_s* tg_flag;
 typedef uint32_t tg_event; /* creation index of the producing task in its graph */
 
 enum { TG_EXPLICIT = 1, TG_IMPLICIT = 2 };
@@ -253,6 +254,42 @@ tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfg, void* stream);
  * tg_graph_execute. */
 tg_status tg_graph_execute_after(tg_graph g, const tg_exec_config* cfg, void* stream, void* const* pre, uint32_t npre,
                                  void* post);
+
+/* Condition flags: pre- and post-condition vertices that need no stream
+ * ordering (Section 4.1: a compiled graph's pre-conditions may be satisfied by
+ * the host or by other work at any time, and its post-condition tells whoever
+ * waits that the whole graph has finished; Section 4.3: edges between the
+ * device and the host).  A flag is one 32-bit word in pinned, coherent host
+ * memory mapped for the device, initially 0.
+ *   tg_flag_create  : *out receives the flag.  TG_EDEVICE if pinned memory
+ *                     cannot be allocated or mapped.
+ *   tg_flag_destroy : frees it; no launch in flight may still use it.
+ *   tg_flag_set     : host store of value (sequentially consistent).
+ *   tg_flag_read    : host load.
+ *   tg_flag_wait    : host wait until the flag holds at least value;
+ *                     TG_ETIMEOUT after timeout_ms.
+ * tg_graph_execute_when: as tg_graph_execute, but the graph's tasks start only
+ * once every pre[i] holds at least pre_value[i] (npre <= 8; checked on the
+ * device, so the host or a graph running on another stream may meet the
+ * condition at any time after the call), and when the whole graph has
+ * finished `post` (may be NULL) is set to post_value on the device.  The wait
+ * is bounded by the configuration's watchdog interval: if a condition is not
+ * met by then the execution is abandoned (no task runs, `post` is left
+ * unchanged) and tg_graph_wait reports TG_ETIMEOUT naming the flag.  A launch
+ * that waits on a flag holds one wavefront while it waits; its executor
+ * occupies the device once the condition holds, so launches that meet the
+ * condition should be issued first or fit beside it (same launch shape,
+ * workers together within the calibrated capacity), else the residency
+ * ordering between streams makes them wait for the waiting launch until its
+ * wait times out.  Errors: TG_EINVAL for npre > 8 or NULL flags, else as
+ * tg_graph_execute. */
+tg_status tg_flag_create(tg_flag* out);
+tg_status tg_flag_destroy(tg_flag f);
+tg_status tg_flag_set(tg_flag f, uint32_t value);
+tg_status tg_flag_read(tg_flag f, uint32_t* value);
+tg_status tg_flag_wait(tg_flag f, uint32_t value, uint32_t timeout_ms);
+tg_status tg_graph_execute_when(tg_graph g, const tg_exec_config* cfg, void* stream, const tg_flag* pre,
+                                const uint32_t* pre_value, uint32_t npre, tg_flag post, uint32_t post_value);
 
 /* Block until the last execution finished; surfaces watchdog aborts
  * (TG_ETIMEOUT) and deferred HIP errors (TG_EDEVICE). */

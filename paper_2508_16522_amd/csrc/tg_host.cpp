@@ -1713,8 +1713,17 @@ bool same_layout(const Config& a, const Config& b) {
 // drop finished launches, make `st` wait for the in-flight launches this one
 // cannot overlap (tg_ledger.h), issue the kernels, record the completion
 // event and enter the launch.
+// External conditions of one launch: pre-condition flags checked on the
+// device before the executor starts, and a flag set on the device after it.
+struct LaunchConds {
+  tg::FlagWait pre{};
+  uint32_t* post = nullptr;  // device address of the post-condition flag, or null
+  uint32_t post_value = 0;
+};
+
 tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph>& gs, hipStream_t st,
-                        hipEvent_t before_kernel = nullptr, hipEvent_t ring0 = nullptr, hipEvent_t ring1 = nullptr) {
+                        hipEvent_t before_kernel = nullptr, hipEvent_t ring0 = nullptr, hipEvent_t ring1 = nullptr,
+                        const LaunchConds* conds = nullptr) {
   std::lock_guard<std::mutex> ledger_lk(g_ledger_mu);
   for (size_t i = 0; i < g_flights.size();) {
     if (g_flights[i].key != &L && hipEventQuery(g_flight_ev[i]) == hipErrorNotReady) {
@@ -1767,6 +1776,8 @@ tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph
   }
   HIPCHK(tg::launch_reset(P, st));
   if (queue) HIPCHK(tg::launch_queue_reset(P, st));
+  P.gated = conds && conds->pre.n ? 1u : 0u;
+  if (P.gated) HIPCHK(tg::launch_wait_flags(conds->pre, P.ctrl, P.watchdog_ticks, st));
   if (before_kernel) HIPCHK(hipEventRecord(before_kernel, st));
   if (ring0) HIPCHK(hipEventRecord(ring0, st));
   if (L.npos) {
@@ -1774,6 +1785,7 @@ tg_status launch_layout(Layout& L, const Config& cfg, const std::vector<tg_graph
     else HIPCHK(tg::launch_exec(P, cfg.mapping, cfg.wg_waves, L.grid_blocks, st));
   }
   if (ring1) HIPCHK(hipEventRecord(ring1, st));
+  if (conds && conds->post) HIPCHK(tg::launch_set_flag(conds->post, conds->post_value, P.ctrl, st));
   HIPCHK(hipEventRecord(L.ev_done, st));
   g_flights.push_back(me);
   g_flight_ev.push_back(L.ev_done);
@@ -1789,11 +1801,14 @@ tg_status check_abort(Layout* L) {
     // the host has now seen these aborts: clear them so the next counter
     // reset does not carry them forward
     const uint32_t zero[2] = {0, 0};
-    HIPCHK(hipMemcpy(&L->ctrl.as<tg::Ctrl>()->sticky, zero, 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(&L->ctrl.as<tg::Ctrl>()->sticky, zero, 8, hipMemcpyHostToDevice));  // sticky, precond
     HIPCHK(hipMemcpy(&L->ctrl.as<tg::Ctrl>()->abort, zero, 4, hipMemcpyHostToDevice));
     tg_status s = null_stream_fence();
     if (s != TG_OK) return s;
   }
+  if (c.abort && c.precond)
+    return fail(TG_ETIMEOUT, "pre-condition flag %u was not met within the watchdog interval: no task ran",
+                c.precond - 1);
   if (c.abort)
     return fail(TG_ETIMEOUT,
                 "executor watchdog aborted the launch (no progress): worker %u of %u stuck at list entry %u/%u "
@@ -2252,7 +2267,13 @@ tg_status tg_graph_finalize(tg_graph g) {
   return TG_OK;
 }
 
+static tg_status graph_execute(tg_graph g, const tg_exec_config* cfgp, void* stream, const LaunchConds* conds);
+
 tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfgp, void* stream) {
+  return graph_execute(g, cfgp, stream, nullptr);
+}
+
+static tg_status graph_execute(tg_graph g, const tg_exec_config* cfgp, void* stream, const LaunchConds* conds) {
   if (!g) return fail(TG_EINVAL, "graph is NULL");
   if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
   // a new execution may follow an unwaited one on the same stream (stream
@@ -2274,7 +2295,7 @@ tg_status tg_graph_execute(tg_graph g, const tg_exec_config* cfgp, void* stream)
   HIPCHK(hipEventRecord(g->ev0, st));
   std::vector<tg_graph> gs{g};
   const uint32_t slot = (uint32_t)(g->launches % tg_graph_s::kRing);
-  if ((s = launch_layout(*g->solo, cfg, gs, st, g->evk, g->rk0[slot], g->rk1[slot])) != TG_OK) return s;
+  if ((s = launch_layout(*g->solo, cfg, gs, st, g->evk, g->rk0[slot], g->rk1[slot], conds)) != TG_OK) return s;
   HIPCHK(hipEventRecord(g->ev1, st));
   g->launches++;
   g->inflight = true;
@@ -2301,6 +2322,78 @@ tg_status tg_graph_execute_after(tg_graph g, const tg_exec_config* cfg, void* st
   if (s != TG_OK) return s;
   if (post) HIPCHK(hipEventRecord((hipEvent_t)post, st));
   return TG_OK;
+}
+
+// ---------------------------------------------------------------- flags
+
+struct tg_flag_s {
+  uint32_t* host = nullptr;  // one 128-byte line of pinned, coherent, mapped host memory
+  uint32_t* dev = nullptr;   // the same word as the device addresses it
+};
+
+tg_status tg_flag_create(tg_flag* out) {
+  if (!out) return fail(TG_EINVAL, "out is NULL");
+  *out = nullptr;
+  auto f = std::make_unique<tg_flag_s>();
+  HIPCHK(hipHostMalloc((void**)&f->host, 128, hipHostMallocCoherent | hipHostMallocMapped));
+  memset(f->host, 0, 128);
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, f->host, 0) != hipSuccess) {
+    (void)hipHostFree(f->host);
+    return fail(TG_EDEVICE, "hipHostGetDevicePointer failed for a flag");
+  }
+  f->dev = (uint32_t*)d;
+  *out = f.release();
+  return TG_OK;
+}
+
+tg_status tg_flag_destroy(tg_flag f) {
+  if (!f) return TG_OK;
+  if (f->host) (void)hipHostFree(f->host);
+  delete f;
+  return TG_OK;
+}
+
+tg_status tg_flag_set(tg_flag f, uint32_t value) {
+  if (!f) return fail(TG_EINVAL, "flag is NULL");
+  __atomic_store_n(f->host, value, __ATOMIC_SEQ_CST);
+  return TG_OK;
+}
+
+tg_status tg_flag_read(tg_flag f, uint32_t* value) {
+  if (!f || !value) return fail(TG_EINVAL, "NULL argument");
+  *value = __atomic_load_n(f->host, __ATOMIC_ACQUIRE);
+  return TG_OK;
+}
+
+tg_status tg_flag_wait(tg_flag f, uint32_t value, uint32_t timeout_ms) {
+  if (!f) return fail(TG_EINVAL, "flag is NULL");
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spins = 0;; ++spins) {
+    if (__atomic_load_n(f->host, __ATOMIC_ACQUIRE) >= value) return TG_OK;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(timeout_ms))
+      return fail(TG_ETIMEOUT, "flag did not reach %u within %u ms", value, timeout_ms);
+    if (spins > 64) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+tg_status tg_graph_execute_when(tg_graph g, const tg_exec_config* cfg, void* stream, const tg_flag* pre,
+                                const uint32_t* pre_value, uint32_t npre, tg_flag post, uint32_t post_value) {
+  if (!g) return fail(TG_EINVAL, "graph is NULL");
+  if (npre > tg::kMaxPreFlags) return fail(TG_EINVAL, "at most %u pre-condition flags, got %u", tg::kMaxPreFlags, npre);
+  if (npre && (!pre || !pre_value)) return fail(TG_EINVAL, "pre or pre_value is NULL");
+  LaunchConds c;
+  for (uint32_t i = 0; i < npre; ++i) {
+    if (!pre[i]) return fail(TG_EINVAL, "pre[%u] is NULL", i);
+    c.pre.addr[i] = pre[i]->dev;
+    c.pre.value[i] = pre_value[i];
+  }
+  c.pre.n = npre;
+  if (post) {
+    c.post = post->dev;
+    c.post_value = post_value;
+  }
+  return graph_execute(g, cfg, stream, &c);
 }
 
 tg_status tg_graph_num_tasks(tg_graph g, uint64_t* n) {

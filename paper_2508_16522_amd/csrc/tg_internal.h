@@ -77,7 +77,8 @@ struct Ctrl {
   uint32_t stuck_worker, stuck_pos, stuck_cnt, stuck_h, stuck_wcnt;  // first abort
   uint32_t resident;   // residency probe: workers that saw every worker check in
   uint32_t sticky;     // aborts of earlier launches since the host last looked
-  uint32_t pad0[23];
+  uint32_t precond;    // 1 + index of the pre-condition flag not met in time (0: none)
+  uint32_t pad0[22];
   // device clock (s_memrealtime) of the most recent task start any worker
   // published (atomic max; each worker publishes at most once per
   // ExecParams::progress_ticks); on its own 128-byte line
@@ -129,6 +130,17 @@ struct ExecParams {
   uint32_t* gdone;             // sinks finished per graph of the layout
   uint32_t* gflag;             // per graph, in host memory: gseq once it finished
   uint32_t gseq;
+  uint32_t gated;              // 1: a pre-condition wait precedes the launch; workers
+                               // leave at once if it gave up (Ctrl::abort set)
+};
+
+// Pre-condition flags of one launch (words in pinned host memory mapped for
+// the device): the launch may start once every *addr[i] >= value[i].
+constexpr uint32_t kMaxPreFlags = 8;
+struct FlagWait {
+  const uint32_t* addr[kMaxPreFlags];
+  uint32_t value[kMaxPreFlags];
+  uint32_t n;
 };
 
 // One graph of a layout whose task records are built on the device
@@ -172,6 +184,13 @@ constexpr uint32_t kMaxGang = 32;
 // mapping 1: one wavefront per task; 2: one workgroup of wg_waves wavefronts;
 // 3: a gang of p.gang such workgroups (grid_blocks = workers x gang).
 hipError_t launch_reset(const ExecParams& p, hipStream_t s);
+// One wavefront waits until every pre-condition flag is met, for at most
+// timeout_ticks (s_memrealtime, 100 MHz); on time-out it raises ctrl->abort
+// and records the flag in ctrl->precond.
+hipError_t launch_wait_flags(const FlagWait& fw, Ctrl* ctrl, uint64_t timeout_ticks, hipStream_t s);
+// Stores value into *flag (system scope, after a system-scope release) unless
+// ctrl->abort is set (the launch before it in stream order was abandoned).
+hipError_t launch_set_flag(uint32_t* flag, uint32_t value, const Ctrl* ctrl, hipStream_t s);
 hipError_t launch_exec(const ExecParams& p, uint32_t mapping, uint32_t wg_waves, uint32_t grid_blocks,
                        hipStream_t s);
 // Ready-queue dispatch: clear the slots used by the previous launch, then

@@ -390,6 +390,13 @@ __device__ __forceinline__ void complete_edges(const Team& tm, const ExecParams&
   for (uint32_t j = tm.t + tm.size(); j < r.nsucc; j += tm.size()) signal_edge<Team>(P, P.succ_pos[r.succ_beg + j]);
 }
 
+// A launch behind a pre-condition wait (k_wait_flags) does nothing if the
+// wait gave up: the wait raised the abort flag, which the reset before it
+// had cleared.
+__device__ __forceinline__ bool gate_closed(const ExecParams& P) {
+  return P.gated && uni(ld_coherent(&P.ctrl->abort)) != 0u;
+}
+
 // ------------------------------------------------------------ worker loop
 
 constexpr uint32_t kExit = 0xFFFFFFFFu;
@@ -562,7 +569,7 @@ __device__ __forceinline__ void worker_init(WorkerState& w, const ExecParams& P,
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exec_wave(ExecParams P) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t worker = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (worker >= P.nworkers) return;
+  if (worker >= P.nworkers || gate_closed(P)) return;
   const WaveTeam tm{lane};
   if (P.diag && lane == 0) __hip_atomic_fetch_add(&P.ctrl->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   WorkerState w;
@@ -587,7 +594,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   __shared__ uint32_t cmd;
   __shared__ uint32_t recl[32];
   const uint32_t worker = blockIdx.x;
-  if (worker >= P.nworkers) return;
+  if (worker >= P.nworkers || gate_closed(P)) return;
   const BlockTeam tm{threadIdx.x, blockDim.x, lds};
   const uint32_t lane = threadIdx.x & 63u;
   if (P.diag && threadIdx.x == 0)
@@ -649,7 +656,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   __shared__ uint32_t recl[32];
   const uint32_t G = P.gang;
   const uint32_t gang = blockIdx.x / G, member = blockIdx.x % G;
-  if (gang >= P.nworkers) return;
+  if (gang >= P.nworkers || gate_closed(P)) return;
   GangTeam tm;
   tm.t = threadIdx.x;
   tm.n = blockDim.x;
@@ -932,7 +939,7 @@ __device__ __forceinline__ void graph_sink_done(const ExecParams& P, uint32_t gr
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exec_wave_q(ExecParams P) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t worker = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (worker >= P.nworkers) return;
+  if (worker >= P.nworkers || gate_closed(P)) return;
   const WaveTeam tm{lane};
   if (P.diag && lane == 0) __hip_atomic_fetch_add(&P.ctrl->started, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   QueueState q;
@@ -956,7 +963,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   __shared__ uint32_t cmd;
   __shared__ uint32_t recl[32];
   const uint32_t worker = blockIdx.x;
-  if (worker >= P.nworkers) return;
+  if (worker >= P.nworkers || gate_closed(P)) return;
   const BlockTeam tm{threadIdx.x, blockDim.x, lds};
   const uint32_t lane = threadIdx.x & 63u;
   if (P.diag && threadIdx.x == 0)
@@ -1045,7 +1052,10 @@ __global__ __launch_bounds__(256) void k_reset(ExecParams P) {
   if (blockIdx.x == 0 && threadIdx.x == 0) P.ctrl->sticky += P.ctrl->abort;
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x < 8) (&P.ctrl->abort)[threadIdx.x] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) P.ctrl->progress = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    P.ctrl->progress = 0;
+    P.ctrl->precond = 0;
+  }
 }
 
 // Comparator: one launch runs one task; ordering comes from the stream or
@@ -1123,6 +1133,37 @@ __global__ __launch_bounds__(256) void k_build_records(const GraphSrc* gsrc, uin
   }
 }
 
+// Pre-condition vertices met by the host or by another launch (Section 4.1):
+// lane i polls flag i (system-scope loads of pinned host memory) until every
+// flag holds at least its value, or gives up after timeout_ticks.
+__global__ __launch_bounds__(64) void k_wait_flags(FlagWait fw, Ctrl* ctrl, uint64_t timeout_ticks) {
+  const uint32_t lane = threadIdx.x;
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (;;) {
+    bool met = true;
+    if (lane < fw.n) met = __hip_atomic_load(fw.addr[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) >= fw.value[lane];
+    const uint64_t unmet = __ballot(!met);
+    if (unmet == 0ull) return;
+    if (__builtin_amdgcn_s_memrealtime() - t0 > timeout_ticks) {
+      if (lane == 0) {
+        st_coherent(&ctrl->precond, 1u + (uint32_t)__builtin_ctzll(unmet));
+        __hip_atomic_fetch_add(&ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      return;
+    }
+    __builtin_amdgcn_s_sleep(32);
+  }
+}
+
+// Post-condition vertex: runs after the launch in stream order, so every
+// task of it has finished; publishes them (system-scope release) and sets the
+// flag, unless the launch was abandoned.
+__global__ __launch_bounds__(64) void k_set_flag(uint32_t* flag, uint32_t value, const Ctrl* ctrl) {
+  if (threadIdx.x != 0) return;
+  if (__hip_atomic_load(&ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return;
+  __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ __launch_bounds__(256) void k_fill(uint32_t* p, uint64_t n, uint32_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -1150,6 +1191,17 @@ hipError_t launch_fill(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+
+hipError_t launch_wait_flags(const FlagWait& fw, Ctrl* ctrl, uint64_t timeout_ticks, hipStream_t s) {
+  if (fw.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wait_flags, dim3(1), dim3(64), 0, s, fw, ctrl, timeout_ticks);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_flag(uint32_t* flag, uint32_t value, const Ctrl* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, s, flag, value, ctrl);
+  return hipGetLastError();
+}
 
 hipError_t launch_reset(const ExecParams& p, hipStream_t s) {
   uint32_t blocks = (p.npos + 255u) / 256u;

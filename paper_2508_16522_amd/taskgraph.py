@@ -41,7 +41,8 @@ EXPORTS = (
     "tg_graph_kernel_ms", "tg_graph_autotune", "tg_probe", "tg_graph_kernel_times", "tg_graph_set_rounds",
     "tg_server_create", "tg_server_submit", "tg_server_wait", "tg_server_stats", "tg_server_destroy",
     "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
-    "tg_graph_execute_after", "tg_reduce_dag", "tg_last_user_dag", "tg_graph_reduce_edges",
+    "tg_graph_execute_after", "tg_flag_create", "tg_flag_destroy", "tg_flag_set", "tg_flag_read", "tg_flag_wait",
+    "tg_graph_execute_when", "tg_reduce_dag", "tg_last_user_dag", "tg_graph_reduce_edges",
     "tg_graph_set_retention", "tg_graph_payload_slots", "tg_graph_read_exec_dag", "tg_emulate_queue",
     "tg_infer_dag", "tg_infer_dag_noalloc", "tg_server_configure",
 )
@@ -130,6 +131,12 @@ def load() -> ctypes.CDLL:
         "tg_batch_info": (i32, [G, P, P, P, P]),
         "tg_batch_autotune": (i32, [G, u32, P, P]),
         "tg_graph_execute_after": (i32, [G, P, P, P, u32, P]),
+        "tg_flag_create": (i32, [P]),
+        "tg_flag_destroy": (i32, [P]),
+        "tg_flag_set": (i32, [P, u32]),
+        "tg_flag_read": (i32, [P, P]),
+        "tg_flag_wait": (i32, [P, u32, u32]),
+        "tg_graph_execute_when": (i32, [G, P, P, P, P, u32, P, u32]),
         "tg_reduce_dag": (i32, [u32, P, P, P, P, P]),
         "tg_last_user_dag": (i32, [u32, P, P, P, P, u64, P]),
         "tg_graph_reduce_edges": (i32, [G, P]),
@@ -312,6 +319,47 @@ def tg_graph_execute_after(g, pre_events=(), post_event=None, cfg: tg_exec_confi
         post = ctypes.c_void_p(post_event.cuda_event)
     _check(load().tg_graph_execute_after(g, ctypes.byref(cfg) if cfg is not None else None, _stream(stream),
                                          arr if handles else None, len(handles), post), "tg_graph_execute_after")
+
+
+def tg_flag_create():
+    """A condition flag (one pinned 32-bit host word the device reads and
+    writes), initially 0."""
+    f = ctypes.c_void_p()
+    _check(load().tg_flag_create(ctypes.byref(f)), "tg_flag_create")
+    return f
+
+
+def tg_flag_destroy(f):
+    _check(load().tg_flag_destroy(f), "tg_flag_destroy")
+
+
+def tg_flag_set(f, value: int):
+    _check(load().tg_flag_set(f, value), "tg_flag_set")
+
+
+def tg_flag_read(f) -> int:
+    v = ctypes.c_uint32()
+    _check(load().tg_flag_read(f, ctypes.byref(v)), "tg_flag_read")
+    return v.value
+
+
+def tg_flag_wait(f, value: int, timeout_ms: int = 10000):
+    _check(load().tg_flag_wait(f, value, timeout_ms), "tg_flag_wait")
+
+
+def tg_graph_execute_when(g, pre=(), pre_values=(), post=None, post_value: int = 1,
+                          cfg: tg_exec_config | None = None, stream=None):
+    """Execute once every flag in pre holds at least its value in pre_values;
+    set post to post_value on the device when the graph has finished."""
+    if len(pre) != len(pre_values):
+        raise ValueError("pre and pre_values differ in length")
+    n = len(pre)
+    fa = (ctypes.c_void_p * max(n, 1))(*[ctypes.c_void_p(f.value if isinstance(f, ctypes.c_void_p) else f)
+                                         for f in pre])
+    va = (ctypes.c_uint32 * max(n, 1))(*[int(v) for v in pre_values])
+    _check(load().tg_graph_execute_when(g, ctypes.byref(cfg) if cfg is not None else None, _stream(stream),
+                                        fa if n else None, va if n else None, n, post, post_value),
+           "tg_graph_execute_when")
 
 
 def tg_graph_wait(g):

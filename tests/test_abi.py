@@ -100,3 +100,20 @@ def test_bad_config_rejected_before_launch(tglib):
         cfg = tg.make_config(**kw)
         assert tglib.tg_graph_execute(g, ctypes.byref(cfg), None) == tg.TG_EINVAL, kw
     tglib.tg_graph_destroy(g)
+
+
+def test_execute_when_argument_errors(tglib):
+    """Refused before any device work: more than 8 pre-condition flags, a NULL
+    flag list or value list, a NULL flag."""
+    st, g = _create(tglib, 1, 64, 0)
+    ev = ctypes.c_uint32()
+    assert tglib.tg_task_add(g, None, 0, 1, ctypes.byref(ev)) == 0
+    assert tglib.tg_graph_finalize(g) == 0
+    vals = (ctypes.c_uint32 * 9)(*range(9))
+    flags = (ctypes.c_void_p * 9)()
+    assert tglib.tg_graph_execute_when(g, None, None, flags, vals, 9, None, 0) == tg.TG_EINVAL
+    assert tglib.tg_graph_execute_when(g, None, None, None, vals, 1, None, 0) == tg.TG_EINVAL
+    assert tglib.tg_graph_execute_when(g, None, None, flags, None, 1, None, 0) == tg.TG_EINVAL
+    assert tglib.tg_graph_execute_when(g, None, None, flags, vals, 1, None, 0) == tg.TG_EINVAL  # flags[0] NULL
+    assert tglib.tg_graph_execute_when(None, None, None, None, None, 0, None, 0) == tg.TG_EINVAL
+    tglib.tg_graph_destroy(g)
