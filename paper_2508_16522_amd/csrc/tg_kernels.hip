@@ -255,15 +255,43 @@ __device__ __forceinline__ uint32_t explicit_words(const Team& tm, const ExecPar
           for (int i = 0; i < VEC; ++i) acc[i] = h32k(G.key1, ((uint64_t)tid << 16) | (k0 + i));
         }
       } else {
+        // groups of up to five predecessors, each group's loads issued
+        // together: one memory round trip per group, not per predecessor
         uint32_t j = 0;
-        for (; j + 4 <= npred; j += 4) {
-          V a0 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 0), nbytes), k0 * 4);
-          V a1 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 1), nbytes), k0 * 4);
-          V a2 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 2), nbytes), k0 * 4);
-          V a3 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 3), nbytes), k0 * 4);
-          acc += (a0 + a1) + (a2 + a3);
+        while (j < npred) {
+          const uint32_t m = npred - j;  // wave-uniform
+          const __amdgpu_buffer_rsrc_t r0 = make_rsrc((const void*)pred_at(P, r, j), nbytes);
+          if (m >= 5) {
+            V a0 = buf_load<VEC>(r0, k0 * 4);
+            V a1 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 1), nbytes), k0 * 4);
+            V a2 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 2), nbytes), k0 * 4);
+            V a3 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 3), nbytes), k0 * 4);
+            V a4 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 4), nbytes), k0 * 4);
+            acc += ((a0 + a1) + (a2 + a3)) + a4;
+            j += 5;
+          } else if (m == 4) {
+            V a0 = buf_load<VEC>(r0, k0 * 4);
+            V a1 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 1), nbytes), k0 * 4);
+            V a2 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 2), nbytes), k0 * 4);
+            V a3 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 3), nbytes), k0 * 4);
+            acc += (a0 + a1) + (a2 + a3);
+            j += 4;
+          } else if (m == 3) {
+            V a0 = buf_load<VEC>(r0, k0 * 4);
+            V a1 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 1), nbytes), k0 * 4);
+            V a2 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 2), nbytes), k0 * 4);
+            acc += (a0 + a1) + a2;
+            j += 3;
+          } else if (m == 2) {
+            V a0 = buf_load<VEC>(r0, k0 * 4);
+            V a1 = buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j + 1), nbytes), k0 * 4);
+            acc += a0 + a1;
+            j += 2;
+          } else {
+            acc += buf_load<VEC>(r0, k0 * 4);
+            j += 1;
+          }
         }
-        for (; j < npred; ++j) acc += buf_load<VEC>(make_rsrc((const void*)pred_at(P, r, j), nbytes), k0 * 4);
       }
     }
     V x = mix_rounds<V>(acc ^ tid, R);
