@@ -145,11 +145,16 @@ typedef struct {
  *                  made ready): the decrement that empties a counter makes
  *                  its task ready; the finishing worker keeps one ready
  *                  successor as its next task and pushes the others into the
- *                  queue shard of its XCD (one atomic per wavefront); idle
- *                  workers claim tiles of tickets (own shard first, then the
- *                  others).  Wavefront and workgroup mappings only.
+ *                  next shard in turn (one atomic add on its tail per
+ *                  wavefront); a worker that needs work claims a tile of
+ *                  tickets of its own shard (one atomic add on the head) and
+ *                  waits on each claimed slot; once every sink has run, exit
+ *                  sentinels fill every shard.  Needs no co-residency.
+ *                  Wavefront and workgroup mappings only.
  *   tile         : queue: tickets claimed per pop (1..64, default 1).
- *   shards       : queue: queue shards (1, 2, 4 or 8; default 8, one per XCD). */
+ *   shards       : queue: queue shards (1, 2, 4 or 8; default 8), at most
+ *                  the launch's workgroups rounded down to a power of two
+ *                  (every shard needs workers that claim from it). */
 enum { TG_DISPATCH_LISTS = 1, TG_DISPATCH_QUEUE = 2 };
 
 enum { TG_MAP_WAVE = 1, TG_MAP_WORKGROUP = 2, TG_MAP_GANG = 3 };
@@ -451,11 +456,14 @@ tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t
                               uint32_t schedule, uint64_t seed, uint64_t* order, uint64_t* executed, uint64_t* makespan,
                               uint64_t* bound);
 /* Host-only model of the ready-queue dispatch (TG_DISPATCH_QUEUE) over
- * graphs[0..ngraphs): nworkers workers with the kernels' steps (claim by
- * compare-and-swap on a shard's head, tickets reserved on its tail before the
- * slots are written, one ready successor kept per completion, the finished
- * count flushed by idle workers) interleaved in a seeded order at every
- * access to shared state.  order (total #tasks entries) receives the
+ * graphs[0..ngraphs): nworkers workers with the kernels' steps (a claim of
+ * `tile` tickets by one atomic add on the head of the worker's shard, then a
+ * wait on each claimed slot; pushes of the ready successors by one atomic
+ * add on the tail of the next shard in turn, one ready successor kept per
+ * completion; sinks counted by workers whose next slot is empty, and exit
+ * sentinels pushed into every shard by the count that completes the total),
+ * interleaved in a seeded order at every access to shared state.  shards
+ * must be a power of two in 1..8 and tile in 1..64 (TG_EINVAL otherwise).  order (total #tasks entries) receives the
  * execution order as (graph index << 32 | event); TG_ETIMEOUT if the model
  * does not terminate. */
 tg_status tg_emulate_queue(const tg_graph* graphs, uint32_t ngraphs, uint32_t nworkers, uint32_t shards, uint32_t tile,
