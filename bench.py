@@ -361,6 +361,9 @@ def main():
             "atomics_contended_per_s": tg.tg_probe(tg.TG_PROBE_ATOMIC_CONTENDED),
             "launches_per_s": tg.tg_probe(tg.TG_PROBE_LAUNCH_RATE),
             "handoff_ns": tg.tg_probe(tg.TG_PROBE_HANDOFF_NS),
+            "handoff_same_xcd_ns": tg.tg_probe(tg.TG_PROBE_HANDOFF_SAME_XCD_NS),
+            "handoff_far_xcd_ns": tg.tg_probe(tg.TG_PROBE_HANDOFF_FAR_XCD_NS),
+            "handoff_l2_payload_ns": tg.tg_probe(tg.TG_PROBE_HANDOFF_L2_NS),
         }
     log(f"probes: {probes}")
     if args.workload != "step":

@@ -506,10 +506,16 @@ enum {
   TG_PROBE_ATOMIC_DISTINCT = 3,  /* device-scope u32 atomics/s on distinct addresses */
   TG_PROBE_ATOMIC_CONTENDED = 4, /* device-scope u32 atomics/s on one address */
   TG_PROBE_LAUNCH_RATE = 5,      /* empty kernel launches/s, back to back */
-  TG_PROBE_HANDOFF_NS = 6        /* ns of one dependent hop between wavefronts on two
-                                    XCDs: see the signal, load the 1 KB payload, store
-                                    one, drain the stores, signal with one atomic
-                                    (the per-level floor of a dependence chain) */
+  TG_PROBE_HANDOFF_NS = 6,       /* ns of one dependent hop between wavefronts on two
+                                    neighbouring XCDs: see the signal, load the 1 KB
+                                    payload, store one, drain the stores, signal with
+                                    one atomic (the per-level floor of a dependence
+                                    chain) */
+  TG_PROBE_HANDOFF_SAME_XCD_NS = 7,  /* the same hop between two CUs of one XCD */
+  TG_PROBE_HANDOFF_FAR_XCD_NS = 8,   /* ... between XCDs in the two halves of the package */
+  TG_PROBE_HANDOFF_L2_NS = 9         /* ... within one XCD, the payload loaded and stored
+                                        through the XCD's L2 (L1 bypassed) instead of at
+                                        device scope; the signal stays device scope */
 };
 tg_status tg_probe(uint32_t kind, double* value);
 

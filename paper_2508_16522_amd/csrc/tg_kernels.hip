@@ -93,10 +93,18 @@ __device__ __forceinline__ V mix_rounds(V x, uint32_t R) {
   return x;
 }
 
+// Wrap-around sum over the 64 lanes (all active), returned wave-uniform.
+// Cross-lane moves within each 16-lane row use DPP (swap neighbours, swap
+// pairs, mirror each half-row, mirror the row); the four row sums are then
+// read with readlane.  No LDS round trip: this sits between a task's payload
+// store and its digest store, on the task's critical path.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+         __builtin_amdgcn_readlane(v, 48);
 }
 
 // ------------------------------------------------------------------ teams

@@ -90,34 +90,42 @@ __global__ void p_empty() {}
 
 constexpr int kSC1 = 16;  // buffer cache policy: device-scope coherent access
 
-// Two single-wave workgroups (blocks 0 and 1 run on different XCDs) pass a
-// token back and forth `hops` times in total.  Block b waits for its flag to
-// reach its turn count, reads the other block's 1 KB payload (16 bytes per
-// lane, device scope), writes its own, drains its stores and increments the
-// other block's flag.  Every wait gives up after `spin_cap` polls (status 1).
-// stamp[0..1]: device clock at block 0's first and last hop.
+constexpr int kSC0 = 1;   // buffer cache policy: bypass L1, may hit the XCD's L2
+
+// Two single-wave workgroups, blocks ba and bb (workgroup b runs on XCD
+// b mod 8), pass a token back and forth `hops` times in total.  A block waits
+// for its flag to reach its turn count, reads the other block's 1 KB payload
+// (16 bytes per lane), writes its own, drains its stores and increments the
+// other block's flag.  Flags are device-scope atomics polled with device-scope
+// loads; the payload is accessed at device scope, or (L2PAY, only coherent when
+// both blocks share an XCD) through the XCD's L2.  Other blocks exit.  Every
+// wait gives up after `spin_cap` polls (status 1).  stamp[0..1]: device clock
+// at block ba's first and last hop.
+template <bool L2PAY>
 __global__ __launch_bounds__(64) void p_handoff(uint32_t* flags, uint32_t* pay, uint32_t hops, uint32_t spin_cap,
-                                                uint32_t* status, uint64_t* stamp) {
-  const uint32_t me = blockIdx.x, other = me ^ 1u, lane = threadIdx.x;
+                                                uint32_t* status, uint64_t* stamp, uint32_t ba, uint32_t bb) {
+  if (blockIdx.x != ba && blockIdx.x != bb) return;
+  const uint32_t me = blockIdx.x == ba ? 0u : 1u, other = me ^ 1u, lane = threadIdx.x;
+  constexpr int pol = L2PAY ? kSC0 : kSC1;
   const __amdgpu_buffer_rsrc_t mine = __builtin_amdgcn_make_buffer_rsrc(pay + me * 256, 0, 1024, 0x00020000);
   const __amdgpu_buffer_rsrc_t theirs = __builtin_amdgcn_make_buffer_rsrc(pay + other * 256, 0, 1024, 0x00020000);
   u32x4 acc = {lane, 0u, 0u, 0u};
   uint64_t t0 = 0;
-  // block 0 takes hops 0, 2, 4, ...; block 1 hops 1, 3, 5, ...
+  // block ba takes hops 0, 2, 4, ...; block bb hops 1, 3, 5, ...
   for (uint32_t h = me; h < hops; h += 2) {
     const uint32_t turn = h / 2;  // messages this block must have received
     uint32_t spins = 0;
-    while (__hip_atomic_load(flags + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < turn + me) {
+    while (__hip_atomic_load(flags + me * 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < turn + me) {
       if (++spins > spin_cap) {
         if (lane == 0) __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
       }
     }
     if (me == 0 && h == 0) t0 = __builtin_amdgcn_s_memrealtime();
-    acc += __builtin_amdgcn_raw_buffer_load_b128(theirs, lane * 16, 0, kSC1);
-    __builtin_amdgcn_raw_buffer_store_b128(acc, mine, lane * 16, 0, kSC1);
+    acc += __builtin_amdgcn_raw_buffer_load_b128(theirs, lane * 16, 0, pol);
+    __builtin_amdgcn_raw_buffer_store_b128(acc, mine, lane * 16, 0, pol);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (lane == 0) __hip_atomic_fetch_add(flags + other, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) __hip_atomic_fetch_add(flags + other * 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (me == 0 && lane == 0) {
     stamp[0] = t0;
@@ -191,19 +199,29 @@ extern "C" tg_status tg_probe(uint32_t kind, double* value) {
       *value = rate;
       break;
     }
-    case TG_PROBE_HANDOFF_NS: {
+    case TG_PROBE_HANDOFF_NS:
+    case TG_PROBE_HANDOFF_SAME_XCD_NS:
+    case TG_PROBE_HANDOFF_FAR_XCD_NS:
+    case TG_PROBE_HANDOFF_L2_NS: {
       const uint32_t hops = 20000;
-      // flags (2 words), status, clock stamps, two 1 KB payloads
-      if ((e = hipMalloc(&a, 4096)) != hipSuccess) break;
-      if ((e = hipMemset(a, 0, 4096)) != hipSuccess) break;
+      // blocks 0 and 1: neighbouring XCDs; 0 and 4: the far half of the
+      // package; 0 and 8: one XCD
+      const uint32_t bb = kind == TG_PROBE_HANDOFF_NS ? 1u : kind == TG_PROBE_HANDOFF_FAR_XCD_NS ? 4u : 8u;
+      // flags (one per 128-byte line), status, clock stamps, two 1 KB payloads
+      if ((e = hipMalloc(&a, 8192)) != hipSuccess) break;
+      if ((e = hipMemset(a, 0, 8192)) != hipSuccess) break;
       uint32_t* w = (uint32_t*)a;
-      hipLaunchKernelGGL(p_handoff, dim3(2), dim3(64), 0, nullptr, w, w + 256, hops, 1u << 22, w + 8,
-                         (uint64_t*)(w + 16));
+      if (kind == TG_PROBE_HANDOFF_L2_NS)
+        hipLaunchKernelGGL(p_handoff<true>, dim3(bb + 1), dim3(64), 0, nullptr, w, w + 1024, hops, 1u << 22, w + 64,
+                           (uint64_t*)(w + 96), 0u, bb);
+      else
+        hipLaunchKernelGGL(p_handoff<false>, dim3(bb + 1), dim3(64), 0, nullptr, w, w + 1024, hops, 1u << 22, w + 64,
+                           (uint64_t*)(w + 96), 0u, bb);
       if ((e = hipDeviceSynchronize()) != hipSuccess) break;
       uint32_t status = 0;
       uint64_t stamp[2] = {0, 0};
-      if ((e = hipMemcpy(&status, w + 8, 4, hipMemcpyDeviceToHost)) != hipSuccess) break;
-      if ((e = hipMemcpy(stamp, w + 16, 16, hipMemcpyDeviceToHost)) != hipSuccess) break;
+      if ((e = hipMemcpy(&status, w + 64, 4, hipMemcpyDeviceToHost)) != hipSuccess) break;
+      if ((e = hipMemcpy(stamp, w + 96, 16, hipMemcpyDeviceToHost)) != hipSuccess) break;
       if (status != 0 || stamp[1] <= stamp[0]) {
         (void)hipFree(a);
         return TG_ETIMEOUT;

@@ -479,6 +479,7 @@ def tg_graph_debug_state(g):
 
 TG_PROBE_MIX_RATE, TG_PROBE_COPY_BW, TG_PROBE_ATOMIC_DISTINCT, TG_PROBE_ATOMIC_CONTENDED, TG_PROBE_LAUNCH_RATE = 1, 2, 3, 4, 5
 TG_PROBE_HANDOFF_NS = 6
+TG_PROBE_HANDOFF_SAME_XCD_NS, TG_PROBE_HANDOFF_FAR_XCD_NS, TG_PROBE_HANDOFF_L2_NS = 7, 8, 9
 
 
 def tg_probe(kind: int) -> float:
