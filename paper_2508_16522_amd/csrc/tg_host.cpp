@@ -966,6 +966,30 @@ tg_status plan_layout(const std::vector<tg_graph>& gs, uint64_t nw_req, uint32_t
   return TG_OK;
 }
 
+// List dispatch: an edge from a list entry to the next entry of the same
+// worker's list needs no counter.  The worker finishes its tasks one after
+// another, so the earlier task is done before the later one is taken; the
+// edge is moved past the end of the earlier task's successors (not
+// signalled) and the later task's counter starts one lower, with kAfterPrev
+// set (the ready scan then also waits for the entry before it to be taken).
+// A dependence chain kept on one worker (a Task Bench column) thus costs no
+// atomic and no counter round trip per task.
+void elide_list_edges(HostLayout& H) {
+  for (uint32_t w = 0; w < H.nw; ++w)
+    for (uint32_t p = H.wbase[w] + 1; p < H.wbase[w + 1]; ++p) {
+      TaskRec& r = H.rec[p - 1];
+      uint32_t* list = H.succ_pos.data() + r.succ_beg;
+      for (uint32_t j = 0; j < r.nsucc; ++j)
+        if (list[j] == p) {
+          std::swap(list[j], list[r.nsucc - 1]);
+          r.nsucc--;
+          for (uint32_t k = 0; k < tg::kInSucc && k < r.nsucc + 1; ++k) r.succ[k] = list[k];
+          H.indeg[p] = (H.indeg[p] - 1u) | tg::kAfterPrev;
+          break;
+        }
+    }
+}
+
 // Most workers that claim tickets from one queue shard: a worker claims from
 // shard (workgroup index mod 8) mod shards, as the kernels do; wavefront
 // workers sit four to a workgroup.
@@ -1037,6 +1061,7 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   const bool keep = cache && !reuse && ntasks <= PlanCache::kMaxTasks && cache->m.size() < PlanCache::kMaxEntries;
   auto kept = keep ? std::make_shared<Plan>() : nullptr;
   if ((s = plan_layout(gs, nw, cfg.schedule, H, reuse, kept.get())) != TG_OK) return s;
+  if (cfg.dispatch == TG_DISPATCH_LISTS) elide_list_edges(H);
   if (keep) cache->m[key] = kept;
   const double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_plan).count();
   auto L = std::make_unique<Layout>();
@@ -1391,7 +1416,9 @@ tg_status emulate_layout(const HostLayout& H, uint32_t window, uint64_t seed, ui
     for (uint32_t lane = 0; lane < 64; ++lane) {
       const uint32_t idx = x.h + lane;
       const bool valid = lane < window && idx < wcnt && !((x.done >> lane) & 1ull);
-      if (valid && cnt[wb + idx] == 0) ready |= 1ull << lane;
+      const uint32_t c = cnt[wb + idx < N ? wb + idx : 0];
+      const bool prev_taken = lane == 0 || ((x.done >> (lane - 1)) & 1ull);
+      if (valid && (c & tg::kPendingMask) == 0 && (!(c & tg::kAfterPrev) || prev_taken)) ready |= 1ull << lane;
     }
     return ready;
   };
@@ -1437,7 +1464,8 @@ tg_status emulate_layout(const HostLayout& H, uint32_t window, uint64_t seed, ui
     ++ex;
     for (uint32_t j = 0; j < r.nsucc; ++j) {
       uint32_t& c = cnt[H.succ_pos[r.succ_beg + j]];
-      if (c == 0) return fail(TG_EINVAL, "counter underflow at position %u", H.succ_pos[r.succ_beg + j]);
+      if ((c & tg::kPendingMask) == 0)
+        return fail(TG_EINVAL, "counter underflow at position %u", H.succ_pos[r.succ_beg + j]);
       --c;
     }
   }
@@ -1813,7 +1841,7 @@ tg_status check_abort(Layout* L) {
     return fail(TG_ETIMEOUT,
                 "executor watchdog aborted the launch (no progress): worker %u of %u stuck at list entry %u/%u "
                 "(position %u, pending in-edges %u)",
-                c.stuck_worker, L->nworkers, c.stuck_h, c.stuck_wcnt, c.stuck_pos, c.stuck_cnt);
+                c.stuck_worker, L->nworkers, c.stuck_h, c.stuck_wcnt, c.stuck_pos, c.stuck_cnt & tg::kPendingMask);
   if (c.sticky) return fail(TG_ETIMEOUT, "an earlier launch of this layout was aborted by the executor watchdog");
   return TG_OK;
 }
@@ -3167,7 +3195,7 @@ tg_status tg_graph_debug_state(tg_graph g, uint32_t* pending, uint32_t* execs, u
   HIPCHK(hipMemcpy(wb.data(), L.wbase.p, wb.size() * 4, hipMemcpyDeviceToHost));
   for (uint32_t v = 0; v < N; ++v) {
     const uint32_t pos = L.pos_of[0][v];
-    pending[v] = c[pos];
+    pending[v] = c[pos] & tg::kPendingMask;
     execs[v] = x[pos];
     uint32_t w = (uint32_t)(std::upper_bound(wb.begin(), wb.end(), pos) - wb.begin()) - 1;
     owner[v] = w;
@@ -3194,7 +3222,11 @@ tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t
   tg_status s = plan_layout(gs, nworkers, schedule ? schedule : (uint32_t)TG_SCHED_LEVEL, H);
   if (s != TG_OK) return s;
   std::vector<uint32_t> ord(H.N);
-  s = emulate_layout(H, window, seed, ord.data(), executed);
+  {
+    HostLayout E = H;  // as the list executor runs it
+    elide_list_edges(E);
+    s = emulate_layout(E, window, seed, ord.data(), executed);
+  }
   // report (graph, id), not positions
   std::vector<uint64_t> key_of(H.N);
   for (uint32_t gi = 0; gi < gs.size(); ++gi)

@@ -169,6 +169,14 @@ struct alignas(16) GraphSrc {
   uint32_t pad[2];
 };
 
+// List dispatch: counter bit meaning "this list entry also waits for the
+// entry before it in its worker's list".  That predecessor runs on the same
+// worker, which finishes it before taking this task, so its edge is not
+// counted (the layout drops it from the predecessor's successors); the bits
+// below hold the other in-edges still pending.
+constexpr uint32_t kAfterPrev = 0x80000000u;
+constexpr uint32_t kPendingMask = 0x7FFFFFFFu;
+
 constexpr uint32_t kQEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kQExit = 0xFFFFFFFEu;  // exit sentinel
 constexpr uint32_t kQLine = 32;           // u32 words between queue control words (128 bytes)

@@ -411,7 +411,7 @@ __device__ __forceinline__ void signal_edge(const ExecParams& P, uint32_t dst) {
     // that starts the task at its owner: the owner's doorbell is rung only
     // after the decrement has been performed (its old value has returned).
     const uint32_t old = __hip_atomic_fetch_sub(P.cnt + dst, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == 1u)
+    if ((old & kPendingMask) == 1u)
       __hip_atomic_fetch_add(P.bell + P.owner[dst] * kBellStride, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   } else {
     __hip_atomic_fetch_sub(P.cnt + dst, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -472,7 +472,10 @@ __device__ __forceinline__ uint64_t ready_scan(uint32_t lane, const ExecParams& 
   const bool valid = lane < P.window && idx < w.wcnt && !((w.done >> lane) & 1ull);
   uint32_t c = 1u;
   if (valid) c = ld_coherent(P.cnt + w.wb + idx);
-  return uni64(__ballot(valid && c == 0u));
+  // an entry marked kAfterPrev also needs the entry before it taken (entry
+  // h - 1 is finished; this worker runs its tasks one after another)
+  const bool prev_taken = lane == 0u || ((w.done >> (lane - 1u)) & 1ull);
+  return uni64(__ballot(valid && (c & kPendingMask) == 0u && (!(c & kAfterPrev) || prev_taken)));
 }
 
 // Global progress: a worker that takes a task publishes the time (atomic
@@ -1136,16 +1139,22 @@ __global__ __launch_bounds__(256) void k_build_records(const GraphSrc* gsrc, uin
     r.graph = gi;
     r.rounds = g.rounds[v];
     const uint64_t wbytes = (uint64_t)g.n * 4u;
+    // the inline lists are filled with constant indices so that the record
+    // stays in registers (a variable index would put it in scratch memory)
     if (g.mode == 1) {
       r.out = g.payload + (uint64_t)(g.slot ? g.slot[v] : v) * wbytes;
       const uint32_t d0 = g.pred_ptr[v], d1 = g.pred_ptr[v + 1];
       r.npred = d1 - d0;
       r.pred_beg = g.pred_base + d0;
+#pragma unroll
+      for (uint32_t k = 0; k < kInPred; ++k)
+        if (k < r.npred) {
+          const uint32_t q = g.preds[d0 + k];
+          r.pred[k] = g.payload + (uint64_t)(g.slot ? g.slot[q] : q) * wbytes;
+        }
       for (uint32_t j = d0; j < d1; ++j) {
         const uint32_t q = g.preds[j];
-        const uint64_t addr = g.payload + (uint64_t)(g.slot ? g.slot[q] : q) * wbytes;
-        if (j - d0 < kInPred) r.pred[j - d0] = addr;
-        pred_addr[g.pred_base + j] = addr;
+        pred_addr[g.pred_base + j] = g.payload + (uint64_t)(g.slot ? g.slot[q] : q) * wbytes;
       }
     } else {
       const uint32_t a0 = g.req_ptr[v];
@@ -1155,11 +1164,10 @@ __global__ __launch_bounds__(256) void k_build_records(const GraphSrc* gsrc, uin
     const uint32_t s0 = g.succ_ptr[v], s1 = g.succ_ptr[v + 1];
     r.nsucc = s1 - s0;
     r.succ_beg = g.succ_base + s0;
-    for (uint32_t j = s0; j < s1; ++j) {
-      const uint32_t sp = g.pos_base + g.succ[j];
-      if (j - s0 < kInSucc) r.succ[j - s0] = sp;
-      succ_pos[g.succ_base + j] = sp;
-    }
+#pragma unroll
+    for (uint32_t k = 0; k < kInSucc; ++k)
+      if (k < r.nsucc) r.succ[k] = g.pos_base + g.succ[s0 + k];
+    for (uint32_t j = s0; j < s1; ++j) succ_pos[g.succ_base + j] = g.pos_base + g.succ[j];
     rec[p] = r;
     indeg[p] = g.indeg[v];
   }
