@@ -390,7 +390,11 @@ def main():
         bcfg, bms = tg.tg_batch_autotune(batch, reps=2)
         log(f"autotune batch: {bcfg} {bms:.3f} ms")
     bcfg, _, btimes = tg.tg_batch_info(batch, with_times=True)
-    log(f"batch layout: plan {btimes['plan_ms']:.0f} ms, build {btimes['build_ms']:.0f} ms")
+    # counter atomics per launch: edges between consecutive entries of one
+    # worker's list are ordered by the list and signal nothing
+    signalled_per_step = tg.tg_batch_signalled_edges(batch)
+    log(f"batch layout: plan {btimes['plan_ms']:.0f} ms, build {btimes['build_ms']:.0f} ms; "
+        f"{signalled_per_step} of {edges_per_step} edges signalled")
 
     def step():
         tg.tg_batch_execute(batch, stream)
@@ -606,9 +610,10 @@ def main():
             "kernel_ms_per_step": kernel_ms_per_step,
             "frac_of_measured_copy": (achieved_gbs * 1e9 / probes["copy_bytes_per_s"]
                                       if probes.get("copy_bytes_per_s") else None),
-            "atomics_per_step": edges_per_step,
-            "atomics_per_s": edges_per_step / (kernel_ms_per_step * 1e-3),
-            "atomics_frac": (edges_per_step / (kernel_ms_per_step * 1e-3) / probes["atomics_distinct_per_s"]
+            "edges_per_step": edges_per_step,
+            "atomics_per_step": signalled_per_step,
+            "atomics_per_s": signalled_per_step / (kernel_ms_per_step * 1e-3),
+            "atomics_frac": (signalled_per_step / (kernel_ms_per_step * 1e-3) / probes["atomics_distinct_per_s"]
                              if probes.get("atomics_distinct_per_s") else None),
             "atomics_counted_per_step": counters.get("l2_atomic_requests_per_step"),
             "l2_hit_fraction": counters.get("l2_hit_fraction"),

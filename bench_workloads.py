@@ -72,9 +72,17 @@ def run_alone(args, stream, probes=None):
     import oracle
     ref = oracle.exec_explicit(eg.N, eg.n, eg.pred_ptr, eg.preds, 0, want_payload=False)
     ok = bool(np.array_equal(tg.tg_graph_read_digests(g.handle), ref["digest"]))
+    # edges signalled by a counter atomic in this launch shape (a one-graph
+    # batch plans the same layout)
+    b = tg.tg_batch_create([g.handle], cfg)
+    try:
+        signalled = tg.tg_batch_signalled_edges(b)
+    finally:
+        tg.tg_batch_destroy(b)
+    log(f"alone: {signalled} of {eg.E} edges signalled")
     return {"workload": f"{args.pattern} 1024 x 1000 alone, n=256, R=0, {args.dispatch}", "tasks": eg.N,
-            "edges": eg.E, "exec_ms": ms, "tasks_per_s": eg.N / (ms * 1e-3), "parity": ok,
-            "launch": tg.tg_graph_exec_info(g.handle)[0]}
+            "edges": eg.E, "signalled_edges": signalled, "exec_ms": ms, "tasks_per_s": eg.N / (ms * 1e-3),
+            "parity": ok, "launch": tg.tg_graph_exec_info(g.handle)[0]}
 
 
 # ---------------------------------------------------------------- implicit

@@ -426,6 +426,11 @@ tg_status tg_batch_set_rounds(tg_batch b, uint32_t uniform_rounds);
  * schedule and task records, build_ms for all of it including the upload
  * (Algorithm 1, Compile).  Any output pointer may be NULL. */
 tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks, double* plan_ms, double* build_ms);
+/* Edges of the batch's layout signalled with a counter atomic per launch
+ * (Algorithm 1 COMPLETED_EDGE): all executed edges, less those between
+ * consecutive entries of one worker's list, which the list dispatch does not
+ * count (their order follows from the list).  TG_EINVAL for NULL arguments. */
+tg_status tg_batch_signalled_edges(tg_batch b, uint64_t* edges);
 /* Autotuner for a batch (as tg_graph_autotune); keeps the fastest layout. */
 tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, double* best_ms);
 tg_status tg_batch_destroy(tg_batch b);

@@ -283,6 +283,7 @@ struct Layout {
   std::vector<TaskRec> rec_host;               // host copy (rounds can be re-set)
   ExecParams params{};
   double plan_ms = 0, build_ms = 0;  // host time: schedule + records, whole layout incl. upload
+  uint64_t signalled = 0;             // edges signalled by a counter atomic per launch
   // residency ledger: kernel variant, co-resident units this layout's launch
   // occupies, the variant's calibrated capacity, device, completion event
   int dev = 0;
@@ -1062,10 +1063,13 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   auto kept = keep ? std::make_shared<Plan>() : nullptr;
   if ((s = plan_layout(gs, nw, cfg.schedule, H, reuse, kept.get())) != TG_OK) return s;
   if (cfg.dispatch == TG_DISPATCH_LISTS) elide_list_edges(H);
+  uint64_t signalled = 0;
+  for (const TaskRec& r : H.rec) signalled += r.nsucc;
   if (keep) cache->m[key] = kept;
   const double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_plan).count();
   auto L = std::make_unique<Layout>();
   L->cfg = cfg;
+  L->signalled = signalled;
   L->npos = H.N;
   L->nworkers = H.nw;
   L->grid_blocks = cfg.mapping == TG_MAP_WAVE ? (H.nw + 3) / 4 : H.nw * cfg.gang;
@@ -3023,6 +3027,12 @@ tg_status tg_batch_set_rounds(tg_batch b, uint32_t uniform_rounds) {
   if (!L.rec_host.empty())
     HIPCHK(hipMemcpy(L.rec.p, L.rec_host.data(), L.rec_host.size() * sizeof(TaskRec), hipMemcpyHostToDevice));
   return null_stream_fence();
+}
+
+tg_status tg_batch_signalled_edges(tg_batch b, uint64_t* edges) {
+  if (!b || !edges) return fail(TG_EINVAL, "NULL argument");
+  *edges = b->lay->signalled;
+  return TG_OK;
 }
 
 tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks, double* plan_ms, double* build_ms) {

@@ -40,7 +40,7 @@ EXPORTS = (
     "tg_graph_execute_comparator", "tg_exec_occupancy", "tg_graph_exec_info", "tg_graph_debug_state", "tg_emulate_schedule", "tg_graph_debug_times",
     "tg_graph_kernel_ms", "tg_graph_autotune", "tg_probe", "tg_graph_kernel_times", "tg_graph_set_rounds",
     "tg_server_create", "tg_server_submit", "tg_server_wait", "tg_server_stats", "tg_server_destroy",
-    "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_info", "tg_batch_autotune",
+    "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_signalled_edges", "tg_batch_info", "tg_batch_autotune",
     "tg_graph_execute_after", "tg_flag_create", "tg_flag_destroy", "tg_flag_set", "tg_flag_read", "tg_flag_wait",
     "tg_graph_execute_when", "tg_reduce_dag", "tg_last_user_dag", "tg_graph_reduce_edges",
     "tg_graph_set_retention", "tg_graph_payload_slots", "tg_graph_read_exec_dag", "tg_emulate_queue",
@@ -131,6 +131,7 @@ def load() -> ctypes.CDLL:
         "tg_batch_info": (i32, [G, P, P, P, P]),
         "tg_batch_autotune": (i32, [G, u32, P, P]),
         "tg_graph_execute_after": (i32, [G, P, P, P, u32, P]),
+        "tg_batch_signalled_edges": (i32, [P, P]),
         "tg_flag_create": (i32, [P]),
         "tg_flag_destroy": (i32, [P]),
         "tg_flag_set": (i32, [P, u32]),
@@ -658,6 +659,13 @@ def tg_batch_kernel_times(b, n: int = 64) -> np.ndarray:
 
 def tg_batch_set_rounds(b, rounds: int):
     _check(load().tg_batch_set_rounds(b, rounds), "tg_batch_set_rounds")
+
+
+def tg_batch_signalled_edges(b) -> int:
+    """Edges the batch's layout signals with a counter atomic per launch."""
+    e = ctypes.c_uint64()
+    _check(load().tg_batch_signalled_edges(b, ctypes.byref(e)), "tg_batch_signalled_edges")
+    return e.value
 
 
 def tg_batch_info(b, with_times: bool = False):

@@ -105,3 +105,27 @@ def test_benchmark_step_full_size(gpu, schedule):
                 check_explicit(g, eg, ref)
     finally:
         tg.tg_batch_destroy(b)
+
+
+def test_signalled_edges_per_dispatch(gpu):
+    """The ready queue signals every edge; the per-worker lists of a column
+    schedule leave out the edges between consecutive entries of one list (a
+    stencil keeps each column on one worker, so each of its T-1 in-column
+    edges is among them), and still give the oracle's digests."""
+    W, T = 64, 40
+    eg = wl.pattern_graph("stencil", W, T, seed=4, n=64, rounds=2)
+    g = tg.graph_from_explicit(eg)
+    ref = oracle_explicit(eg, want_payload=False)
+    got = {}
+    for name, cfg in (("queue", tg.make_config(dispatch=tg.TG_DISPATCH_QUEUE)),
+                      ("lists", tg.make_config(dispatch=tg.TG_DISPATCH_LISTS, schedule=tg.TG_SCHED_COLUMN))):
+        b = tg.tg_batch_create([g.handle], cfg)
+        try:
+            got[name] = tg.tg_batch_signalled_edges(b)
+            tg.tg_batch_execute(b)
+            tg.tg_batch_wait(b)
+            check_explicit(g, eg, ref)
+        finally:
+            tg.tg_batch_destroy(b)
+    assert got["queue"] == eg.E
+    assert got["lists"] == eg.E - W * (T - 1)
