@@ -85,6 +85,16 @@ def run_alone(args, stream, probes=None):
             "parity": ok, "launch": tg.tg_graph_exec_info(g.handle)[0]}
 
 
+def oracle_rate(tasks, refs, wall_s, processes):
+    """The oracle's throughput on a parity sample: tasks over the summed
+    single-process oracle seconds (one core), and over the pool's wall time
+    with `processes` worker processes side by side."""
+    busy = sum(r[2] for r in refs)
+    return {"kind": "oracle", "tasks": int(tasks), "tasks_per_s_one_core": tasks / busy if busy else None,
+            "tasks_per_s_pool": tasks / wall_s if wall_s else None, "processes": processes,
+            "oracle_s": busy, "wall_s": wall_s}
+
+
 # ---------------------------------------------------------------- implicit
 
 RETENTION = {"all": tg.TG_KEEP_ALL, "sinks": tg.TG_KEEP_SINKS}
@@ -151,6 +161,27 @@ def run_implicit(args, stream, probes=None):
     rok = parity()
     log(f"implicit: {ms:.2f} ms (parity {ok}); reduced DAG {E - removed} edges, {rms:.2f} ms (parity {rok})")
     pi = (probes or {}).get("mix_word_rounds_per_s")
+    cpu = None
+    if "cpu" not in getattr(args, "skipset", set()):
+        # the oracle on the program's first sweep (1024 tasks, the same
+        # requirements and seed; about 4 s on one core), one thread pinned
+        # to one core; its digests must equal the stored first-sweep hash
+        import oracle
+        ig1 = wl.halo_graph(1024, 16384, 1, seed=0, rounds=64)
+        allowed = sorted(os.sched_getaffinity(0))
+        old = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {allowed[0]})
+        try:
+            tc = time.perf_counter()
+            r1 = oracle.implicit_program_order(ig1.N, ig1.req_ptr, ig1.lo, ig1.hi, ig1.priv, ig1.rounds, ig1.space,
+                                               seed=ig1.seed)
+            cs = time.perf_counter() - tc
+        finally:
+            os.sched_setaffinity(0, old)
+        cpu = {"kind": "oracle", "cores": 1, "sample": "the first sweep: 1024 tasks over 2^24 u32, R=64",
+               "tasks_per_s": ig1.N / cs, "word_rounds_per_s": 16384 * 64 * ig1.N / cs, "oracle_s": cs,
+               "matches_stored_first_sweep": _sha(r1["digest"]) == gold["sweep_digest_sha256"][0]}
+        log(f"implicit: oracle first sweep {cs:.1f} s on one core")
     return {
         "workload": "implicit halo program: 65536 tasks, 2^24 u32 in 1024 subregions, halos 1..64, R=64",
         "tasks": ig.N, "inferred_edges": E, "edges_expected": 6254592, "infer_ms": tm["infer_ms"],
@@ -162,6 +193,7 @@ def run_implicit(args, stream, probes=None):
         "parity": {"ok": ok, "against": "oracle program order, stored by tests/golden/make_halo_program_r64.py: "
                                         "checksum, SHA-256 of all 65536 digests and of the 2^24-element array"},
         "reduced": {"edges": E - removed, "reduce_ms": reduce_ms, "exec_ms": rms, "parity": rok},
+        "cpu_oracle": cpu,
     }
 
 
@@ -287,7 +319,9 @@ def run_batch(args, stream, probes=None):
     bad = [i for i, (dig, cs, _) in zip(sample, refs)
            if not (np.array_equal(tg.tg_graph_read_digests(gs[i].handle), dig) and
                    tg.tg_graph_checksum(gs[i].handle) == cs)]
-    log(f"batch: parity on {len(sample)} graphs ({time.perf_counter() - tp:.0f} s, {workers} processes): "
+    pool_s = time.perf_counter() - tp
+    cpu = oracle_rate(sum(egs[i].N for i in sample), refs, pool_s, workers)
+    log(f"batch: parity on {len(sample)} graphs ({pool_s:.0f} s, {workers} processes): "
         f"{'ok' if not bad else bad}")
     # comparators: one persistent launch per graph (seeded sample of 256),
     # and one kernel per task / hipGraph replays on a seeded subsample of
@@ -315,7 +349,8 @@ def run_batch(args, stream, probes=None):
     rec.update({
         "parity": {"ok": not bad, "graphs": len(sample), "failed": bad, "oracle_processes": workers,
                    "sample": "per (pattern, payload) cell the highest-R graph and one random graph, plus the 14 "
-                             f"highest-R graphs, all under {BATCH_COST_CAP:.1e} word-rounds (seed 7)"},
+                             f"highest-R graphs, all under {BATCH_COST_CAP:.1e} word-rounds (seed 7)",
+                   "cpu_oracle": cpu},
         "one_launch_per_graph": {"sample_graphs": len(sample256), "tasks": seq_tasks,
                                  "tasks_per_s": seq_tasks / (seq_ms * 1e-3)},
         "kernel_per_task_subsample": {
@@ -392,12 +427,15 @@ def run_serving(args, stream, probes=None):
     pick = sorted(int(i) for i in np.random.default_rng(1).choice(len(reqs), size=min(64, len(reqs)), replace=False))
     exp = [i for i in pick if reqs[i].mode == "explicit"]
     imp = [i for i in pick if reqs[i].mode == "implicit"]
+    tp = time.perf_counter()
     refs = dict(zip(exp, opar.explicit_many([(reqs[i].pattern, reqs[i].W, reqs[i].T, reqs[i].seed, reqs[i].n,
                                                reqs[i].rounds) for i in exp])))
     refs.update(zip(imp, opar.implicit_many([(reqs[i].P, 256, reqs[i].iters, reqs[i].seed, reqs[i].rounds)
                                              for i in imp])))
+    pool_s = time.perf_counter() - tp
     bad = [i for i in pick if not (np.array_equal(tg.tg_graph_read_digests(handles[i].handle), refs[i][0]) and
                                    tg.tg_graph_checksum(handles[i].handle) == refs[i][1])]
+    cpu = oracle_rate(sum(graphs[i].N for i in pick), list(refs.values()), pool_s, opar.default_workers())
     return {
         "workload": f"serving: Poisson {args.rate:.0f} req/s, {args.requests} measured requests after {warm} warm-up, "
                     "sizes LogNormal(median 4096, sigma 1) in [64, 2^20], explicit/implicit 1:1, 64 GB budget, "
@@ -415,5 +453,5 @@ def run_serving(args, stream, probes=None):
         "explicit_payload_bytes": payload_run, "explicit_payload_bytes_keep_all": payload_all,
         "implicit_dag": "reduced (last-user, two-hop)" if reduce_implicit else "full inferred DAG",
         "parity": {"ok": not bad, "requests": len(pick), "failed": bad,
-                   "sample": "64 requests drawn with seed 1 from all submitted"},
+                   "sample": "64 requests drawn with seed 1 from all submitted", "cpu_oracle": cpu},
     }
