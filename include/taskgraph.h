@@ -119,9 +119,12 @@ typedef struct {
  *                  the level order but gives each task to the worker with the
  *                  least estimated work so far (tasks of very different
  *                  costs).
- *   gang         : mapping 3: workgroups per gang (2..32).  Member 0 runs the
- *                  scheduling loop and publishes each task to the others; the
- *                  task's work items are split over all members. */
+ *   gang         : mapping 3: workgroups per gang (2..32).  Every member runs
+ *                  the scheduling loop of the gang's list, executes its share
+ *                  of each task's work items and signals the task's out-edges
+ *                  itself (a counter starts at in-degree x gang; TG_EINVAL if
+ *                  that exceeds 2^31 - 1); the digest is the sum of the
+ *                  members' parts. */
 typedef struct {
   uint32_t mapping;
   uint32_t workers;
@@ -429,7 +432,9 @@ tg_status tg_batch_info(tg_batch b, tg_exec_config* cfg, uint64_t* tasks, double
 /* Edges of the batch's layout signalled with a counter atomic per launch
  * (Algorithm 1 COMPLETED_EDGE): all executed edges, less those between
  * consecutive entries of one worker's list, which the list dispatch does not
- * count (their order follows from the list).  TG_EINVAL for NULL arguments. */
+ * count (their order follows from the list) unless the workers are gangs
+ * (whose members signal every edge, once each).  TG_EINVAL for NULL
+ * arguments. */
 tg_status tg_batch_signalled_edges(tg_batch b, uint64_t* edges);
 /* Autotuner for a batch (as tg_graph_autotune); keeps the fastest layout. */
 tg_status tg_batch_autotune(tg_batch b, uint32_t reps, tg_exec_config* best, double* best_ms);
@@ -497,7 +502,8 @@ tg_status tg_graph_kernel_times(tg_graph g, double* ms_out, uint32_t n, uint32_t
 tg_status tg_graph_set_rounds(tg_graph g, uint32_t uniform_rounds);
 
 /* Autotuner: time the candidate launch configurations (wavefront or
- * workgroup per task, worker counts, workgroup sizes, doorbell mode) on
+ * workgroup or gang per task, worker and gang counts, workgroup sizes,
+ * schedules, doorbell mode, the ready queue) on
  * this graph, reps executions each, and keep the fastest as the graph's
  * default (used when tg_graph_execute gets cfg == NULL).  Results never
  * depend on the configuration.  *best receives the chosen one; best_ms its

@@ -265,7 +265,7 @@ static void ledger_forget(const void* key);
 struct Layout {
   Config cfg;
   uint32_t nworkers = 0, grid_blocks = 0, npos = 0, last_started = 0;
-  DevBuf rec, pred_addr, succ_pos, indeg, cnt, wbase, gtab, ctrl, execs, wprog, owner, bell, tstamp, wstamp, mbox;
+  DevBuf rec, pred_addr, succ_pos, indeg, cnt, wbase, gtab, ctrl, execs, wprog, owner, bell, tstamp, wstamp;
   DevBuf q, qctl, qsrc;  // ready-queue dispatch
   uint32_t qwmax = 0;    // most workers claiming from one queue shard
   // layouts built on the device (build_layout_device): the graph tables, the
@@ -1062,7 +1062,17 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   const bool keep = cache && !reuse && ntasks <= PlanCache::kMaxTasks && cache->m.size() < PlanCache::kMaxEntries;
   auto kept = keep ? std::make_shared<Plan>() : nullptr;
   if ((s = plan_layout(gs, nw, cfg.schedule, H, reuse, kept.get())) != TG_OK) return s;
-  if (cfg.dispatch == TG_DISPATCH_LISTS) elide_list_edges(H);
+  // A worker's list order replaces the edges between its consecutive entries
+  // only where one team runs the whole task; the members of a gang finish
+  // their shares independently, so there every edge is counted once per
+  // member and a counter starts at in-degree x gang size.
+  if (cfg.dispatch == TG_DISPATCH_LISTS && cfg.mapping != TG_MAP_GANG) elide_list_edges(H);
+  if (cfg.mapping == TG_MAP_GANG)
+    for (uint32_t& c : H.indeg) {
+      if (c > tg::kPendingMask / cfg.gang)
+        return fail(TG_EINVAL, "in-degree %u times a gang of %u exceeds the counter range", c, cfg.gang);
+      c *= cfg.gang;
+    }
   uint64_t signalled = 0;
   for (const TaskRec& r : H.rec) signalled += r.nsucc;
   if (keep) cache->m[key] = kept;
@@ -1125,10 +1135,6 @@ tg_status build_layout(const std::vector<tg_graph>& gs, const Config& cfg, std::
   P.owner = L->owner.as<uint32_t>();
   P.bell = L->bell.as<uint32_t>();
   P.gang = cfg.gang;
-  if (cfg.mapping == TG_MAP_GANG) {
-    if ((s = L->mbox.alloc((size_t)H.nw * tg::kMboxStride * 4)) != TG_OK) return s;
-    P.mbox = L->mbox.as<uint32_t>();
-  }
   P.npos = N;
   P.nworkers = L->nworkers;
   P.window = cfg.window;
@@ -2857,13 +2863,17 @@ tg_status tg_graph_autotune(tg_graph g, uint32_t reps, tg_exec_config* best, dou
     // one worker per task of a typical level
     const uint32_t lw = typical_level_width(std::vector<tg_graph>{g});
     if (lw >= 64 && lw <= rw && lw != rw && lw != rw / 4 && lw != rw / 8) shapes.push_back(mk(TG_MAP_WAVE, lw, 0, 0));
-    // gangs of workgroups on several CUs per task, for large tasks
+    // gangs of workgroups on several CUs per task, for large tasks: every
+    // resident gang, or three quarters of them (which gangs share a CU, and
+    // so how evenly the busy members of a level spread over the CUs, depends
+    // on the gang count: measured up to 6 % apart on a 64-wide wavefront)
     const uint32_t gshape[][3] = {{16, 4, rg16}, {8, 4, rg8}, {8, 8, rg8}, {4, 16, rg4}};
     for (const auto& gsh : gshape)
-      if (gsh[2] / gsh[1]) {
-        shapes.push_back(mk(TG_MAP_GANG, gsh[2] / gsh[1], gsh[0], 0));
-        shapes.back().gang = gsh[1];
-      }
+      for (uint32_t n : {gsh[2] / gsh[1], gsh[2] / gsh[1] * 3 / 4})
+        if (n) {
+          shapes.push_back(mk(TG_MAP_GANG, n, gsh[0], 0));
+          shapes.back().gang = gsh[1];
+        }
     for (auto c : shapes) {
       c.schedule = sch;
       cand.push_back(c);

@@ -98,7 +98,6 @@ struct ExecParams {
   Ctrl* ctrl;
   const uint32_t* owner;       // worker of every position
   uint32_t* bell;              // per-worker doorbell, one per 128-byte line
-  uint32_t* mbox;              // gangs: per gang kMboxStride words (see k_exec_gang)
   uint32_t* execs;             // diagnostics: executions per position (or null)
   uint32_t* wprog;             // diagnostics: list entries finished per worker (or null)
   uint64_t* tstamp;            // diagnostics: per position [start, end] realtime (or null)
@@ -111,7 +110,9 @@ struct ExecParams {
   uint32_t idle_sleep;         // s_sleep(2) steps between empty polls after 64 of them
   uint32_t notify;             // 1: zeroing decrements ring the owner's doorbell
   uint32_t residency_probe;    // 1: check in, wait for all workers (bounded), exit
-  uint32_t gang;               // workgroups per gang (mapping 3), else 1
+  uint32_t gang;               // workgroups per gang (mapping 3), else 1; with gangs the
+                               // counters start at in-degree x gang and digests are
+                               // sums of the members' parts
   uint64_t watchdog_ticks;     // s_memrealtime ticks (100 MHz)
   uint64_t progress_ticks;     // a worker publishes Ctrl::progress at most this often
   // ready-queue dispatch (kernels k_exec_wave_q / k_exec_block_q)
@@ -182,11 +183,7 @@ constexpr uint32_t kQExit = 0xFFFFFFFEu;  // exit sentinel
 constexpr uint32_t kQLine = 32;           // u32 words between queue control words (128 bytes)
 
 constexpr uint32_t kBellStride = 32;  // u32 words between doorbells (128 bytes)
-// Gang mailbox, kMboxStride u32 per gang: [0] sequence number of the last
-// published task, [1] its position, [2] member arrivals, [16 + m] digest part
-// of member m (m < kMaxGang).
-constexpr uint32_t kMboxStride = 64;
-constexpr uint32_t kMaxGang = 32;
+constexpr uint32_t kMaxGang = 32;  // workgroups per gang (mapping 3)
 
 // Launchers (tg_kernels.hip).  All return hipError_t of the launch.
 // mapping 1: one wavefront per task; 2: one workgroup of wg_waves wavefronts;

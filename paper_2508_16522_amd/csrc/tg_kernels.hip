@@ -663,35 +663,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   if (P.wprog && threadIdx.x == 0) P.wprog[worker] = w.h;
 }
 
-// Bounded wait on a gang mailbox word: returns true once *p >= target; false
-// when the launch is being aborted or nothing progressed anywhere for the
-// watchdog interval (the waiter then raises the abort flag itself).
-__device__ bool gang_wait(const ExecParams& P, const uint32_t* p, uint32_t target) {
-  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-  for (uint32_t spins = 1;; ++spins) {
-    if (ld_coherent(p) >= target) return true;
-    if ((spins & 63u) == 0u) {
-      if (ld_coherent(&P.ctrl->abort) != 0u) return false;
-      const bool limit = P.spin_limit != 0u && spins >= P.spin_limit;
-      if (limit || stalled(P, t0, __builtin_amdgcn_s_memrealtime())) {
-        __hip_atomic_fetch_add(&P.ctrl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-}
-
-// A gang of P.gang workgroups per task (on different CUs): member 0 runs the
-// scheduling state machine of the gang's list and publishes each task in the
-// gang's mailbox (position, then sequence number); every member executes its
-// share of the task's work items and reports its digest part and arrival;
-// member 0 waits for all arrivals, stores the digest and signals the
-// out-edges.  Members' payload stores are drained before they report, so
-// the edge signals follow every store of the task.
+// A gang of P.gang workgroups per task (on different CUs), without a leader:
+// every member runs the scheduling loop over the gang's list itself, executes
+// its share of each task's work items, adds its digest part to the task's
+// digest (zeroed by the reset) and signals every out-edge after draining its
+// stores.  A task's counter starts at its in-degree times the gang size, so it
+// becomes ready once every member of every predecessor's gang has finished
+// its share.  No member waits for another: the members of one gang may run
+// different tasks of the list at the same time (each takes its ready entries
+// in its own order), and none of the mailbox round trips a leader would need
+// (publish the task, collect the arrivals) sits between two dependent tasks.
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_exec_gang(ExecParams P) {
   __shared__ uint32_t lds[32];
-  __shared__ uint32_t cmd, ok;
+  __shared__ uint32_t cmd;
   __shared__ uint32_t recl[32];
   const uint32_t G = P.gang;
   const uint32_t gang = blockIdx.x / G, member = blockIdx.x % G;
@@ -703,66 +687,30 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   tm.m = member;
   tm.G = G;
   const uint32_t lane = threadIdx.x & 63u;
-  uint32_t* mb = P.mbox + (size_t)gang * kMboxStride;
   WorkerState w;
   worker_init(w, P, gang);
-  for (uint32_t it = 0;; ++it) {
-    if (member == 0) {
-      if (threadIdx.x < 64) {
-        const uint32_t pos = next_task(P, w, lane);
-        if (pos != kExit) {
-          const uint32_t v = pos == w.pf_pos ? w.pf_v : rec_dword(P, pos, lane);
-          if (lane < 32) recl[lane] = v;
-        }
-        if (lane == 0) {
-          cmd = pos;
-          st_coherent(mb + 1, pos);
-          vm_drain();  // the position is visible before its sequence number
-          __hip_atomic_store(mb + 0, it + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+  for (;;) {
+    if (threadIdx.x < 64) {
+      const uint32_t pos = next_task(P, w, lane);
+      if (pos != kExit) {
+        const uint32_t v = pos == w.pf_pos ? w.pf_v : rec_dword(P, pos, lane);
+        if (lane < 32) recl[lane] = v;
       }
-    } else if (threadIdx.x == 0) {
-      cmd = gang_wait(P, mb + 0, it + 1) ? ld_coherent(mb + 1) : kExit;
+      if (lane == 0) cmd = pos;
     }
     __syncthreads();
     const uint32_t pos = uni(cmd);
-    uint32_t v = member == 0 ? recl[lane & 31u] : 0u;
+    const uint32_t v = recl[lane & 31u];
     __syncthreads();
     if (pos == kExit) break;
-    if (member != 0) v = rec_dword(P, pos, lane);
     Rec r;
     const uint32_t d = run_body(tm, P, pos, v, r);
-    vm_drain();  // this lane's payload stores are complete
-    __syncthreads();
-    if (member != 0) {
-      if (threadIdx.x == 0) {
-        st_coherent(mb + 16 + member, d);
-        vm_drain();
-        __hip_atomic_fetch_add(mb + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      continue;
-    }
-    if (threadIdx.x == 0) {
-      ok = gang_wait(P, mb + 2, (it + 1) * (G - 1)) ? 1u : 0u;
-      if (ok) {
-        uint32_t total = d;
-        for (uint32_t m = 1; m < G; ++m) total += ld_coherent(mb + 16 + m);
-        st_coherent(r.digest + r.tid, total);
-      }
-    }
-    __syncthreads();
-    if (ok == 0u) {
-      // a member did not arrive: the launch is being aborted; tell the
-      // members to stop and leave
-      if (threadIdx.x == 0) {
-        st_coherent(mb + 1, kExit);
-        vm_drain();
-        __hip_atomic_store(mb + 0, it + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      break;
-    }
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(r.digest + r.tid, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     complete_edges(tm, P, r);
-    if (P.tstamp && threadIdx.x == 0) P.tstamp[2 * pos + 1] = __builtin_amdgcn_s_memrealtime();
+    // diagnostics: a task ends when its last member finishes
+    if (P.tstamp && threadIdx.x == 0)
+      __hip_atomic_fetch_max(P.tstamp + 2 * pos + 1, __builtin_amdgcn_s_memrealtime(), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
   }
   if (member == 0 && P.wprog && threadIdx.x == 0) P.wprog[gang] = w.h;
@@ -1077,8 +1025,12 @@ __global__ __launch_bounds__(256) void k_reset(ExecParams P) {
     P.cnt[i] = P.indeg[i];
     if (P.execs) P.execs[i] = 0;
   }
-  if (P.mbox)
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P.nworkers * kMboxStride; i += stride) P.mbox[i] = 0;
+  // gangs add their members' digest parts into the digest words
+  if (P.gang > 1)
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P.npos; i += stride) {
+      const uint32_t* rd = reinterpret_cast<const uint32_t*>(P.rec + i);
+      P.gtab[rd[kDwGraph]].digest[rd[kDwTid]] = 0;
+    }
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P.nworkers; i += stride) {
     P.bell[i * kBellStride] = 0;
     if (P.wprog) P.wprog[i] = 0xFFFFFFFFu;

@@ -250,7 +250,7 @@ def test_watchdog_path_then_recovery(gpu):
 def test_patterns_gangs(gpu, n, gang, wg_waves):
     """Explicit graphs with a gang of workgroups per task: payload words are
     split over the whole gang (a gang wider than the payload leaves members
-    idle), digests combined by member 0."""
+    idle), digests summed from the members' parts."""
     for pattern in ("stencil", "random"):
         eg = wl.pattern_graph(pattern, 13 if n == 65536 else 37, 5 if n == 65536 else 11, seed=4, n=n, rounds=2)
         ref = oracle_explicit(eg)

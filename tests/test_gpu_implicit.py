@@ -113,7 +113,7 @@ GANGS = [dict(mapping=3, wg_waves=1, gang=2), dict(mapping=3, wg_waves=4, gang=3
 @pytest.mark.parametrize("P,S,iters", [(8, 128, 4), (33, 256, 3)])
 def test_halo_small_gangs(gpu, P, S, iters, kw):
     """A gang of workgroups on several CUs per task: the read-write elements
-    are split over the gang, the digest parts are combined by member 0."""
+    are split over the gang, the digest is the sum of the members' parts."""
     ig = wl.halo_graph(P, S, iters, seed=2, rounds=3)
     g = tg.graph_from_implicit(ig)
     run(g, tg.make_config(**kw))
