@@ -143,9 +143,9 @@ def run_implicit(args, stream, probes=None):
                     f"{tg.tg_graph_checksum(g.handle):#018x}" == gold["checksum"])
 
     if getattr(args, "no_tune", False):
-        # the shape the autotuner picks for this program: gangs of eight
-        # 8-wave workgroups, level order
-        cfg = dict(mapping=3, workers=0, wg_waves=8, schedule=tg.TG_SCHED_LEVEL, gang=8)
+        # the shape the autotuner picked for this program: 96 gangs of four
+        # 16-wave workgroups, column order
+        cfg = dict(mapping=3, workers=96, wg_waves=16, schedule=tg.TG_SCHED_COLUMN, gang=4)
         ms = _timed_graph(g, tg.make_config(**cfg), stream, args.warmup, args.steps)
     else:
         cfg, tms = tg.tg_graph_autotune(g.handle, reps=1)

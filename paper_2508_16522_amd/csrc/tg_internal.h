@@ -98,10 +98,6 @@ struct ExecParams {
   Ctrl* ctrl;
   const uint32_t* owner;       // worker of every position
   uint32_t* bell;              // per-worker doorbell, one per 128-byte line
-  uint32_t* execs;             // diagnostics: executions per position (or null)
-  uint32_t* wprog;             // diagnostics: list entries finished per worker (or null)
-  uint64_t* tstamp;            // diagnostics: per position [start, end] realtime (or null)
-  uint64_t* wstamp;            // diagnostics: per worker [first poll, last scan, scans, bell reads]
   uint32_t npos;
   uint32_t nworkers;
   uint32_t window;             // 1..64
@@ -133,6 +129,13 @@ struct ExecParams {
   uint32_t gseq;
   uint32_t gated;              // 1: a pre-condition wait precedes the launch; workers
                                // leave at once if it gave up (Ctrl::abort set)
+  // diagnostics, last: the kernels read them rarely, and with these four
+  // pointers after the fields the executors read on every task the compiler
+  // keeps more of the latter in scalar registers (fewer spills)
+  uint32_t* execs;             // diagnostics: executions per position (or null)
+  uint32_t* wprog;             // diagnostics: list entries finished per worker (or null)
+  uint64_t* tstamp;            // diagnostics: per position [start, end] realtime (or null)
+  uint64_t* wstamp;            // diagnostics: per worker [first poll, last scan, scans, bell reads]
 };
 
 // Pre-condition flags of one launch (words in pinned host memory mapped for

@@ -186,3 +186,16 @@ def test_reduce_rejects_explicit(gpu):
     with pytest.raises(tg.TaskGraphError) as ei:
         tg.tg_graph_reduce_edges(g.handle)
     assert ei.value.status == tg.TG_EINVAL
+
+
+def test_gang_digests_restart_every_launch(gpu):
+    """A gang adds its members' digest parts into the digest words, which the
+    reset zeroes before every launch: three gang launches in a row, then one
+    wavefront launch and a gang launch again, each bit-exact."""
+    ig = wl.halo_graph(12, 192, 5, seed=4, rounds=3)
+    g = tg.graph_from_implicit(ig)
+    ref = _ref(ig)
+    gang = tg.make_config(mapping=3, wg_waves=2, gang=4)
+    for cfg in (gang, gang, gang, tg.make_config(mapping=1), gang):
+        run(g, cfg)
+        _check_exec(g, ig, ref)
