@@ -103,9 +103,9 @@ typedef struct {
  *                  owning worker's doorbell, and idle workers poll only their
  *                  doorbell (fewer polls, one more hop per task).
  *   idle_sleep   : back-off of an idle worker, in units of 128 cycles
- *                  (1..64, default 2), after its first 64 empty polls; it
- *                  doubles after every further 64 empty polls, up to 32 times
- *                  this value (at most 256 units).
+ *                  (1..64, default 2), after its first 64 empty polls; with
+ *                  the lists it doubles after every further 64 empty polls,
+ *                  up to 32 times this value (at most 256 units).
  *   schedule     : how tasks are partitioned over the workers' lists
  *                  (Algorithm 1, Compile): TG_SCHED_LEVEL (default) sorts by
  *                  dependence level and deals round-robin; TG_SCHED_SPREAD

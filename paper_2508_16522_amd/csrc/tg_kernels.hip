@@ -850,8 +850,13 @@ __device__ uint32_t queue_next(const ExecParams& P, QueueState& q, uint32_t lane
   if (v == kQEmpty) {
     queue_report(P, q, lane);  // nothing to run now: report the finished sinks first
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    // a fixed back-off here, not the growing one of the lists: a queue
+    // worker waits for whichever task is pushed next, and in the serving
+    // loop a late claim delays a request (median latency 9.7 ms with the
+    // fixed back-off, 11.4 ms with the growing one, same box)
     for (uint32_t spins = 1;; ++spins) {
-      idle_nap(P, spins);
+      const uint32_t nap = spins < 64 ? 1u : P.idle_sleep;
+      for (uint32_t i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(2);
       v = uni(ld_coherent(slot));
       if (v != kQEmpty) break;
       if ((spins & 63u) == 0u) {
