@@ -481,7 +481,8 @@ tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t
 tg_status tg_emulate_queue(const tg_graph* graphs, uint32_t ngraphs, uint32_t nworkers, uint32_t shards, uint32_t tile,
                            uint64_t seed, uint64_t* order, uint64_t* executed);
 /* After a diagnostic launch (diag=1) of the graph on its own: per task (by
- * event) the pending in-edge counter, the number of times it ran, its worker
+ * event) the pending in-edge counter (with gangs, every in-edge counts once
+ * per gang member), the number of times it ran, its worker
  * and its entry in that worker's list; optionally (wprog != NULL, nworkers =
  * the launch's worker count) how many list entries each worker finished. */
 tg_status tg_graph_debug_state(tg_graph g, uint32_t* pending, uint32_t* execs, uint32_t* owner, uint32_t* entry,
