@@ -480,6 +480,19 @@ tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t
  * does not terminate. */
 tg_status tg_emulate_queue(const tg_graph* graphs, uint32_t ngraphs, uint32_t nworkers, uint32_t shards, uint32_t tile,
                            uint64_t seed, uint64_t* order, uint64_t* executed);
+/* Host-only model of a gang launch (mapping 3, Algorithm 1 EXECUTE_OP with
+ * one task per gang of workgroups) over graphs[0..ngraphs): ngangs lists
+ * compiled with `schedule` (0 = default), and `gang` members per list that
+ * each scan, take and finish their share on their own, in a seeded
+ * interleaving; a counter starts at in-degree x gang and each member
+ * decrements every out-edge once.  Checks that a member takes a task only
+ * after every member of each predecessor finished it and that every member
+ * runs each entry of its list exactly once.  *executed = shares finished
+ * (total #tasks x gang on success); TG_ETIMEOUT if the members get stuck,
+ * TG_EINVAL for a violated check or arguments out of range (window 1..64,
+ * ngangs >= 1, gang 1..32). */
+tg_status tg_emulate_gang(const tg_graph* graphs, uint32_t ngraphs, uint32_t ngangs, uint32_t gang, uint32_t window,
+                          uint32_t schedule, uint64_t seed, uint64_t* executed);
 /* After a diagnostic launch (diag=1) of the graph on its own: per task (by
  * event) the pending in-edge counter (with gangs, every in-edge counts once
  * per gang member), the number of times it ran, its worker

@@ -1483,6 +1483,119 @@ tg_status emulate_layout(const HostLayout& H, uint32_t window, uint64_t seed, ui
   return ex == N ? TG_OK : fail(TG_EINVAL, "executed %llu of %u tasks", (unsigned long long)ex, N);
 }
 
+// CPU model of the gang executor (k_exec_gang): every one of the G members of
+// a gang runs the list dispatch over the gang's list on its own (ready window,
+// ballot, oldest entry first), a counter starts at in-degree x G and every
+// member decrements each out-edge once when it finishes its share, and the
+// in-list edge elision is off.  A member's share is two steps -- take, then
+// finish -- so other members and gangs interleave with it, in a seeded
+// pseudo-random order.  Checks: a member takes a task only after every member
+// of each predecessor has finished it, every member runs each entry of its
+// list exactly once, no counter underflows, and no interleaving leaves the
+// members stuck.  *executed counts finished shares (N x G when all ran).
+tg_status emulate_gang_layout(const HostLayout& H, uint32_t G, uint32_t window, uint64_t seed, uint64_t* executed) {
+  const uint32_t N = H.N, nw = H.nw;
+  const uint32_t kIdle = 0xFFFFFFFFu;
+  struct M {
+    uint32_t h = 0, run = 0xFFFFFFFFu;
+    uint64_t done = 0, pend = 0;
+  };
+  std::vector<uint32_t> cnt(N), finished(N, 0);
+  for (uint32_t p = 0; p < N; ++p) {
+    if (H.indeg[p] > tg::kPendingMask / G) return fail(TG_EINVAL, "in-degree too large for the gang");
+    cnt[p] = H.indeg[p] * G;
+  }
+  // predecessors by position, to check precedence at each take
+  std::vector<uint32_t> pptr(N + 1, 0), pred;
+  for (uint32_t p = 0; p < N; ++p)
+    for (uint32_t j = 0; j < H.rec[p].nsucc; ++j) pptr[H.succ_pos[H.rec[p].succ_beg + j] + 1]++;
+  for (uint32_t p = 0; p < N; ++p) pptr[p + 1] += pptr[p];
+  pred.resize(pptr[N]);
+  {
+    std::vector<uint32_t> fill(pptr.begin(), pptr.end() - 1);
+    for (uint32_t p = 0; p < N; ++p)
+      for (uint32_t j = 0; j < H.rec[p].nsucc; ++j) pred[fill[H.succ_pos[H.rec[p].succ_beg + j]]++] = p;
+  }
+  std::vector<M> mem((size_t)nw * G);
+  std::vector<uint32_t> active;
+  for (uint32_t w = 0; w < nw; ++w)
+    if (H.wbase[w + 1] > H.wbase[w])
+      for (uint32_t m = 0; m < G; ++m) active.push_back(w * G + m);
+  uint64_t ex = 0, rng = seed * 0x9E3779B97F4A7C15ull + 1, idle = 0;
+  auto scan = [&](uint32_t a) {
+    const M& x = mem[a];
+    const uint32_t w = a / G, wb = H.wbase[w], wcnt = H.wbase[w + 1] - wb;
+    uint64_t ready = 0;
+    for (uint32_t lane = 0; lane < 64; ++lane) {
+      const uint32_t idx = x.h + lane;
+      const bool valid = lane < window && idx < wcnt && !((x.done >> lane) & 1ull);
+      if (valid && (cnt[wb + idx] & tg::kPendingMask) == 0) ready |= 1ull << lane;
+    }
+    return ready;
+  };
+  while (!active.empty()) {
+    rng ^= rng << 13;
+    rng ^= rng >> 7;
+    rng ^= rng << 17;
+    const size_t ai = (size_t)(rng % active.size());
+    const uint32_t a = active[ai];
+    M& x = mem[a];
+    const uint32_t w = a / G, wb = H.wbase[w], wcnt = H.wbase[w + 1] - wb;
+    if (x.run != kIdle) {  // finish this member's share
+      const TaskRec& r = H.rec[x.run];
+      for (uint32_t j = 0; j < r.nsucc; ++j) {
+        uint32_t& c = cnt[H.succ_pos[r.succ_beg + j]];
+        if ((c & tg::kPendingMask) == 0)
+          return fail(TG_EINVAL, "counter underflow at position %u", H.succ_pos[r.succ_beg + j]);
+        --c;
+      }
+      if (++finished[x.run] > G) return fail(TG_EINVAL, "position %u finished more than %u times", x.run, G);
+      x.run = kIdle;
+      ++ex;
+      idle = 0;
+      continue;
+    }
+    if (!x.pend) {
+      const uint32_t adv = (~x.done == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~x.done);
+      x.h += adv;
+      x.done = adv >= 64u ? 0ull : (x.done >> adv);
+      if (x.h >= wcnt) {
+        active[ai] = active.back();
+        active.pop_back();
+        continue;
+      }
+      x.pend = scan(a);
+      if (!x.pend) {
+        if (++idle > 64ull * active.size() + 1024) {
+          bool any = false;
+          for (uint32_t a2 : active)
+            if (mem[a2].pend || mem[a2].run != kIdle || scan(a2)) any = true;
+          if (!any) {
+            *executed = ex;
+            return fail(TG_ETIMEOUT, "gang schedule deadlocks after %llu of %llu shares", (unsigned long long)ex,
+                        (unsigned long long)N * G);
+          }
+          idle = 0;
+        }
+        continue;
+      }
+    }
+    idle = 0;
+    const uint32_t b = (uint32_t)__builtin_ctzll(x.pend);
+    x.pend &= x.pend - 1;
+    x.done |= 1ull << b;
+    const uint32_t pos = wb + x.h + b;
+    for (uint32_t i = pptr[pos]; i < pptr[pos + 1]; ++i)
+      if (finished[pred[i]] != G)
+        return fail(TG_EINVAL, "position %u taken before its predecessor %u finished", pos, pred[i]);
+    x.run = pos;
+  }
+  *executed = ex;
+  for (uint32_t p = 0; p < N; ++p)
+    if (finished[p] != G) return fail(TG_EINVAL, "position %u finished %u of %u times", p, finished[p], G);
+  return TG_OK;
+}
+
 // CPU model of the ready-queue dispatch (k_exec_wave_q): workers take one
 // step at a time in a seeded pseudo-random order, and every access to shared
 // state is a step of its own, so the model visits the interleavings the
@@ -3254,6 +3367,22 @@ tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t
   for (uint64_t i = 0; i < *executed; ++i) order[i] = key_of[ord[i]];
   if (s == TG_OK && makespan && bound) timed_makespan(gs, H, window, makespan, bound);
   return s;
+}
+
+tg_status tg_emulate_gang(const tg_graph* graphs, uint32_t ngraphs, uint32_t ngangs, uint32_t gang, uint32_t window,
+                          uint32_t schedule, uint64_t seed, uint64_t* executed) {
+  if (!graphs || !ngraphs || !executed) return fail(TG_EINVAL, "NULL argument");
+  if (window < 1 || window > 64 || ngangs == 0 || gang < 1 || gang > tg::kMaxGang)
+    return fail(TG_EINVAL, "window in [1,64], ngangs >= 1, gang in [1,%u]", tg::kMaxGang);
+  std::vector<tg_graph> gs(graphs, graphs + ngraphs);
+  for (auto g : gs) {
+    if (!g) return fail(TG_EINVAL, "NULL graph");
+    if (!g->finalized) return fail(TG_ESTATE, "graph not finalised");
+  }
+  HostLayout H;
+  tg_status s = plan_layout(gs, ngangs, schedule ? schedule : (uint32_t)TG_SCHED_LEVEL, H);
+  if (s != TG_OK) return s;
+  return emulate_gang_layout(H, gang, window, seed, executed);
 }
 
 tg_status tg_emulate_queue(const tg_graph* graphs, uint32_t ngraphs, uint32_t nworkers, uint32_t shards, uint32_t tile,

@@ -43,7 +43,7 @@ EXPORTS = (
     "tg_batch_kernel_times", "tg_batch_set_rounds", "tg_batch_signalled_edges", "tg_batch_info", "tg_batch_autotune",
     "tg_graph_execute_after", "tg_flag_create", "tg_flag_destroy", "tg_flag_set", "tg_flag_read", "tg_flag_wait",
     "tg_graph_execute_when", "tg_reduce_dag", "tg_last_user_dag", "tg_graph_reduce_edges",
-    "tg_graph_set_retention", "tg_graph_payload_slots", "tg_graph_read_exec_dag", "tg_emulate_queue",
+    "tg_graph_set_retention", "tg_graph_payload_slots", "tg_graph_read_exec_dag", "tg_emulate_gang", "tg_emulate_queue",
     "tg_infer_dag", "tg_infer_dag_noalloc", "tg_server_configure",
 )
 
@@ -132,6 +132,7 @@ def load() -> ctypes.CDLL:
         "tg_batch_autotune": (i32, [G, u32, P, P]),
         "tg_graph_execute_after": (i32, [G, P, P, P, u32, P]),
         "tg_batch_signalled_edges": (i32, [P, P]),
+        "tg_emulate_gang": (i32, [P, u32, u32, u32, u32, u32, u64, P]),
         "tg_flag_create": (i32, [P]),
         "tg_flag_destroy": (i32, [P]),
         "tg_flag_set": (i32, [P, u32]),
@@ -549,6 +550,15 @@ def tg_emulate_queue(graphs, nworkers: int, shards: int = 8, tile: int = 1, seed
     st = load().tg_emulate_queue(arr, len(hs), nworkers, shards, tile, seed, _ptr(order), ctypes.byref(ex))
     o = order[:ex.value]
     return st, np.stack([(o >> np.uint64(32)).astype(np.int64), (o & np.uint64(0xFFFFFFFF)).astype(np.int64)], axis=1)
+
+
+def tg_emulate_gang(graphs, ngangs: int, gang: int, window: int = 64, seed: int = 0, schedule: int = 0):
+    """Host-only model of a gang launch: returns (status, shares finished)."""
+    hs = list(graphs) if isinstance(graphs, (list, tuple)) else [graphs]
+    arr = (ctypes.c_void_p * len(hs))(*[ctypes.cast(h, ctypes.c_void_p) for h in hs])
+    ex = ctypes.c_uint64()
+    st = load().tg_emulate_gang(arr, len(hs), ngangs, gang, window, schedule, seed, ctypes.byref(ex))
+    return st, ex.value
 
 
 def tg_graph_emulate_schedule(g, nworkers: int, window: int = 64, seed: int = 0, schedule: int = 0):
