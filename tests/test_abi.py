@@ -117,3 +117,10 @@ def test_execute_when_argument_errors(tglib):
     assert tglib.tg_graph_execute_when(g, None, None, flags, vals, 1, None, 0) == tg.TG_EINVAL  # flags[0] NULL
     assert tglib.tg_graph_execute_when(None, None, None, None, None, 0, None, 0) == tg.TG_EINVAL
     tglib.tg_graph_destroy(g)
+
+
+def test_batch_queries_refuse_null(tglib):
+    """Batch queries with a NULL batch or output are refused, no device work."""
+    e = ctypes.c_uint64()
+    assert tglib.tg_batch_signalled_edges(None, ctypes.byref(e)) == tg.TG_EINVAL
+    assert tglib.tg_batch_info(None, None, None, None, None) == tg.TG_EINVAL
