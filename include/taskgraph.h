@@ -487,12 +487,14 @@ tg_status tg_emulate_queue(const tg_graph* graphs, uint32_t ngraphs, uint32_t nw
  * interleaving; a counter starts at in-degree x gang and each member
  * decrements every out-edge once.  Checks that a member takes a task only
  * after every member of each predecessor finished it and that every member
- * runs each entry of its list exactly once.  *executed = shares finished
- * (total #tasks x gang on success); TG_ETIMEOUT if the members get stuck,
- * TG_EINVAL for a violated check or arguments out of range (window 1..64,
- * ngangs >= 1, gang 1..32). */
+ * runs each entry of its list exactly once.  elide != 0 models the lists'
+ * in-list edge elision, which gang launches do not use (a member could then
+ * run ahead of the others; the check reports it).  *executed = shares
+ * finished (total #tasks x gang on success); TG_ETIMEOUT if the members get
+ * stuck, TG_EINVAL for a violated check or arguments out of range (window
+ * 1..64, ngangs >= 1, gang 1..32). */
 tg_status tg_emulate_gang(const tg_graph* graphs, uint32_t ngraphs, uint32_t ngangs, uint32_t gang, uint32_t window,
-                          uint32_t schedule, uint64_t seed, uint64_t* executed);
+                          uint32_t schedule, uint64_t seed, uint32_t elide, uint64_t* executed);
 /* After a diagnostic launch (diag=1) of the graph on its own: per task (by
  * event) the pending in-edge counter (with gangs, every in-edge counts once
  * per gang member), the number of times it ran, its worker

@@ -1493,7 +1493,18 @@ tg_status emulate_layout(const HostLayout& H, uint32_t window, uint64_t seed, ui
 // of each predecessor has finished it, every member runs each entry of its
 // list exactly once, no counter underflows, and no interleaving leaves the
 // members stuck.  *executed counts finished shares (N x G when all ran).
-tg_status emulate_gang_layout(const HostLayout& H, uint32_t G, uint32_t window, uint64_t seed, uint64_t* executed) {
+// With `elide` the model applies the lists' in-list edge elision, which the
+// gang executor leaves off: a member may then take the next entry of its list
+// before the other members finished the one before it, and the precedence
+// check reports that.
+tg_status emulate_gang_layout(const HostLayout& H0, uint32_t G, uint32_t window, uint64_t seed, bool elide,
+                              uint64_t* executed) {
+  HostLayout E;
+  if (elide) {
+    E = H0;
+    elide_list_edges(E);
+  }
+  const HostLayout& H = elide ? E : H0;
   const uint32_t N = H.N, nw = H.nw;
   const uint32_t kIdle = 0xFFFFFFFFu;
   struct M {
@@ -1502,19 +1513,21 @@ tg_status emulate_gang_layout(const HostLayout& H, uint32_t G, uint32_t window, 
   };
   std::vector<uint32_t> cnt(N), finished(N, 0);
   for (uint32_t p = 0; p < N; ++p) {
-    if (H.indeg[p] > tg::kPendingMask / G) return fail(TG_EINVAL, "in-degree too large for the gang");
-    cnt[p] = H.indeg[p] * G;
+    const uint32_t d = H.indeg[p] & tg::kPendingMask;
+    if (d > tg::kPendingMask / G) return fail(TG_EINVAL, "in-degree too large for the gang");
+    cnt[p] = d * G | (H.indeg[p] & tg::kAfterPrev);
   }
-  // predecessors by position, to check precedence at each take
+  // predecessors by position (every edge of the graph, elided or not), to
+  // check precedence at each take
   std::vector<uint32_t> pptr(N + 1, 0), pred;
   for (uint32_t p = 0; p < N; ++p)
-    for (uint32_t j = 0; j < H.rec[p].nsucc; ++j) pptr[H.succ_pos[H.rec[p].succ_beg + j] + 1]++;
+    for (uint32_t j = 0; j < H0.rec[p].nsucc; ++j) pptr[H0.succ_pos[H0.rec[p].succ_beg + j] + 1]++;
   for (uint32_t p = 0; p < N; ++p) pptr[p + 1] += pptr[p];
   pred.resize(pptr[N]);
   {
     std::vector<uint32_t> fill(pptr.begin(), pptr.end() - 1);
     for (uint32_t p = 0; p < N; ++p)
-      for (uint32_t j = 0; j < H.rec[p].nsucc; ++j) pred[fill[H.succ_pos[H.rec[p].succ_beg + j]]++] = p;
+      for (uint32_t j = 0; j < H0.rec[p].nsucc; ++j) pred[fill[H0.succ_pos[H0.rec[p].succ_beg + j]]++] = p;
   }
   std::vector<M> mem((size_t)nw * G);
   std::vector<uint32_t> active;
@@ -1529,7 +1542,9 @@ tg_status emulate_gang_layout(const HostLayout& H, uint32_t G, uint32_t window, 
     for (uint32_t lane = 0; lane < 64; ++lane) {
       const uint32_t idx = x.h + lane;
       const bool valid = lane < window && idx < wcnt && !((x.done >> lane) & 1ull);
-      if (valid && (cnt[wb + idx] & tg::kPendingMask) == 0) ready |= 1ull << lane;
+      const uint32_t c = cnt[wb + idx < N ? wb + idx : 0];
+      const bool prev_taken = lane == 0 || ((x.done >> (lane - 1)) & 1ull);
+      if (valid && (c & tg::kPendingMask) == 0 && (!(c & tg::kAfterPrev) || prev_taken)) ready |= 1ull << lane;
     }
     return ready;
   };
@@ -3370,7 +3385,7 @@ tg_status tg_emulate_schedule(const tg_graph* graphs, uint32_t ngraphs, uint32_t
 }
 
 tg_status tg_emulate_gang(const tg_graph* graphs, uint32_t ngraphs, uint32_t ngangs, uint32_t gang, uint32_t window,
-                          uint32_t schedule, uint64_t seed, uint64_t* executed) {
+                          uint32_t schedule, uint64_t seed, uint32_t elide, uint64_t* executed) {
   if (!graphs || !ngraphs || !executed) return fail(TG_EINVAL, "NULL argument");
   if (window < 1 || window > 64 || ngangs == 0 || gang < 1 || gang > tg::kMaxGang)
     return fail(TG_EINVAL, "window in [1,64], ngangs >= 1, gang in [1,%u]", tg::kMaxGang);
@@ -3382,7 +3397,7 @@ tg_status tg_emulate_gang(const tg_graph* graphs, uint32_t ngraphs, uint32_t nga
   HostLayout H;
   tg_status s = plan_layout(gs, ngangs, schedule ? schedule : (uint32_t)TG_SCHED_LEVEL, H);
   if (s != TG_OK) return s;
-  return emulate_gang_layout(H, gang, window, seed, executed);
+  return emulate_gang_layout(H, gang, window, seed, elide != 0, executed);
 }
 
 tg_status tg_emulate_queue(const tg_graph* graphs, uint32_t ngraphs, uint32_t nworkers, uint32_t shards, uint32_t tile,

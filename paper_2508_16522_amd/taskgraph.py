@@ -132,7 +132,7 @@ def load() -> ctypes.CDLL:
         "tg_batch_autotune": (i32, [G, u32, P, P]),
         "tg_graph_execute_after": (i32, [G, P, P, P, u32, P]),
         "tg_batch_signalled_edges": (i32, [P, P]),
-        "tg_emulate_gang": (i32, [P, u32, u32, u32, u32, u32, u64, P]),
+        "tg_emulate_gang": (i32, [P, u32, u32, u32, u32, u32, u64, u32, P]),
         "tg_flag_create": (i32, [P]),
         "tg_flag_destroy": (i32, [P]),
         "tg_flag_set": (i32, [P, u32]),
@@ -552,12 +552,14 @@ def tg_emulate_queue(graphs, nworkers: int, shards: int = 8, tile: int = 1, seed
     return st, np.stack([(o >> np.uint64(32)).astype(np.int64), (o & np.uint64(0xFFFFFFFF)).astype(np.int64)], axis=1)
 
 
-def tg_emulate_gang(graphs, ngangs: int, gang: int, window: int = 64, seed: int = 0, schedule: int = 0):
+def tg_emulate_gang(graphs, ngangs: int, gang: int, window: int = 64, seed: int = 0, schedule: int = 0,
+                    elide: bool = False):
     """Host-only model of a gang launch: returns (status, shares finished)."""
     hs = list(graphs) if isinstance(graphs, (list, tuple)) else [graphs]
     arr = (ctypes.c_void_p * len(hs))(*[ctypes.cast(h, ctypes.c_void_p) for h in hs])
     ex = ctypes.c_uint64()
-    st = load().tg_emulate_gang(arr, len(hs), ngangs, gang, window, schedule, seed, ctypes.byref(ex))
+    st = load().tg_emulate_gang(arr, len(hs), ngangs, gang, window, schedule, seed, 1 if elide else 0,
+                                ctypes.byref(ex))
     return st, ex.value
 
 

@@ -75,3 +75,23 @@ def test_arguments(tglib):
     for ngangs, gang, window in [(0, 2, 64), (4, 0, 64), (4, 33, 64), (4, 2, 0), (4, 2, 65)]:
         st, _ = tg.tg_emulate_gang([g.handle], ngangs, gang, window)
         assert st == tg.TG_EINVAL
+
+
+def test_in_list_elision_would_break_gangs(tglib):
+    """Why gang launches count every edge: with the lists' in-list elision a
+    member takes the next entry of its list as soon as it finished its own
+    share of the previous one, before the other members have; the model
+    reports the violated precedence (a stencil column kept on one gang)."""
+    g = tg.graph_from_explicit(wl.pattern_graph("stencil", 8, 24, seed=0, n=64))
+    caught = 0
+    for seed in range(8):
+        st, _ = tg.tg_emulate_gang([g.handle], 8, 4, 64, seed, tg.TG_SCHED_COLUMN, elide=True)
+        assert st in (tg.TG_OK, tg.TG_EINVAL)
+        caught += st == tg.TG_EINVAL
+    assert caught > 0
+    # without the elision (the executor's rule) every seed passes
+    _check([g], 8, 4, schedule=tg.TG_SCHED_COLUMN, seeds=range(8))
+    # a gang of one is the list executor: the elision is sound there
+    for seed in range(4):
+        st, shares = tg.tg_emulate_gang([g.handle], 8, 1, 64, seed, tg.TG_SCHED_COLUMN, elide=True)
+        assert st == tg.TG_OK and shares == 8 * 24
